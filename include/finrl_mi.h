@@ -1,0 +1,185 @@
+/*
+ * finrl_mi.h -- C ABI of the MI355X (gfx950) massively parallel trading-environment rollout.
+ *
+ * The library implements the simulation ("producer") phase of the training loop the paper
+ * describes in Section 3.2: N vectorised stock-trading sub-environments (Section 4.2) whose
+ * actions come from a K-actor ensemble (Section 5.2.1), with the samples written as
+ * T x N x D device tensors (Section 4.3).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device buffers owned by the caller (for example the data_ptr of a
+ *     torch tensor on the current GPU).  Pointers named h_* are host memory.  The library never
+ *     allocates device memory: the caller sizes workspaces with the *_workspace_bytes queries
+ *     and keeps every buffer alive for as long as a handle that refers to it.
+ *   - Work is enqueued on the stream given at creation (environments) or per call (ensemble_act)
+ *     and the call returns without synchronising the host, except where stated.
+ *   - External layouts are row-major with the last index fastest: actions [N][D], states
+ *     [N][S] with S = (I+2)*D+1, trajectories [T][N][...] (Section 4.3).
+ *   - Errors: arguments are validated before anything is enqueued; an invalid argument returns
+ *     FM_ERR_INVALID, a call that does not fit the environment's current day returns
+ *     FM_ERR_STATE, a launch or device failure returns FM_ERR_DEVICE, and a size the kernels do
+ *     not support returns FM_ERR_UNSUPPORTED.  Nothing aborts and nothing throws across the ABI;
+ *     fm_last_error() describes the most recent failure on the calling thread.
+ */
+#ifndef FINRL_MI_H
+#define FINRL_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fm_status {
+  FM_OK = 0,
+  FM_ERR_INVALID = 1,
+  FM_ERR_STATE = 2,
+  FM_ERR_DEVICE = 3,
+  FM_ERR_UNSUPPORTED = 4
+} fm_status;
+
+typedef enum fm_dtype { FM_F32 = 0, FM_BF16 = 1 } fm_dtype;
+
+typedef enum fm_path {
+  FM_PATH_PLAIN = 0,  /* per-step launches: ensemble MLP, then noise + trade + reward + state */
+  FM_PATH_FUSED = 1   /* one persistent launch that loops over the steps (bfloat16 ensembles) */
+} fm_path;
+
+/* Environment parameters.  The MDP is that of Section 3.1: state [b, p, h, f], an action is a
+ * change of holdings, reward v_{t+1} - v_t with v_t = b_t + p_t^T h_t. */
+typedef struct fm_env_config {
+  int32_t n_envs;          /* N sub-environments, >= 1 */
+  int32_t n_stocks;        /* D assets, 1..128 */
+  int32_t n_ind;           /* I indicators per asset, 0..16 */
+  int32_t n_days;          /* T steps; the market arrays hold T+1 days */
+  int32_t hmax;            /* shares per unit action, 1..2^20 */
+  double init_cash;        /* b_0 >= 0 */
+  double cost_rate;        /* proportional transaction cost c in [0, 1) */
+  double reward_scale;     /* r_t = (v_{t+1} - v_t) * reward_scale */
+  float cash_obs_scale;    /* state entries: fl32(b * cash_obs_scale), p * price_obs_scale, */
+  float price_obs_scale;   /*                fl32(h) * hold_obs_scale (powers of two keep    */
+  float hold_obs_scale;    /*                these exact)                                    */
+} fm_env_config;
+
+typedef struct fm_env fm_env;           /* opaque host handle */
+typedef struct fm_ensemble fm_ensemble; /* opaque host handle */
+
+/* Rollout options.  Trajectory pointers may each be NULL (not stored). */
+typedef struct fm_rollout_opts {
+  const float* d_actions;  /* [n_steps][N][D] float32: driven mode (the caller's actions are
+                              executed); NULL: the ensemble acts on every state */
+  float sigma;             /* Gaussian exploration noise added after averaging, >= 0 */
+  uint64_t noise_key;      /* Philox4x64-10 key word; noise for env n, day t, stock d uses
+                              counter (env_offset + n, t, d / 4, 0) */
+  int64_t env_offset;      /* global index of env 0 (for sharding across devices) */
+  int32_t path;            /* fm_path */
+  float* d_obs_traj;       /* [n_steps][N][S] float32: state s_{t+1} after each step */
+  float* d_act_traj;       /* [n_steps][N][D] float32: the action executed at each step */
+  double* d_rew_traj;      /* [n_steps][N] float64 rewards */
+  int32_t* d_qty_traj;     /* [n_steps][N][D] int32 executed shares (negative = sold) */
+} fm_rollout_opts;
+
+/* ---------------------------------------------------------------------------------------------
+ * Environment (Section 4.2: a VecEnv of N SubEnvs, each with its own balance and holdings, on a
+ * shared market path of prices and indicators).
+ * ------------------------------------------------------------------------------------------- */
+
+/* Device bytes the environment needs for its state (cash, total asset, cumulative reward as
+ * float64 [N]; holdings int32 [D][N]; an action staging buffer float32 [N][D]).  Returns 0 for
+ * an invalid configuration. */
+size_t env_workspace_bytes(const fm_env_config* cfg);
+
+/* Create an environment over the market arrays d_close [T+1][D] and d_ind [T+1][I][D]
+ * (float32, indicator-major within a day).  d_workspace holds at least env_workspace_bytes(cfg)
+ * bytes, 256-byte aligned.  The market arrays and the workspace must outlive the handle.
+ * Nothing is enqueued: the state is undefined until env_reset or env_write_state. */
+fm_status env_create(const fm_env_config* cfg, const float* d_close, const float* d_ind,
+                     void* d_workspace, size_t workspace_bytes, hipStream_t stream, fm_env** out);
+
+/* reset (Section 4.2): every sub-environment returns to day 0 with the initial cash and no
+ * holdings.  Writes s_0 to d_obs [N][S] if it is not NULL. */
+fm_status env_reset(fm_env* env, float* d_obs);
+
+/* step and reward (Section 4.2) for one day: converts d_act [N][D] into integer orders
+ * q = trunc(fl32(clamp(a, -1, 1) * hmax)) (NaN counts as 0), executes every sell (capped at the
+ * holding) in ascending stock order and then every buy (the largest affordable k <= q) in
+ * ascending stock order at the day-t close with proportional cost, advances to day t+1, and
+ * writes r_t to d_reward [N], s_{t+1} to d_obs [N][S] and the executed shares to d_exec_qty
+ * [N][D] (each optional except d_reward).  *h_done is set to 1 when day T is reached.
+ * Returns FM_ERR_STATE if the environment is already at day T. */
+fm_status env_step(fm_env* env, const float* d_act, float* d_obs, double* d_reward,
+                   int32_t* d_exec_qty, int32_t* h_done);
+
+/* A rollout of n_steps steps from the current day (Section 4.3: samples stored as T x N x D
+ * tensors on the device).  ens may be NULL only in driven mode.  FM_PATH_FUSED needs a bfloat16
+ * ensemble or driven mode.  Returns FM_ERR_STATE if the current day + n_steps exceeds T. */
+fm_status env_rollout(fm_env* env, const fm_ensemble* ens, int32_t n_steps,
+                      const fm_rollout_opts* opts);
+
+/* Copy the state out to caller buffers (any may be NULL): cash, total asset v_t and cumulative
+ * reward float64 [N], holdings int32 [N][D]; *h_day gets the current day. */
+fm_status env_read_state(const fm_env* env, double* d_cash, int32_t* d_hold, double* d_asset,
+                         double* d_cumrew, int32_t* h_day);
+
+/* Overwrite the state (checkpoint resume).  All four buffers are required; 0 <= day <= T. */
+fm_status env_write_state(fm_env* env, const double* d_cash, const int32_t* d_hold,
+                          const double* d_asset, const double* d_cumrew, int32_t day);
+
+/* The environment's current day (host-side bookkeeping; -1 for NULL). */
+int32_t env_day(const fm_env* env);
+void env_destroy(fm_env* env);
+
+/* ---------------------------------------------------------------------------------------------
+ * Ensemble (Section 5.2.1: the stock ensemble acts on the weighted average of its agents'
+ * actions).  Each actor k is an MLP mu_k(s) = tanh(tanh(tanh(s W1 + b1) W2 + b2) W3 + b3) with
+ * W1 [S][H], W2 [H][H], W3 [H][A]; the ensemble action is
+ *   a = clip(sum_k w_k mu_k(s) + sigma * eps, -1, 1),
+ * eps standard normal from Philox4x64-10 (Salmon et al., SC'11) and the Box-Muller transform.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Device bytes for an ensemble that acts on at most max_batch states per call. */
+size_t ensemble_workspace_bytes(int32_t n_actors, int32_t in_dim, int32_t hidden, int32_t out_dim,
+                                int32_t dtype, int32_t max_batch);
+
+/* Pack the float32 master weights d_w (for k in 0..K-1: W1[S][H], b1[H], W2[H][H], b2[H],
+ * W3[H][A], b3[A]) into d_workspace in the device layout of dtype (bfloat16 rounds the weight
+ * matrices to nearest-even and keeps the biases float32).  h_mix [K] gives w_k (NULL: 1/K).
+ * Limits: 1 <= K <= 8, 1 <= S <= 1024, H a multiple of 32 in 32..512, 1 <= A <= 128.  The
+ * packing runs on stream and the call waits for it, so d_w may be released on return. */
+fm_status ensemble_create(int32_t n_actors, int32_t in_dim, int32_t hidden, int32_t out_dim,
+                          int32_t dtype, const float* d_w, const float* h_mix, int32_t max_batch,
+                          void* d_workspace, size_t workspace_bytes, hipStream_t stream,
+                          fm_ensemble** out);
+
+/* Act on n states d_obs [n][S]: writes the ensemble mean to d_mean [n][A] (optional) and the
+ * noisy, clipped action to d_act [n][A].  State row i is environment env_offset + i at day t for
+ * the noise counter.  n <= max_batch.  Concurrent calls on one ensemble must use one stream. */
+fm_status ensemble_act(const fm_ensemble* ens, const float* d_obs, int32_t n, float sigma,
+                       uint64_t noise_key, int32_t t, int64_t env_offset, float* d_mean,
+                       float* d_act, hipStream_t stream);
+
+void ensemble_destroy(fm_ensemble* ens);
+
+/* ---------------------------------------------------------------------------------------------
+ * Diagnostics
+ * ------------------------------------------------------------------------------------------- */
+
+/* Message for the last non-OK status returned on the calling thread ("" if none). */
+const char* fm_last_error(void);
+
+/* The Gaussian exploration noise exactly as the ensemble draws it: eps [n][D] float32 for
+ * environments env_offset .. env_offset+n-1 at day t, and optionally the raw Philox4x64-10
+ * blocks d_words [n][ceil(D/4)][4] (uint64).  Exposes the generator for checking. */
+fm_status fm_noise(uint64_t noise_key, int64_t env_offset, int32_t n, int32_t t, int32_t n_stocks,
+                   uint64_t* d_words, float* d_eps, hipStream_t stream);
+
+/* Library version string. */
+const char* fm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FINRL_MI_H */

@@ -71,12 +71,16 @@ def ensemble_mean(actors, obs, mix=None) -> np.ndarray:
 
 
 def ensemble_act(actors, obs, t: int, env_offset: int, sigma: float, noise_key: int, mix=None,
-                 return_mean: bool = False):
-    """a = fl32(clip(a_bar + sigma*eps(n, t, d), -1, 1)) for envs env_offset .. env_offset+n-1."""
+                 return_mean: bool = False, env_ids=None):
+    """a = fl32(clip(a_bar + sigma*eps(n, t, d), -1, 1)).
+
+    Row i of obs is environment env_offset + i, or env_ids[i] when env_ids is given.
+    """
     mean = ensemble_mean(actors, obs, mix)
     sig = np.float64(np.float32(sigma))
     if sig != 0.0:
-        eps = noise(noise_key, np.arange(env_offset, env_offset + mean.shape[0]), t, mean.shape[1])
+        ids = np.arange(env_offset, env_offset + mean.shape[0]) if env_ids is None else np.asarray(env_ids)
+        eps = noise(noise_key, ids, t, mean.shape[1])
         pre = mean + sig * eps
     else:
         pre = mean

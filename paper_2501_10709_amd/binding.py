@@ -1,0 +1,233 @@
+"""Thin ctypes binding of libfinrl_mi.so (include/finrl_mi.h).
+
+The functions below carry the C entry points' names and only marshal arguments: torch
+tensors become device pointers, the current torch stream becomes the hipStream_t, and a
+non-OK status becomes an exception carrying fm_last_error().  All computation happens in the
+library's HIP kernels; if the library is not built, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfinrl_mi.so")
+
+FM_OK, FM_ERR_INVALID, FM_ERR_STATE, FM_ERR_DEVICE, FM_ERR_UNSUPPORTED = range(5)
+FM_F32, FM_BF16 = 0, 1
+FM_PATH_PLAIN, FM_PATH_FUSED = 0, 1
+
+# Symbols declared in include/finrl_mi.h.
+EXPORTS = (
+    "env_workspace_bytes", "env_create", "env_reset", "env_step", "env_rollout", "env_read_state",
+    "env_write_state", "env_day", "env_destroy", "ensemble_workspace_bytes", "ensemble_create",
+    "ensemble_act", "ensemble_destroy", "fm_last_error", "fm_noise", "fm_version",
+)
+
+
+class FmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"finrl_mi status {status}: {msg}")
+        self.status = status
+
+
+class FmEnvConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_envs", ctypes.c_int32), ("n_stocks", ctypes.c_int32), ("n_ind", ctypes.c_int32),
+        ("n_days", ctypes.c_int32), ("hmax", ctypes.c_int32),
+        ("init_cash", ctypes.c_double), ("cost_rate", ctypes.c_double), ("reward_scale", ctypes.c_double),
+        ("cash_obs_scale", ctypes.c_float), ("price_obs_scale", ctypes.c_float),
+        ("hold_obs_scale", ctypes.c_float),
+    ]
+
+
+class FmRolloutOpts(ctypes.Structure):
+    _fields_ = [
+        ("d_actions", ctypes.c_void_p), ("sigma", ctypes.c_float), ("noise_key", ctypes.c_uint64),
+        ("env_offset", ctypes.c_int64), ("path", ctypes.c_int32),
+        ("d_obs_traj", ctypes.c_void_p), ("d_act_traj", ctypes.c_void_p),
+        ("d_rew_traj", ctypes.c_void_p), ("d_qty_traj", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+    sig = {
+        "env_workspace_bytes": (SZ, [ctypes.POINTER(FmEnvConfig)]),
+        "env_create": (I32, [ctypes.POINTER(FmEnvConfig), P, P, P, SZ, P, ctypes.POINTER(P)]),
+        "env_reset": (I32, [P, P]),
+        "env_step": (I32, [P, P, P, P, P, ctypes.POINTER(I32)]),
+        "env_rollout": (I32, [P, P, I32, ctypes.POINTER(FmRolloutOpts)]),
+        "env_read_state": (I32, [P, P, P, P, P, ctypes.POINTER(I32)]),
+        "env_write_state": (I32, [P, P, P, P, P, I32]),
+        "env_day": (I32, [P]),
+        "env_destroy": (None, [P]),
+        "ensemble_workspace_bytes": (SZ, [I32, I32, I32, I32, I32, I32]),
+        "ensemble_create": (I32, [I32, I32, I32, I32, I32, P, P, I32, P, SZ, P, ctypes.POINTER(P)]),
+        "ensemble_act": (I32, [P, P, I32, ctypes.c_float, U64, I32, I64, P, P, P]),
+        "ensemble_destroy": (None, [P]),
+        "fm_last_error": (ctypes.c_char_p, []),
+        "fm_noise": (I32, [U64, I64, I32, I32, I32, P, P, P]),
+        "fm_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != FM_OK:
+        raise FmError(status, load().fm_last_error().decode())
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_config(cfg) -> FmEnvConfig:
+    """FmEnvConfig from any object with the fields of workload.EnvConfig."""
+    return FmEnvConfig(cfg.n_envs, cfg.n_stocks, cfg.n_ind, cfg.n_days, cfg.hmax, cfg.init_cash,
+                       cfg.cost_rate, cfg.reward_scale, cfg.cash_obs_scale, cfg.price_obs_scale,
+                       cfg.hold_obs_scale)
+
+
+# --- entry points, same names as the C ABI ---------------------------------------------------
+
+def env_workspace_bytes(cfg) -> int:
+    c = cfg if isinstance(cfg, FmEnvConfig) else make_config(cfg)
+    return int(load().env_workspace_bytes(ctypes.byref(c)))
+
+
+def env_create(cfg, d_close, d_ind, d_workspace, stream=None):
+    import torch
+    c = cfg if isinstance(cfg, FmEnvConfig) else make_config(cfg)
+    h = ctypes.c_void_p()
+    _check(load().env_create(ctypes.byref(c), _ptr(d_close, torch.float32, name="close"),
+                             _ptr(d_ind, torch.float32, name="ind"), _ptr(d_workspace, name="workspace"),
+                             d_workspace.numel() * d_workspace.element_size(), _stream(stream),
+                             ctypes.byref(h)))
+    return h
+
+
+def env_reset(env, d_obs=None):
+    import torch
+    _check(load().env_reset(env, _ptr(d_obs, torch.float32, name="obs")))
+
+
+def env_step(env, d_act, d_reward, d_obs=None, d_exec_qty=None) -> bool:
+    import torch
+    done = ctypes.c_int32(0)
+    _check(load().env_step(env, _ptr(d_act, torch.float32, name="act"), _ptr(d_obs, torch.float32, name="obs"),
+                           _ptr(d_reward, torch.float64, name="reward"),
+                           _ptr(d_exec_qty, torch.int32, name="exec_qty"), ctypes.byref(done)))
+    return bool(done.value)
+
+
+def env_rollout(env, ens, n_steps, d_actions=None, sigma=0.0, noise_key=0, env_offset=0, path=FM_PATH_PLAIN,
+                d_obs_traj=None, d_act_traj=None, d_rew_traj=None, d_qty_traj=None):
+    import torch
+    o = FmRolloutOpts(_ptr(d_actions, torch.float32, name="actions"), float(sigma), int(noise_key),
+                      int(env_offset), int(path), _ptr(d_obs_traj, torch.float32, name="obs_traj"),
+                      _ptr(d_act_traj, torch.float32, name="act_traj"),
+                      _ptr(d_rew_traj, torch.float64, name="rew_traj"),
+                      _ptr(d_qty_traj, torch.int32, name="qty_traj"))
+    _check(load().env_rollout(env, ens, int(n_steps), ctypes.byref(o)))
+
+
+def env_read_state(env, d_cash=None, d_hold=None, d_asset=None, d_cumrew=None) -> int:
+    import torch
+    day = ctypes.c_int32(0)
+    _check(load().env_read_state(env, _ptr(d_cash, torch.float64, name="cash"), _ptr(d_hold, torch.int32, name="hold"),
+                                 _ptr(d_asset, torch.float64, name="asset"),
+                                 _ptr(d_cumrew, torch.float64, name="cumrew"), ctypes.byref(day)))
+    return int(day.value)
+
+
+def env_write_state(env, d_cash, d_hold, d_asset, d_cumrew, day: int):
+    import torch
+    _check(load().env_write_state(env, _ptr(d_cash, torch.float64, name="cash"), _ptr(d_hold, torch.int32, name="hold"),
+                                  _ptr(d_asset, torch.float64, name="asset"),
+                                  _ptr(d_cumrew, torch.float64, name="cumrew"), int(day)))
+
+
+def env_day(env) -> int:
+    return int(load().env_day(env))
+
+
+def env_destroy(env):
+    load().env_destroy(env)
+
+
+def ensemble_workspace_bytes(n_actors, in_dim, hidden, out_dim, dtype, max_batch) -> int:
+    return int(load().ensemble_workspace_bytes(n_actors, in_dim, hidden, out_dim, dtype, max_batch))
+
+
+def ensemble_create(n_actors, in_dim, hidden, out_dim, dtype, d_w, mix, max_batch, d_workspace, stream=None):
+    import torch
+    h = ctypes.c_void_p()
+    mix_arr = None
+    if mix is not None:
+        mix_arr = (ctypes.c_float * n_actors)(*[float(x) for x in mix])
+    _check(load().ensemble_create(n_actors, in_dim, hidden, out_dim, dtype, _ptr(d_w, torch.float32, name="weights"),
+                                  mix_arr, max_batch, _ptr(d_workspace, name="workspace"),
+                                  d_workspace.numel() * d_workspace.element_size(), _stream(stream),
+                                  ctypes.byref(h)))
+    return h
+
+
+def ensemble_act(ens, d_obs, n, sigma, noise_key, t, env_offset, d_act, d_mean=None, stream=None):
+    import torch
+    _check(load().ensemble_act(ens, _ptr(d_obs, torch.float32, name="obs"), int(n), float(sigma), int(noise_key),
+                               int(t), int(env_offset), _ptr(d_mean, torch.float32, name="mean"),
+                               _ptr(d_act, torch.float32, name="act"), _stream(stream)))
+
+
+def ensemble_destroy(ens):
+    load().ensemble_destroy(ens)
+
+
+def fm_noise(noise_key, env_offset, n, t, n_stocks, d_eps, d_words=None, stream=None):
+    import torch
+    _check(load().fm_noise(int(noise_key), int(env_offset), int(n), int(t), int(n_stocks),
+                           _ptr(d_words, torch.int64, name="words"), _ptr(d_eps, torch.float32, name="eps"),
+                           _stream(stream)))
+
+
+def fm_last_error() -> str:
+    return load().fm_last_error().decode()
+
+
+def fm_version() -> str:
+    return load().fm_version().decode()

@@ -1,0 +1,451 @@
+// The C ABI (include/finrl_mi.h): argument validation, workspace layout, handles and launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/finrl_mi.h"
+#include "fused.h"
+#include "launch.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fm_status fail(fm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+fm_status device_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return FM_OK;
+  return fail(FM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
+
+// Environments per 64-lane workgroup of the environment kernels: small tiles spread the serial
+// trading chains over more compute units; the tile is capped by the kernels' LDS budget.
+int env_tile(int N) {
+  if (N >= 16384) return 32;
+  if (N >= 4096) return 16;
+  return 8;
+}
+
+struct EnvLayout {
+  size_t cash, asset, cumrew, hold, act, obs, total;
+};
+
+EnvLayout env_layout(const fm_env_config& c) {
+  const int S = (c.n_ind + 2) * c.n_stocks + 1;
+  EnvLayout L{};
+  size_t off = 0;
+  L.cash = off;
+  off = align_up(off + sizeof(double) * c.n_envs);
+  L.asset = off;
+  off = align_up(off + sizeof(double) * c.n_envs);
+  L.cumrew = off;
+  off = align_up(off + sizeof(double) * c.n_envs);
+  L.hold = off;
+  off = align_up(off + sizeof(int32_t) * static_cast<size_t>(c.n_stocks) * c.n_envs);
+  L.act = off;
+  off = align_up(off + sizeof(float) * static_cast<size_t>(c.n_stocks) * c.n_envs);
+  L.obs = off;
+  off = align_up(off + sizeof(float) * static_cast<size_t>(S) * c.n_envs);
+  L.total = off;
+  return L;
+}
+
+std::string validate_config(const fm_env_config* c) {
+  if (!c) return "config is NULL";
+  if (c->n_envs < 1 || c->n_envs > (1 << 24)) return "n_envs must be in 1..2^24";
+  if (c->n_stocks < 1 || c->n_stocks > 128) return "n_stocks must be in 1..128";
+  if (c->n_ind < 0 || c->n_ind > 16) return "n_ind must be in 0..16";
+  if (c->n_days < 1 || c->n_days > (1 << 20)) return "n_days must be in 1..2^20";
+  if (c->hmax < 1 || c->hmax > (1 << 20)) return "hmax must be in 1..2^20";
+  if (!(c->init_cash >= 0.0) || !std::isfinite(c->init_cash)) return "init_cash must be finite and >= 0";
+  if (!(c->cost_rate >= 0.0 && c->cost_rate < 1.0)) return "cost_rate must be in [0, 1)";
+  if (!std::isfinite(c->reward_scale)) return "reward_scale must be finite";
+  if (!std::isfinite(c->cash_obs_scale) || !std::isfinite(c->price_obs_scale) ||
+      !std::isfinite(c->hold_obs_scale))
+    return "state scales must be finite";
+  const size_t S = static_cast<size_t>(c->n_ind + 2) * c->n_stocks + 1;
+  if (S * static_cast<size_t>(c->n_envs) * c->n_days > (static_cast<size_t>(1) << 46))
+    return "trajectory too large";
+  return "";
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct fm_env {
+  fm_env_config cfg;
+  fm::EnvConst C;
+  fm::EnvState st;
+  float* act_stage;
+  float* obs_stage;
+  hipStream_t stream;
+  int device;
+  int day;
+  int tile;
+};
+
+struct fm_ensemble {
+  int K, S, H, A, dtype, max_batch, device;
+  fm::EnsDev E;
+  float* mu;  // [K][max_batch][A]
+};
+
+namespace {
+
+struct EnsLayout {
+  int S_pad, A_pad;
+  size_t w1, w2, w3, b1, b2, b3, actor, mix, mu, total;
+};
+
+EnsLayout ens_layout(int K, int S, int H, int A, int dtype, int max_batch) {
+  EnsLayout L{};
+  const int kg = dtype == FM_F32 ? 16 : 32;
+  const size_t es = dtype == FM_F32 ? 4 : 2;
+  L.S_pad = fm::round_up(S, kg);
+  L.A_pad = fm::round_up(A, 16);
+  size_t off = 0;
+  L.w1 = off;
+  off = align_up(off + es * L.S_pad * H);
+  L.w2 = off;
+  off = align_up(off + es * static_cast<size_t>(H) * H);
+  L.w3 = off;
+  off = align_up(off + es * static_cast<size_t>(H) * L.A_pad);
+  L.b1 = off;
+  off = align_up(off + 4 * H);
+  L.b2 = off;
+  off = align_up(off + 4 * H);
+  L.b3 = off;
+  off = align_up(off + 4 * L.A_pad);
+  L.actor = off;
+  L.mix = L.actor * K;
+  L.mu = align_up(L.mix + 4 * 8);
+  L.total = align_up(L.mu + sizeof(float) * static_cast<size_t>(K) * max_batch * A);
+  return L;
+}
+
+std::string validate_ensemble(int K, int S, int H, int A, int dtype, int max_batch) {
+  if (K < 1 || K > 8) return "n_actors must be in 1..8";
+  if (S < 1 || S > 1024) return "in_dim must be in 1..1024";
+  if (H < 32 || H > 512 || H % 32 != 0) return "hidden must be a multiple of 32 in 32..512";
+  if (A < 1 || A > 128) return "out_dim must be in 1..128";
+  if (dtype != FM_F32 && dtype != FM_BF16) return "dtype must be FM_F32 or FM_BF16";
+  if (max_batch < 1 || max_batch > (1 << 24)) return "max_batch must be in 1..2^24";
+  return "";
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fm_last_error(void) { return g_last_error.c_str(); }
+
+const char* fm_version(void) { return "finrl_mi 0.1 gfx950"; }
+
+size_t env_workspace_bytes(const fm_env_config* cfg) {
+  if (!validate_config(cfg).empty()) return 0;
+  return env_layout(*cfg).total;
+}
+
+fm_status env_create(const fm_env_config* cfg, const float* d_close, const float* d_ind,
+                     void* d_workspace, size_t workspace_bytes, hipStream_t stream,
+                     fm_env** out) {
+  if (!out) return fail(FM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  const std::string why = validate_config(cfg);
+  if (!why.empty()) return fail(FM_ERR_INVALID, why);
+  if (!d_close) return fail(FM_ERR_INVALID, "d_close is NULL");
+  if (!d_ind && cfg->n_ind > 0) return fail(FM_ERR_INVALID, "d_ind is NULL");
+  if (!d_workspace) return fail(FM_ERR_INVALID, "d_workspace is NULL");
+  if (!aligned(d_workspace)) return fail(FM_ERR_INVALID, "d_workspace must be 256-byte aligned");
+  const EnvLayout L = env_layout(*cfg);
+  if (workspace_bytes < L.total) return fail(FM_ERR_INVALID, "workspace too small");
+  fm_env* e = new (std::nothrow) fm_env();
+  if (!e) return fail(FM_ERR_DEVICE, "host allocation failed");
+  e->cfg = *cfg;
+  fm::EnvConst& C = e->C;
+  C.N = cfg->n_envs;
+  C.D = cfg->n_stocks;
+  C.I = cfg->n_ind;
+  C.T = cfg->n_days;
+  C.S = (cfg->n_ind + 2) * cfg->n_stocks + 1;
+  C.hmax = cfg->hmax;
+  C.hmax_f = static_cast<float>(cfg->hmax);
+  C.cash_scale = cfg->cash_obs_scale;
+  C.price_scale = cfg->price_obs_scale;
+  C.hold_scale = cfg->hold_obs_scale;
+  C.init_cash = cfg->init_cash;
+  C.one_m = 1.0 - cfg->cost_rate;
+  C.one_p = 1.0 + cfg->cost_rate;
+  C.reward_scale = cfg->reward_scale;
+  C.close = d_close;
+  C.ind = d_ind;
+  unsigned char* base = static_cast<unsigned char*>(d_workspace);
+  e->st.cash = reinterpret_cast<double*>(base + L.cash);
+  e->st.asset = reinterpret_cast<double*>(base + L.asset);
+  e->st.cumrew = reinterpret_cast<double*>(base + L.cumrew);
+  e->st.hold = reinterpret_cast<int*>(base + L.hold);
+  e->act_stage = reinterpret_cast<float*>(base + L.act);
+  e->obs_stage = reinterpret_cast<float*>(base + L.obs);
+  e->stream = stream;
+  if (hipGetDevice(&e->device) != hipSuccess) e->device = 0;
+  e->day = 0;
+  e->tile = env_tile(C.N);
+  *out = e;
+  return FM_OK;
+}
+
+fm_status env_reset(fm_env* env, float* d_obs) {
+  if (!env) return fail(FM_ERR_INVALID, "env is NULL");
+  DeviceGuard g(env->device);
+  fm_status s = device_status(fm::launch_env_reset(env->C, env->st, d_obs, env->tile, env->stream),
+                              "env_reset");
+  if (s == FM_OK) env->day = 0;
+  return s;
+}
+
+fm_status env_step(fm_env* env, const float* d_act, float* d_obs, double* d_reward,
+                   int32_t* d_exec_qty, int32_t* h_done) {
+  if (!env) return fail(FM_ERR_INVALID, "env is NULL");
+  if (!d_act) return fail(FM_ERR_INVALID, "d_act is NULL");
+  if (!d_reward) return fail(FM_ERR_INVALID, "d_reward is NULL");
+  if (env->day >= env->C.T) return fail(FM_ERR_STATE, "environment is at the last day; reset first");
+  DeviceGuard g(env->device);
+  fm_status s = device_status(fm::launch_env_given(env->C, env->st, env->day, 1, d_act, d_obs,
+                                                   d_reward, d_exec_qty, env->tile, env->stream),
+                              "env_step");
+  if (s != FM_OK) return s;
+  env->day += 1;
+  if (h_done) *h_done = env->day == env->C.T ? 1 : 0;
+  return FM_OK;
+}
+
+fm_status env_rollout(fm_env* env, const fm_ensemble* ens, int32_t n_steps,
+                      const fm_rollout_opts* opts) {
+  if (!env) return fail(FM_ERR_INVALID, "env is NULL");
+  if (!opts) return fail(FM_ERR_INVALID, "opts is NULL");
+  if (n_steps < 0) return fail(FM_ERR_INVALID, "n_steps must be >= 0");
+  if (opts->path != FM_PATH_PLAIN && opts->path != FM_PATH_FUSED)
+    return fail(FM_ERR_INVALID, "path must be FM_PATH_PLAIN or FM_PATH_FUSED");
+  if (env->day + n_steps > env->C.T)
+    return fail(FM_ERR_STATE, "rollout would run past the last day");
+  if (n_steps == 0) return FM_OK;
+  const fm::EnvConst& C = env->C;
+  const size_t N = C.N, D = C.D, S = C.S;
+  DeviceGuard g(env->device);
+  hipStream_t st = env->stream;
+  if (opts->d_actions) {  // driven mode: one launch over all steps
+    fm_status s = device_status(
+        fm::launch_env_given(C, env->st, env->day, n_steps, opts->d_actions, opts->d_obs_traj,
+                             opts->d_rew_traj, opts->d_qty_traj, env->tile, st),
+        "env_rollout (driven)");
+    if (s != FM_OK) return s;
+    if (opts->d_act_traj) {
+      s = device_status(hipMemcpyAsync(opts->d_act_traj, opts->d_actions,
+                                       sizeof(float) * N * D * n_steps, hipMemcpyDeviceToDevice, st),
+                        "env_rollout (copy actions)");
+      if (s != FM_OK) return s;
+    }
+    env->day += n_steps;
+    return FM_OK;
+  }
+  if (!ens) return fail(FM_ERR_INVALID, "closed-loop rollout needs an ensemble");
+  if (ens->S != C.S || ens->A != C.D)
+    return fail(FM_ERR_INVALID, "ensemble in_dim/out_dim do not match the environment state/action");
+  if (!(opts->sigma >= 0.0f) || !std::isfinite(opts->sigma)) return fail(FM_ERR_INVALID, "sigma must be finite and >= 0");
+  if (ens->device != env->device) return fail(FM_ERR_INVALID, "ensemble and environment are on different devices");
+  if (opts->path == FM_PATH_FUSED) {
+    if (ens->dtype != FM_BF16) return fail(FM_ERR_UNSUPPORTED, "the fused path runs bfloat16 ensembles");
+    std::string why;
+    const hipError_t e = fm::launch_fused_rollout(C, env->st, ens->E, env->day, n_steps, opts->sigma,
+                                                  opts->noise_key, opts->env_offset, opts->d_obs_traj,
+                                                  opts->d_act_traj, opts->d_rew_traj, opts->d_qty_traj,
+                                                  st, &why);
+    if (!why.empty()) return fail(FM_ERR_UNSUPPORTED, why);
+    fm_status s = device_status(e, "env_rollout (fused)");
+    if (s != FM_OK) return s;
+    env->day += n_steps;
+    return FM_OK;
+  }
+  if (static_cast<size_t>(ens->max_batch) < N)
+    return fail(FM_ERR_INVALID, "ensemble max_batch is smaller than n_envs");
+  // Plain path: the current state, then per step the ensemble MLP and the env step.
+  fm_status s = device_status(fm::launch_env_observe(C, env->st, env->day, env->obs_stage, env->tile, st),
+                              "env_rollout (observe)");
+  if (s != FM_OK) return s;
+  const float* obs_in = env->obs_stage;
+  for (int i = 0; i < n_steps; ++i) {
+    const int t = env->day + i;
+    s = device_status(fm::launch_mlp(ens->dtype, ens->E, obs_in, C.N, ens->mu, st), "env_rollout (mlp)");
+    if (s != FM_OK) return s;
+    float* obs_out = opts->d_obs_traj ? opts->d_obs_traj + static_cast<size_t>(i) * N * S : env->obs_stage;
+    float* act_out = opts->d_act_traj ? opts->d_act_traj + static_cast<size_t>(i) * N * D : nullptr;
+    double* rew = opts->d_rew_traj ? opts->d_rew_traj + static_cast<size_t>(i) * N : nullptr;
+    int* qty = opts->d_qty_traj ? opts->d_qty_traj + static_cast<size_t>(i) * N * D : nullptr;
+    s = device_status(fm::launch_env_ensemble_step(C, env->st, t, ens->mu, ens->E.mix, ens->K, opts->sigma,
+                                                   opts->noise_key, opts->env_offset, obs_out, act_out,
+                                                   rew, qty, env->tile, st),
+                      "env_rollout (step)");
+    if (s != FM_OK) return s;
+    obs_in = obs_out;
+  }
+  env->day += n_steps;
+  return FM_OK;
+}
+
+fm_status env_read_state(const fm_env* env, double* d_cash, int32_t* d_hold, double* d_asset,
+                         double* d_cumrew, int32_t* h_day) {
+  if (!env) return fail(FM_ERR_INVALID, "env is NULL");
+  if (h_day) *h_day = env->day;
+  if (!d_cash && !d_hold && !d_asset && !d_cumrew) return FM_OK;
+  DeviceGuard g(env->device);
+  return device_status(fm::launch_read_state(env->C, env->st, d_cash, d_hold, d_asset, d_cumrew, env->stream),
+                       "env_read_state");
+}
+
+fm_status env_write_state(fm_env* env, const double* d_cash, const int32_t* d_hold,
+                          const double* d_asset, const double* d_cumrew, int32_t day) {
+  if (!env) return fail(FM_ERR_INVALID, "env is NULL");
+  if (!d_cash || !d_hold || !d_asset || !d_cumrew) return fail(FM_ERR_INVALID, "all state buffers are required");
+  if (day < 0 || day > env->C.T) return fail(FM_ERR_INVALID, "day must be in 0..T");
+  DeviceGuard g(env->device);
+  fm_status s = device_status(
+      fm::launch_write_state(env->C, env->st, d_cash, d_hold, d_asset, d_cumrew, env->stream), "env_write_state");
+  if (s == FM_OK) env->day = day;
+  return s;
+}
+
+int32_t env_day(const fm_env* env) { return env ? env->day : -1; }
+
+void env_destroy(fm_env* env) { delete env; }
+
+size_t ensemble_workspace_bytes(int32_t n_actors, int32_t in_dim, int32_t hidden, int32_t out_dim,
+                                int32_t dtype, int32_t max_batch) {
+  if (!validate_ensemble(n_actors, in_dim, hidden, out_dim, dtype, max_batch).empty()) return 0;
+  return ens_layout(n_actors, in_dim, hidden, out_dim, dtype, max_batch).total;
+}
+
+fm_status ensemble_create(int32_t K, int32_t S, int32_t H, int32_t A, int32_t dtype, const float* d_w,
+                          const float* h_mix, int32_t max_batch, void* d_workspace, size_t workspace_bytes,
+                          hipStream_t stream, fm_ensemble** out) {
+  if (!out) return fail(FM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  const std::string why = validate_ensemble(K, S, H, A, dtype, max_batch);
+  if (!why.empty()) return fail(FM_ERR_INVALID, why);
+  if (!d_w) return fail(FM_ERR_INVALID, "d_w is NULL");
+  if (!d_workspace) return fail(FM_ERR_INVALID, "d_workspace is NULL");
+  if (!aligned(d_workspace)) return fail(FM_ERR_INVALID, "d_workspace must be 256-byte aligned");
+  const EnsLayout L = ens_layout(K, S, H, A, dtype, max_batch);
+  if (workspace_bytes < L.total) return fail(FM_ERR_INVALID, "workspace too small");
+  float mix[8];
+  for (int k = 0; k < K; ++k) {
+    mix[k] = h_mix ? h_mix[k] : 1.0f / static_cast<float>(K);
+    if (!std::isfinite(mix[k])) return fail(FM_ERR_INVALID, "mix weights must be finite");
+  }
+  fm_ensemble* e = new (std::nothrow) fm_ensemble();
+  if (!e) return fail(FM_ERR_DEVICE, "host allocation failed");
+  e->K = K;
+  e->S = S;
+  e->H = H;
+  e->A = A;
+  e->dtype = dtype;
+  e->max_batch = max_batch;
+  if (hipGetDevice(&e->device) != hipSuccess) e->device = 0;
+  unsigned char* base = static_cast<unsigned char*>(d_workspace);
+  fm::EnsDev& E = e->E;
+  E.K = K;
+  E.S = S;
+  E.H = H;
+  E.A = A;
+  E.S_pad = L.S_pad;
+  E.A_pad = L.A_pad;
+  E.base = base;
+  E.actor_stride = L.actor;
+  E.off_w1 = L.w1;
+  E.off_w2 = L.w2;
+  E.off_w3 = L.w3;
+  E.off_b1 = L.b1;
+  E.off_b2 = L.b2;
+  E.off_b3 = L.b3;
+  E.mix = reinterpret_cast<const float*>(base + L.mix);
+  e->mu = reinterpret_cast<float*>(base + L.mu);
+  // Master layout per actor: W1[S][H], b1[H], W2[H][H], b2[H], W3[H][A], b3[A].
+  const size_t per_actor = static_cast<size_t>(S) * H + H + static_cast<size_t>(H) * H + H +
+                           static_cast<size_t>(H) * A + A;
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < K && err == hipSuccess; ++k) {
+    const float* src = d_w + per_actor * k;
+    unsigned char* dst = base + L.actor * k;
+    const float* w1 = src;
+    const float* b1 = w1 + static_cast<size_t>(S) * H;
+    const float* w2 = b1 + H;
+    const float* b2 = w2 + static_cast<size_t>(H) * H;
+    const float* w3 = b2 + H;
+    const float* b3 = w3 + static_cast<size_t>(H) * A;
+    err = fm::launch_pack_matrix(dtype, w1, S, H, L.S_pad, H, dst + L.w1, stream);
+    if (err == hipSuccess) err = fm::launch_pack_matrix(dtype, w2, H, H, H, H, dst + L.w2, stream);
+    if (err == hipSuccess) err = fm::launch_pack_matrix(dtype, w3, H, A, H, L.A_pad, dst + L.w3, stream);
+    if (err == hipSuccess) err = fm::launch_copy_pad(b1, H, H, reinterpret_cast<float*>(dst + L.b1), stream);
+    if (err == hipSuccess) err = fm::launch_copy_pad(b2, H, H, reinterpret_cast<float*>(dst + L.b2), stream);
+    if (err == hipSuccess) err = fm::launch_copy_pad(b3, A, L.A_pad, reinterpret_cast<float*>(dst + L.b3), stream);
+  }
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(base + L.mix, mix, sizeof(float) * K, hipMemcpyHostToDevice, stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);
+  if (err != hipSuccess) {
+    delete e;
+    return device_status(err, "ensemble_create");
+  }
+  *out = e;
+  return FM_OK;
+}
+
+fm_status ensemble_act(const fm_ensemble* ens, const float* d_obs, int32_t n, float sigma, uint64_t noise_key,
+                       int32_t t, int64_t env_offset, float* d_mean, float* d_act, hipStream_t stream) {
+  if (!ens) return fail(FM_ERR_INVALID, "ensemble is NULL");
+  if (!d_obs || !d_act) return fail(FM_ERR_INVALID, "d_obs and d_act are required");
+  if (n < 0 || n > ens->max_batch) return fail(FM_ERR_INVALID, "n must be in 0..max_batch");
+  if (!(sigma >= 0.0f) || !std::isfinite(sigma)) return fail(FM_ERR_INVALID, "sigma must be finite and >= 0");
+  if (t < 0) return fail(FM_ERR_INVALID, "t must be >= 0");
+  if (env_offset < 0) return fail(FM_ERR_INVALID, "env_offset must be >= 0");
+  if (n == 0) return FM_OK;
+  DeviceGuard g(ens->device);
+  fm_status s = device_status(fm::launch_mlp(ens->dtype, ens->E, d_obs, n, ens->mu, stream), "ensemble_act (mlp)");
+  if (s != FM_OK) return s;
+  return device_status(fm::launch_combine(ens->K, n, ens->A, ens->mu, ens->E.mix, sigma, noise_key, t, env_offset,
+                                          d_mean, d_act, stream),
+                       "ensemble_act (combine)");
+}
+
+void ensemble_destroy(fm_ensemble* ens) { delete ens; }
+
+fm_status fm_noise(uint64_t noise_key, int64_t env_offset, int32_t n, int32_t t, int32_t n_stocks,
+                   uint64_t* d_words, float* d_eps, hipStream_t stream) {
+  if (!d_eps) return fail(FM_ERR_INVALID, "d_eps is NULL");
+  if (n < 0 || n_stocks < 1 || n_stocks > 1024 || t < 0 || env_offset < 0)
+    return fail(FM_ERR_INVALID, "bad sizes");
+  if (n == 0) return FM_OK;
+  return device_status(fm::launch_noise(noise_key, env_offset, n, t, n_stocks, d_words, d_eps, stream), "fm_noise");
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+// Device-side building blocks shared by the environment, ensemble and fused rollout kernels:
+// the Philox4x64-10 noise generator, the Box-Muller map, and the per-environment trading chain.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fm {
+
+// ------------------------------------------------------------------------------------------
+// Environment constants as the kernels see them.
+// ------------------------------------------------------------------------------------------
+struct EnvConst {
+  int N, D, I, T, S, hmax;
+  float hmax_f, cash_scale, price_scale, hold_scale;
+  double init_cash, one_m, one_p, reward_scale;
+  const float* close;  // [T+1][D]
+  const float* ind;    // [T+1][I][D]
+};
+
+// Environment state in the workspace, structure-of-arrays with the env index fastest.
+struct EnvState {
+  double* cash;    // [N]
+  double* asset;   // [N]  v_t, the pre-trade value at the current day's close
+  double* cumrew;  // [N]
+  int* hold;       // [D][N]
+};
+
+// ------------------------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 64x64->128 multiplies
+// of counter words 0 and 2, XOR of the high halves with words 1 and 3 and the round key, and a
+// Weyl increment of the key between rounds.
+// ------------------------------------------------------------------------------------------
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;  // golden ratio
+constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;  // sqrt(3) - 1
+
+__device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2,
+                                              uint64_t& c3, uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += kPhiloxW0;
+      k1 += kPhiloxW1;
+    }
+    const uint64_t hi0 = __umul64hi(kPhiloxM0, c0), lo0 = kPhiloxM0 * c0;
+    const uint64_t hi1 = __umul64hi(kPhiloxM1, c2), lo1 = kPhiloxM1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0;
+    const uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+}
+
+// Top 23 bits of the word, centred: ((w >> 41) + 0.5) * 2^-23, exact in float32, in (0, 1).
+__device__ __forceinline__ float uniform_from_word(uint64_t w) {
+  return (static_cast<float>(static_cast<uint32_t>(w >> 41)) + 0.5f) * 0x1p-23f;
+}
+
+// Box-Muller: two standard normals from two uniforms.  cos/sin of 2*pi*u use the pi-scaled
+// forms so that the argument 2u is exact.
+__device__ __forceinline__ void box_muller(float ua, float ub, float& z0, float& z1) {
+  const float r = sqrtf(-2.0f * logf(ua));
+  float s, c;
+  sincospif(2.0f * ub, &s, &c);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+// The noise block for environment n, day t, stock group j (stocks 4j..4j+3): key
+// (noise_key, 0), counter (n, t, j, 0).  Writes the raw words if w != nullptr.
+__device__ __forceinline__ void noise_block(uint64_t key, uint64_t n, uint64_t t, uint64_t j,
+                                            float z[4], uint64_t* w = nullptr) {
+  uint64_t c0 = n, c1 = t, c2 = j, c3 = 0;
+  philox4x64_10(c0, c1, c2, c3, key, 0);
+  if (w) {
+    w[0] = c0;
+    w[1] = c1;
+    w[2] = c2;
+    w[3] = c3;
+  }
+  box_muller(uniform_from_word(c0), uniform_from_word(c1), z[0], z[1]);
+  box_muller(uniform_from_word(c2), uniform_from_word(c3), z[2], z[3]);
+}
+
+// ------------------------------------------------------------------------------------------
+// Orders and the trading chain.  Every float64 operation below rounds once: the library is
+// built with contraction off and the pragma repeats that for these functions.
+// ------------------------------------------------------------------------------------------
+
+// q = trunc(fl32(clamp(a, -1, 1) * hmax)); NaN -> 0.
+__device__ __forceinline__ int order_from_action(float a, float hmax_f) {
+#pragma clang fp contract(off)
+  a = (a == a) ? fminf(fmaxf(a, -1.0f), 1.0f) : 0.0f;
+  const float prod = a * hmax_f;
+  return static_cast<int>(truncf(prod));
+}
+
+// Largest k in [0, q] with (p*k)*one_p <= cash, for the case (p*q)*one_p > cash.  The debit is
+// monotone in k, so a quotient estimate followed by unit steps in both directions is exact
+// whatever the rounding of the division.
+__device__ __noinline__ int partial_fill(double cash, double p, int q, double one_p) {
+#pragma clang fp contract(off)
+  const double c1 = p * one_p;
+  if (!(c1 <= cash)) return 0;
+  double est = floor(cash / c1);
+  est = fmin(est, static_cast<double>(q));
+  int k = static_cast<int>(fmax(est, 0.0));
+  while (k < q && (p * static_cast<double>(k + 1)) * one_p <= cash) ++k;
+  while (k > 0 && (p * static_cast<double>(k)) * one_p > cash) --k;
+  return k;
+}
+
+// One day's trades for one environment held in registers: all sells in ascending stock order,
+// then all buys in ascending stock order, at prices px (float32, day t).  a: this env's
+// actions; x: executed shares (signed).
+template <int DMAX>
+__device__ __forceinline__ void trade(double& cash, int (&h)[DMAX], int (&x)[DMAX],
+                                      const float* a, const float* px, int D, float hmax_f,
+                                      double one_m, double one_p) {
+#pragma clang fp contract(off)
+  int q[DMAX];
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d) q[d] = (d < D) ? order_from_action(a[d], hmax_f) : 0;
+  // Sells: proceeds (p*s)*(1-c); a zero sale adds +0.0, which leaves a non-negative cash as is.
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d) {
+    if (d < D) {
+      const int s = q[d] < 0 ? min(h[d], -q[d]) : 0;
+      const double proceeds = (static_cast<double>(px[d]) * static_cast<double>(s)) * one_m;
+      cash = cash + proceeds;
+      h[d] -= s;
+      x[d] = -s;
+    }
+  }
+  // Buys: the whole order if its debit fits, otherwise the largest affordable part.
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d) {
+    if (d < D) {
+      const int qd = q[d] > 0 ? q[d] : 0;
+      const double p = static_cast<double>(px[d]);
+      const double debit_q = (p * static_cast<double>(qd)) * one_p;
+      int k = qd;
+      double debit = debit_q;
+      if (!(debit_q <= cash)) {
+        k = partial_fill(cash, p, qd, one_p);
+        debit = (p * static_cast<double>(k)) * one_p;
+      }
+      cash = cash - debit;
+      h[d] += k;
+      x[d] += k;
+    }
+  }
+}
+
+// v = b + p^T h, accumulated in ascending stock order.
+template <int DMAX>
+__device__ __forceinline__ double portfolio_value(double cash, const int (&h)[DMAX],
+                                                  const float* px, int D) {
+#pragma clang fp contract(off)
+  double acc = cash;
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d)
+    if (d < D) acc = acc + static_cast<double>(px[d]) * static_cast<double>(h[d]);
+  return acc;
+}
+
+// Exact floor(i / D) for 0 <= i < 2^20 and 1 <= D <= 1024, via a float reciprocal: i/D is at
+// least 1/(2D) away from the next integer above it and the float error is far smaller.
+__device__ __forceinline__ int div_small(int i, float inv_d) {
+  return static_cast<int>((static_cast<float>(i) + 0.5f) * inv_d);
+}
+
+}  // namespace fm

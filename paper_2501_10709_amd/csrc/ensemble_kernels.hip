@@ -1,0 +1,195 @@
+// Ensemble kernels: weight packing, the per-actor MLP over 16-row tiles, and the combine step
+// (weighted average of the actor means, Gaussian noise, clip) used by ensemble_act.
+#include "device_common.h"
+#include "launch.h"
+#include "mlp_device.h"
+
+namespace fm {
+
+namespace {
+
+// Pack one float32 matrix W [kin][nout] (row-major) into the MFMA B-operand layout of DT.
+template <int DT>
+__global__ void pack_matrix_kernel(const float* __restrict__ w, int kin, int nout, int kin_pad,
+                                   int nout_pad, void* __restrict__ out) {
+  const size_t total = static_cast<size_t>(kin_pad) * nout_pad;
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  int k, col;
+  if constexpr (DT == kF32) {
+    // i = ((c * KQ + kq) * 64 + lane) * 4 + e
+    const int e = static_cast<int>(i & 3);
+    const int lane = static_cast<int>((i >> 2) & 63);
+    const size_t rest = i >> 8;
+    const int KQ = kin_pad / 16;
+    const int kq = static_cast<int>(rest % KQ);
+    const int c = static_cast<int>(rest / KQ);
+    k = 16 * kq + 4 * e + (lane >> 4);
+    col = 16 * c + (lane & 15);
+    static_cast<float*>(out)[i] = (k < kin && col < nout) ? w[static_cast<size_t>(k) * nout + col] : 0.0f;
+  } else {
+    // i = ((c * KK + kk) * 64 + lane) * 8 + j
+    const int j = static_cast<int>(i & 7);
+    const int lane = static_cast<int>((i >> 3) & 63);
+    const size_t rest = i >> 9;
+    const int KK = kin_pad / 32;
+    const int kk = static_cast<int>(rest % KK);
+    const int c = static_cast<int>(rest / KK);
+    k = 32 * kk + 8 * (lane >> 4) + j;
+    col = 16 * c + (lane & 15);
+    const float v = (k < kin && col < nout) ? w[static_cast<size_t>(k) * nout + col] : 0.0f;
+    static_cast<__bf16*>(out)[i] = static_cast<__bf16>(v);  // round to nearest even
+  }
+}
+
+__global__ void copy_pad_kernel(const float* __restrict__ src, int n, int n_pad,
+                                float* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_pad) dst[i] = i < n ? src[i] : 0.0f;
+}
+
+// The MLP of actor blockIdx.y on rows [16*blockIdx.x, +16) of obs [n][S]; writes tanh outputs to
+// mu [K][n][A].
+template <int DT, int TMAX>
+__global__ __launch_bounds__(256) void mlp_kernel(EnsDev E, const float* __restrict__ obs, int n,
+                                                  float* __restrict__ mu) {
+  using act_t = typename MT<DT>::act_t;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int k = blockIdx.y;
+  const int row0 = blockIdx.x * 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int st0 = act_stride<DT>(E.S_pad), sth = act_stride<DT>(E.H);
+  act_t* x0 = reinterpret_cast<act_t*>(smem);
+  act_t* x1 = x0 + 16 * st0;
+  act_t* x2 = x1 + 16 * sth;
+
+  // Stage the state tile, zero-padded to S_pad columns and 16 rows.
+  for (int i = threadIdx.x; i < 16 * E.S_pad; i += 256) {
+    const int r = i / E.S_pad, c = i - r * E.S_pad;
+    float v = 0.0f;
+    if (c < E.S && row0 + r < n) v = obs[static_cast<size_t>(row0 + r) * E.S + c];
+    x0[r * st0 + c] = static_cast<act_t>(v);
+  }
+  __syncthreads();
+
+  const unsigned char* P = E.base + static_cast<size_t>(k) * E.actor_stride;
+  const float* b1 = reinterpret_cast<const float*>(P + E.off_b1);
+  const float* b2 = reinterpret_cast<const float*>(P + E.off_b2);
+  const float* b3 = reinterpret_cast<const float*>(P + E.off_b3);
+  const int row_q = 4 * (lane >> 4), col_l = lane & 15;
+
+  auto hidden_epi = [&](act_t* out, int ost, const float* bias) {
+    return [=](int, int c, floatx4 acc) {
+      const int col = 16 * c + col_l;
+      const float b = bias[col];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[(row_q + r) * ost + col] = static_cast<act_t>(fast_tanh(acc[r] + b));
+    };
+  };
+  const int ht = E.H / 16;
+  mlp_layer<DT, TMAX>(x0, st0, E.S_pad, P + E.off_w1, ht, wave, lane, hidden_epi(x1, sth, b1));
+  __syncthreads();
+  mlp_layer<DT, TMAX>(x1, sth, E.H, P + E.off_w2, ht, wave, lane, hidden_epi(x2, sth, b2));
+  __syncthreads();
+  float* mu_k = mu + static_cast<size_t>(k) * n * E.A;
+  mlp_layer<DT, TMAX>(x2, sth, E.H, P + E.off_w3, E.A_pad / 16, wave, lane,
+                      [&](int, int c, floatx4 acc) {
+                        const int col = 16 * c + col_l;
+                        if (col >= E.A) return;
+                        const float b = b3[col];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                          const int row = row0 + row_q + r;
+                          if (row < n) mu_k[static_cast<size_t>(row) * E.A + col] = fast_tanh(acc[r] + b);
+                        }
+                      });
+}
+
+// a_bar = sum_k w_k mu_k; a = clip(a_bar + sigma * eps, -1, 1).  One thread per (row, group of
+// four outputs) so each Philox block is drawn once.
+__global__ void combine_kernel(int K, int n, int A, const float* __restrict__ mu,
+                               const float* __restrict__ mix, float sigma, uint64_t key, int t,
+                               int64_t env_offset, float* __restrict__ mean,
+                               float* __restrict__ act) {
+  const int G = (A + 3) >> 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * G) return;
+  const int row = i / G, g = i - row * G;
+  float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (sigma != 0.0f)
+    noise_block(key, static_cast<uint64_t>(env_offset + row), static_cast<uint64_t>(t),
+                static_cast<uint64_t>(g), z);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int d = 4 * g + r;
+    if (d >= A) break;
+    const size_t o = static_cast<size_t>(row) * A + d;
+    float acc = 0.0f;
+    for (int k = 0; k < K; ++k) acc = acc + mix[k] * mu[static_cast<size_t>(k) * n * A + o];
+    if (mean) mean[o] = acc;
+    float a = acc;
+    if (sigma != 0.0f) a = acc + sigma * z[r];
+    act[o] = fminf(fmaxf(a, -1.0f), 1.0f);
+  }
+}
+
+template <int DT>
+hipError_t launch_mlp_dt(const EnsDev& E, const float* obs, int n, float* mu, hipStream_t stream) {
+  const int st0 = act_stride<DT>(E.S_pad), sth = act_stride<DT>(E.H);
+  const size_t lds = static_cast<size_t>(16) * (st0 + 2 * sth) * MT<DT>::kElem;
+  const dim3 grid((n + 15) / 16, E.K);
+  const int tiles_per_wave = (E.H / 16 + 3) / 4;
+  auto go = [&](auto kern) -> hipError_t {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, stream, E, obs, n, mu);
+    return hipGetLastError();
+  };
+  if (tiles_per_wave <= 2) return go(mlp_kernel<DT, 2>);
+  if (tiles_per_wave <= 4) return go(mlp_kernel<DT, 4>);
+  return go(mlp_kernel<DT, 8>);
+}
+
+}  // namespace
+
+size_t mlp_lds_bytes(int dtype, int S_pad, int H) {
+  return dtype == kF32 ? static_cast<size_t>(16) * (act_stride<kF32>(S_pad) + 2 * act_stride<kF32>(H)) * 4
+                       : static_cast<size_t>(16) * (act_stride<kBF16>(S_pad) + 2 * act_stride<kBF16>(H)) * 2;
+}
+
+hipError_t launch_pack_matrix(int dtype, const float* w, int kin, int nout, int kin_pad,
+                              int nout_pad, void* out, hipStream_t stream) {
+  const size_t total = static_cast<size_t>(kin_pad) * nout_pad;
+  const dim3 grid(static_cast<unsigned>((total + 255) / 256));
+  if (dtype == kF32)
+    hipLaunchKernelGGL(pack_matrix_kernel<kF32>, grid, dim3(256), 0, stream, w, kin, nout, kin_pad,
+                       nout_pad, out);
+  else
+    hipLaunchKernelGGL(pack_matrix_kernel<kBF16>, grid, dim3(256), 0, stream, w, kin, nout, kin_pad,
+                       nout_pad, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_pad(const float* src, int n, int n_pad, float* dst, hipStream_t stream) {
+  hipLaunchKernelGGL(copy_pad_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, stream, src, n, n_pad,
+                     dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp(int dtype, const EnsDev& E, const float* obs, int n, float* mu,
+                      hipStream_t stream) {
+  return dtype == kF32 ? launch_mlp_dt<kF32>(E, obs, n, mu, stream)
+                       : launch_mlp_dt<kBF16>(E, obs, n, mu, stream);
+}
+
+hipError_t launch_combine(int K, int n, int A, const float* mu, const float* mix, float sigma,
+                          uint64_t key, int t, int64_t env_offset, float* mean, float* act,
+                          hipStream_t stream) {
+  const int total = n * ((A + 3) >> 2);
+  hipLaunchKernelGGL(combine_kernel, dim3((total + 255) / 256), dim3(256), 0, stream, K, n, A, mu, mix,
+                     sigma, key, t, env_offset, mean, act);
+  return hipGetLastError();
+}
+
+}  // namespace fm

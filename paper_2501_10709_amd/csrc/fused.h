@@ -1,0 +1,26 @@
+// The fused rollout: ensemble MLP (bfloat16 MFMA), noise, trading, reward and next state for
+// every step of a rollout in one launch (fused_rollout.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "device_common.h"
+#include "mlp_device.h"
+
+namespace fm {
+
+// Rows (environments) per workgroup of the fused kernel: 16 * row_tiles.
+struct FusedTuning {
+  int row_tiles = 0;  // 0: choose from the problem size
+};
+
+// Returns hipSuccess and leaves *why empty on success; sets *why for unsupported shapes.
+hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0,
+                                int n_steps, float sigma, uint64_t key, int64_t env_offset,
+                                float* obs_traj, float* act_traj, double* rew_traj, int* qty_traj,
+                                hipStream_t stream, std::string* why,
+                                FusedTuning tune = FusedTuning());
+
+}  // namespace fm

@@ -1,0 +1,44 @@
+// Host-side launchers of the library's kernels (internal; the public ABI is finrl_mi.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "device_common.h"
+#include "mlp_device.h"
+
+namespace fm {
+
+// Environment kernels (env_kernels.hip).  M = environments per 64-lane workgroup.
+hipError_t launch_env_reset(const EnvConst& C, const EnvState& st, float* obs, int M,
+                            hipStream_t stream);
+hipError_t launch_env_observe(const EnvConst& C, const EnvState& st, int day, float* obs, int M,
+                              hipStream_t stream);
+hipError_t launch_env_given(const EnvConst& C, const EnvState& st, int t0, int n_steps,
+                            const float* act, float* obs, double* rew, int* qty, int M,
+                            hipStream_t stream);
+hipError_t launch_env_ensemble_step(const EnvConst& C, const EnvState& st, int t,
+                                    const float* mu, const float* mix, int K, float sigma,
+                                    uint64_t key, int64_t env_offset, float* obs, float* act_out,
+                                    double* rew, int* qty, int M, hipStream_t stream);
+hipError_t launch_read_state(const EnvConst& C, const EnvState& st, double* cash, int* hold,
+                             double* asset, double* cumrew, hipStream_t stream);
+hipError_t launch_write_state(const EnvConst& C, const EnvState& st, const double* cash,
+                              const int* hold, const double* asset, const double* cumrew,
+                              hipStream_t stream);
+hipError_t launch_noise(uint64_t key, int64_t env_offset, int n, int t, int D, uint64_t* words,
+                        float* eps, hipStream_t stream);
+
+// Ensemble kernels (ensemble_kernels.hip).
+size_t mlp_lds_bytes(int dtype, int S_pad, int H);
+hipError_t launch_pack_matrix(int dtype, const float* w, int kin, int nout, int kin_pad,
+                              int nout_pad, void* out, hipStream_t stream);
+hipError_t launch_copy_pad(const float* src, int n, int n_pad, float* dst, hipStream_t stream);
+hipError_t launch_mlp(int dtype, const EnsDev& E, const float* obs, int n, float* mu,
+                      hipStream_t stream);
+hipError_t launch_combine(int K, int n, int A, const float* mu, const float* mix, float sigma,
+                          uint64_t key, int t, int64_t env_offset, float* mean, float* act,
+                          hipStream_t stream);
+
+}  // namespace fm

@@ -1,0 +1,128 @@
+// Ensemble MLP building blocks on MFMA (gfx950).
+//
+// Each actor is S -> H -> H -> A with tanh after every layer.  A workgroup evaluates one layer
+// for a 16-row tile of states: the tile's activations sit in LDS (row-major, padded rows), the
+// layer's weights are pre-packed so that every lane of a wavefront fetches the B-operand of an
+// MFMA with one contiguous load, and the four wavefronts of the workgroup split the layer's
+// 16-column output tiles between them.
+//
+//   float32:  v_mfma_f32_16x16x4_f32, B packed [col tile][k/16][lane][4]
+//             (element e of lane l is W[16 kq + 4 e + l/16][16 c + l%16])
+//   bfloat16: v_mfma_f32_16x16x32_bf16, B packed [col tile][k/32][lane][8]
+//             (element j of lane l is W[32 kk + 8 (l/16) + j][16 c + l%16])
+//
+// In both, lane l holds rows 4(l/16)..4(l/16)+3 of column l%16 of the 16x16 accumulator.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fm {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float floatx4;
+
+enum { kF32 = 0, kBF16 = 1 };
+
+template <int DT>
+struct MT;
+template <>
+struct MT<kF32> {
+  using act_t = float;
+  static constexpr int kKGroup = 16;  // k covered by one packed load per lane
+  static constexpr int kElem = 4;     // bytes per weight
+};
+template <>
+struct MT<kBF16> {
+  using act_t = __bf16;
+  static constexpr int kKGroup = 32;
+  static constexpr int kElem = 2;
+};
+
+__host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Row stride (elements) of an LDS activation tile with kin_pad columns: keeps the MFMA
+// A-operand reads free of bank conflicts.
+template <int DT>
+__host__ __device__ inline int act_stride(int kin_pad) {
+  return DT == kF32 ? round_up(kin_pad, 32) + 2 : kin_pad + 8;
+}
+
+// Device view of a packed ensemble.
+struct EnsDev {
+  int K, S, H, A;
+  int S_pad, A_pad;  // layer-1 input and layer-3 output, padded
+  const unsigned char* base;
+  size_t actor_stride;
+  size_t off_w1, off_w2, off_w3, off_b1, off_b2, off_b3;
+  const float* mix;  // [K]
+};
+
+// tanh from one exponential and one reciprocal: tanh|x| = (1 - e^{-2|x|}) / (1 + e^{-2|x|}).
+// Absolute error below 1e-6 over the whole range.
+__device__ __forceinline__ float fast_tanh(float x) {
+  const float t = __builtin_amdgcn_exp2f(-2.8853900817779268f * fabsf(x));  // e^{-2|x|}
+  const float y = (1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t);
+  return copysignf(y, x);
+}
+
+__device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 mfma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// One layer for the wavefront's column tiles c = wave, wave+4, ... (< ntiles).  sin: LDS tile
+// [16][in_stride] holding kin_pad valid (zero-padded) columns.  Calls epi(i, c, acc) for every
+// tile the wave owns.
+template <int DT, int TMAX, class Epi>
+__device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int in_stride,
+                                          int kin_pad, const void* wp, int ntiles, int wave,
+                                          int lane, Epi epi) {
+  floatx4 acc[TMAX];
+#pragma unroll
+  for (int i = 0; i < TMAX; ++i) acc[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  const int row = lane & 15, grp = lane >> 4;
+  if constexpr (DT == kF32) {
+    const float4* W = static_cast<const float4*>(wp);
+    const int KQ = kin_pad / 16;
+    for (int kq = 0; kq < KQ; ++kq) {
+      float a[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = sin[row * in_stride + 16 * kq + 4 * e + grp];
+#pragma unroll
+      for (int i = 0; i < TMAX; ++i) {
+        const int c = wave + 4 * i;
+        if (c < ntiles) {
+          const float4 b = W[(static_cast<size_t>(c) * KQ + kq) * 64 + lane];
+          acc[i] = mfma_f32(a[0], b.x, acc[i]);
+          acc[i] = mfma_f32(a[1], b.y, acc[i]);
+          acc[i] = mfma_f32(a[2], b.z, acc[i]);
+          acc[i] = mfma_f32(a[3], b.w, acc[i]);
+        }
+      }
+    }
+  } else {
+    const bf16x8* W = static_cast<const bf16x8*>(wp);
+    const int KK = kin_pad / 32;
+    for (int kk = 0; kk < KK; ++kk) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(sin + row * in_stride + 32 * kk + 8 * grp);
+#pragma unroll
+      for (int i = 0; i < TMAX; ++i) {
+        const int c = wave + 4 * i;
+        if (c < ntiles) {
+          const bf16x8 b = W[(static_cast<size_t>(c) * KK + kk) * 64 + lane];
+          acc[i] = mfma_bf16(a, b, acc[i]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TMAX; ++i) {
+    const int c = wave + 4 * i;
+    if (c < ntiles) epi(i, c, acc[i]);
+  }
+}
+
+}  // namespace fm

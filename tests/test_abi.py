@@ -1,0 +1,92 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol, and the host-side
+validation rejects bad arguments before anything reaches the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2501_10709_amd import binding as B
+from workload import PAPER_SCALE, TINY
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "finrl_mi.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return B.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_version(lib):
+    assert "gfx950" in B.fm_version()
+
+
+def test_env_workspace_bytes():
+    n = B.env_workspace_bytes(PAPER_SCALE.env)
+    N, D, S = 2048, 30, 211
+    assert n >= 3 * 8 * N + 4 * D * N + 4 * D * N + 4 * S * N
+    assert n % 256 == 0
+    for bad in (dict(n_envs=0), dict(n_stocks=0), dict(n_stocks=129), dict(n_ind=17), dict(n_days=0),
+                dict(hmax=0), dict(cost_rate=1.0), dict(cost_rate=-0.1), dict(init_cash=-1.0),
+                dict(init_cash=float("inf")), dict(reward_scale=float("nan"))):
+        assert B.env_workspace_bytes(TINY.env.replace(**bad)) == 0, bad
+
+
+def test_ensemble_workspace_bytes():
+    ok = B.ensemble_workspace_bytes(3, 211, 256, 30, B.FM_BF16, 2048)
+    weights_bf16 = 3 * 2 * (224 * 256 + 256 * 256 + 256 * 32)
+    mu = 3 * 2048 * 30 * 4
+    assert ok >= weights_bf16 + mu
+    assert B.ensemble_workspace_bytes(3, 211, 256, 30, B.FM_F32, 2048) > ok
+    for bad in ((0, 211, 256, 30, 0, 1), (9, 211, 256, 30, 0, 1), (3, 211, 250, 30, 0, 1),
+                (3, 211, 1024, 30, 0, 1), (3, 0, 256, 30, 0, 1), (3, 211, 256, 129, 0, 1),
+                (3, 211, 256, 30, 2, 1), (3, 211, 256, 30, 0, 0)):
+        assert B.ensemble_workspace_bytes(*bad) == 0, bad
+
+
+def test_invalid_arguments_return_error_without_device(lib):
+    cfg = B.make_config(TINY.env)
+    h = ctypes.c_void_p()
+    # NULL market pointer: rejected before any device call.
+    st = lib.env_create(ctypes.byref(cfg), None, None, None, 0, None, ctypes.byref(h))
+    assert st == B.FM_ERR_INVALID and "NULL" in B.fm_last_error()
+    bad = B.make_config(TINY.env.replace(n_stocks=500))
+    st = lib.env_create(ctypes.byref(bad), ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                        1 << 30, None, ctypes.byref(h))
+    assert st == B.FM_ERR_INVALID and "n_stocks" in B.fm_last_error()
+    # Misaligned workspace.
+    st = lib.env_create(ctypes.byref(cfg), ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(1028),
+                        1 << 30, None, ctypes.byref(h))
+    assert st == B.FM_ERR_INVALID and "aligned" in B.fm_last_error()
+    # Too small a workspace.
+    st = lib.env_create(ctypes.byref(cfg), ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                        16, None, ctypes.byref(h))
+    assert st == B.FM_ERR_INVALID and "small" in B.fm_last_error()
+    # NULL handles.
+    assert lib.env_reset(None, None) == B.FM_ERR_INVALID
+    assert lib.env_step(None, None, None, None, None, None) == B.FM_ERR_INVALID
+    assert lib.env_rollout(None, None, 1, None) == B.FM_ERR_INVALID
+    assert lib.ensemble_act(None, None, 1, 0.0, 0, 0, 0, None, None, None) == B.FM_ERR_INVALID
+    assert lib.env_day(None) == -1
+    # Ensemble argument checks.
+    e = ctypes.c_void_p()
+    assert lib.ensemble_create(3, 211, 100, 30, 0, ctypes.c_void_p(256), None, 16, ctypes.c_void_p(1024), 1 << 30,
+                               None, ctypes.byref(e)) == B.FM_ERR_INVALID
+    assert "hidden" in B.fm_last_error()
+    assert lib.fm_noise(7, 0, 4, 0, 30, None, None, None) == B.FM_ERR_INVALID

@@ -97,8 +97,8 @@ def _rsi_wilder(close: np.ndarray, n: int = 14) -> np.ndarray:
 def make_market(seed: int, n_stocks: int, n_days: int, n_ind: int = 5, drift: float = 3e-4,
                 vol=0.02) -> Market:
     """Seeded market of n_days+1 daily rows for n_stocks stocks (numpy PCG64)."""
-    if not 1 <= n_ind <= 5:
-        raise ValueError("n_ind must be in 1..5")
+    if not 0 <= n_ind <= 5:
+        raise ValueError("n_ind must be in 0..5")
     rng = np.random.default_rng(seed)
     n_total = n_days + BURN_IN
     close = gbm_closes(rng, n_total, n_stocks, drift, vol)
@@ -118,7 +118,7 @@ def make_market(seed: int, n_stocks: int, n_days: int, n_ind: int = 5, drift: fl
         volume / _rolling_mean(volume, 20) - 1.0,
         (_ema(close, 12) - _ema(close, 26)) / close,
     ][:n_ind]
-    ind = np.stack(feats, axis=1)  # [rows][I][D]
+    ind = np.stack(feats, axis=1) if feats else np.zeros((n_total + 1, 0, n_stocks))  # [rows][I][D]
     sl = slice(BURN_IN, BURN_IN + n_days + 1)
     f32 = lambda a: np.ascontiguousarray(a[sl], dtype=np.float32)
     return Market(close=f32(close), ind=f32(ind), open=f32(open_), high=f32(high), low=f32(low),
