@@ -100,72 +100,81 @@ __device__ __forceinline__ int order_from_action(float a, float hmax_f) {
 }
 
 // Largest k in [0, q] with (p*k)*one_p <= cash, for the case (p*q)*one_p > cash.  The debit is
-// monotone in k, so a quotient estimate followed by unit steps in both directions is exact
-// whatever the rounding of the division.
-__device__ __noinline__ int partial_fill(double cash, double p, int q, double one_p) {
+// monotone in k, so a quotient estimate (from an approximate reciprocal) followed by unit steps
+// in both directions is exact whatever the estimate's error; the steps are bounded by q.
+__device__ __forceinline__ int partial_fill(double cash, double p, int q, double one_p) {
 #pragma clang fp contract(off)
   const double c1 = p * one_p;
   if (!(c1 <= cash)) return 0;
-  double est = floor(cash / c1);
-  est = fmin(est, static_cast<double>(q));
-  int k = static_cast<int>(fmax(est, 0.0));
+  const double est = floor(cash * __builtin_amdgcn_rcp(c1));
+  int k = static_cast<int>(fmin(fmax(est, 0.0), static_cast<double>(q)));
   while (k < q && (p * static_cast<double>(k + 1)) * one_p <= cash) ++k;
   while (k > 0 && (p * static_cast<double>(k)) * one_p > cash) --k;
   return k;
 }
 
 // One day's trades for one environment held in registers: all sells in ascending stock order,
-// then all buys in ascending stock order, at prices px (float32, day t).  a: this env's
-// actions; x: executed shares (signed).
+// then all buys in ascending stock order, at prices px (float32, day t).  a, px: this env's
+// actions and the day's closes, zero-padded beyond the real stock count; a padded stock has no
+// order, so it adds +0.0 to (and subtracts +0.0 from) a non-negative cash, which leaves it
+// unchanged bit for bit.  x: executed shares (signed).
 template <int DMAX>
 __device__ __forceinline__ void trade(double& cash, int (&h)[DMAX], int (&x)[DMAX],
-                                      const float* a, const float* px, int D, float hmax_f,
-                                      double one_m, double one_p) {
+                                      const float (&a)[DMAX], const float (&px)[DMAX],
+                                      float hmax_f, double one_m, double one_p) {
 #pragma clang fp contract(off)
   int q[DMAX];
 #pragma unroll
-  for (int d = 0; d < DMAX; ++d) q[d] = (d < D) ? order_from_action(a[d], hmax_f) : 0;
-  // Sells: proceeds (p*s)*(1-c); a zero sale adds +0.0, which leaves a non-negative cash as is.
+  for (int d = 0; d < DMAX; ++d) q[d] = order_from_action(a[d], hmax_f);
+  // Sells: proceeds (p*s)*(1-c); a zero sale adds +0.0.
 #pragma unroll
   for (int d = 0; d < DMAX; ++d) {
-    if (d < D) {
-      const int s = q[d] < 0 ? min(h[d], -q[d]) : 0;
-      const double proceeds = (static_cast<double>(px[d]) * static_cast<double>(s)) * one_m;
-      cash = cash + proceeds;
-      h[d] -= s;
-      x[d] = -s;
-    }
+    const int s = q[d] < 0 ? min(h[d], -q[d]) : 0;
+    const double proceeds = (static_cast<double>(px[d]) * static_cast<double>(s)) * one_m;
+    cash = cash + proceeds;
+    h[d] -= s;
+    x[d] = -s;
   }
   // Buys: the whole order if its debit fits, otherwise the largest affordable part.
 #pragma unroll
   for (int d = 0; d < DMAX; ++d) {
-    if (d < D) {
-      const int qd = q[d] > 0 ? q[d] : 0;
-      const double p = static_cast<double>(px[d]);
-      const double debit_q = (p * static_cast<double>(qd)) * one_p;
-      int k = qd;
-      double debit = debit_q;
-      if (!(debit_q <= cash)) {
-        k = partial_fill(cash, p, qd, one_p);
-        debit = (p * static_cast<double>(k)) * one_p;
-      }
-      cash = cash - debit;
-      h[d] += k;
-      x[d] += k;
+    const int qd = q[d] > 0 ? q[d] : 0;
+    const double p = static_cast<double>(px[d]);
+    double debit = (p * static_cast<double>(qd)) * one_p;
+    int k = qd;
+    if (!(debit <= cash)) {
+      k = partial_fill(cash, p, qd, one_p);
+      debit = (p * static_cast<double>(k)) * one_p;
     }
+    cash = cash - debit;
+    h[d] += k;
+    x[d] += k;
   }
 }
 
-// v = b + p^T h, accumulated in ascending stock order.
+// v = b + p^T h, accumulated in ascending stock order (zero-padded stocks add +0.0).
 template <int DMAX>
 __device__ __forceinline__ double portfolio_value(double cash, const int (&h)[DMAX],
-                                                  const float* px, int D) {
+                                                  const float (&px)[DMAX]) {
 #pragma clang fp contract(off)
   double acc = cash;
 #pragma unroll
-  for (int d = 0; d < DMAX; ++d)
-    if (d < D) acc = acc + static_cast<double>(px[d]) * static_cast<double>(h[d]);
+  for (int d = 0; d < DMAX; ++d) acc = acc + static_cast<double>(px[d]) * static_cast<double>(h[d]);
   return acc;
+}
+
+// DMAX consecutive floats from a 16-byte-aligned LDS row.
+template <int DMAX>
+__device__ __forceinline__ void lds_row(float (&v)[DMAX], const float* row) {
+  static_assert(DMAX % 4 == 0, "rows are read four floats at a time");
+#pragma unroll
+  for (int d = 0; d < DMAX; d += 4) {
+    const float4 t = *reinterpret_cast<const float4*>(row + d);
+    v[d] = t.x;
+    v[d + 1] = t.y;
+    v[d + 2] = t.z;
+    v[d + 3] = t.w;
+  }
 }
 
 // Exact floor(i / D) for 0 <= i < 2^20 and 1 <= D <= 1024, via a float reciprocal: i/D is at

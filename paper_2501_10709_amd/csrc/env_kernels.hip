@@ -21,11 +21,13 @@ constexpr int kWave = 64;
 
 template <int DMAX>
 struct TileCfg {
-  static constexpr int kStride = DMAX + 1;                        // odd stride: lane-per-row LDS
-  static constexpr int kMaxM = DMAX <= 32 ? 64 : (2048 / DMAX);   // reads are conflict-free
+  static constexpr int kStride = DMAX + 4;                        // 16-byte rows for the chain
+  static constexpr int kMaxM = DMAX <= 32 ? 64 : (2048 / DMAX);   // envs per workgroup
   static constexpr int kMaxI = 16;
   static constexpr int kMaxS = (kMaxI + 2) * DMAX + 1;
   static constexpr int kSlots = (kMaxS + kWave - 1) / kWave;      // state entries per lane
+  static constexpr int kActRegs = kMaxM * DMAX / kWave;           // prefetched actions per lane
+  static constexpr int kMktRegs = ((kMaxI + 2) * DMAX + kWave - 1) / kWave;
 };
 
 enum Mode { kReset = 0, kGiven = 1, kEnsemble = 2, kObserve = 3 };
@@ -48,16 +50,24 @@ struct StepArgs {
   int* qty;            // [n_steps][N][D] or null
 };
 
+// Market entries of the step (it) in flat order: close[t] (D), close[t+1] (D), ind[t+1] (I*D).
+__device__ __forceinline__ float market_entry(const EnvConst& C, int t, int tn, int i, bool with_trade) {
+  const int D = C.D;
+  if (i < D) return with_trade ? C.close[static_cast<size_t>(t) * D + i] : 0.0f;
+  if (i < 2 * D) return C.close[static_cast<size_t>(tn) * D + (i - D)];
+  return C.ind[static_cast<size_t>(tn) * C.I * D + (i - 2 * D)];
+}
+
 template <int DMAX, int MODE>
 __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st, StepArgs A) {
   using TC = TileCfg<DMAX>;
   constexpr int ST = TC::kStride;
-  __shared__ float s_act[TC::kMaxM * ST];       // actions of the tile, [m][d]
-  __shared__ float s_env[TC::kMaxM * ST];       // per-env state entries [cash, h_0..h_{D-1}]
+  __shared__ __align__(16) float s_act[TC::kMaxM * ST];   // actions of the tile [m][d], zero-padded
+  __shared__ float s_env[TC::kMaxM * ST];                 // per-env state entries [cash, h_0..]
   __shared__ int s_qty[TC::kMaxM * ST];
-  __shared__ float s_px[DMAX];                  // close of the trading day
-  __shared__ float s_pn[DMAX];                  // close of the new day
-  __shared__ float s_mkt[(1 + TC::kMaxI) * DMAX];  // scaled close + indicators of the new day
+  __shared__ __align__(16) float s_px[DMAX];              // close of the trading day, zero-padded
+  __shared__ __align__(16) float s_pn[DMAX];              // close of the new day, zero-padded
+  __shared__ float s_mkt[(1 + TC::kMaxI) * DMAX];         // scaled new close + new indicators
   __shared__ float s_eps[TC::kMaxM * ST];
 
   const int lane = threadIdx.x;
@@ -66,32 +76,40 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
   const int M = min(A.M, N - n0);
   const float inv_d = 1.0f / static_cast<float>(D);
   const int MD = M * D;
+  const int n_mkt = (2 + C.I) * D;
+
+  // Zero the padding once: columns >= D of the action rows and of the price rows.
+  for (int i = lane; i < TC::kMaxM * ST; i += kWave) s_act[i] = 0.0f;
+  for (int i = lane; i < DMAX; i += kWave) {
+    s_px[i] = 0.0f;
+    s_pn[i] = 0.0f;
+  }
 
   // Per-lane plan for writing a state row: slot j covers entry f = lane + 64 j.
-  // kind 0: shared market entry (value cached in mval), 1: per-env entry s_env[idx], 2: none.
+  // kind 0: shared market entry, 1: per-env entry s_env[idx], 2: none.
   int kind[TC::kSlots], eidx[TC::kSlots];
 #pragma unroll
   for (int j = 0; j < TC::kSlots; ++j) {
     const int f = lane + kWave * j;
-    if (f >= S) {
-      kind[j] = 2;
-      eidx[j] = 0;
-    } else if (f == 0) {
-      kind[j] = 1;
-      eidx[j] = 0;
-    } else if (f <= D) {
-      kind[j] = 0;
-      eidx[j] = f - 1;
-    } else if (f <= 2 * D) {
-      kind[j] = 1;
-      eidx[j] = f - D;
-    } else {
-      kind[j] = 0;
-      eidx[j] = f - 1 - D;
+    kind[j] = 2;
+    eidx[j] = 0;
+    if (f < S) {
+      if (f == 0) {
+        kind[j] = 1;
+      } else if (f <= D) {
+        kind[j] = 0;
+        eidx[j] = f - 1;
+      } else if (f <= 2 * D) {
+        kind[j] = 1;
+        eidx[j] = f - D;
+      } else {
+        kind[j] = 0;
+        eidx[j] = f - 1 - D;
+      }
     }
   }
 
-  // Load the tile's state.
+  // The tile's trading state, in the registers of lanes 0..M-1.
   double cash = 0.0, asset = 0.0, cumrew = 0.0;
   int h[DMAX], x[DMAX];
   const bool active = lane < M;
@@ -103,7 +121,6 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
   }
   if (MODE == kReset) {
     cash = C.init_cash;
-    cumrew = 0.0;
   } else if (active) {
     cash = st.cash[n];
     asset = st.asset[n];
@@ -114,26 +131,60 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
   }
 
   const int n_iter = trades(MODE) ? A.n_steps : 1;
-  for (int it = 0; it < n_iter; ++it) {
-    const int t = A.t0 + it;                                  // trading day
-    const int tn = trades(MODE) ? t + 1 : A.t0;               // day of the state written
-    // Market rows to LDS.
-    for (int d = lane; d < D; d += kWave) {
-      if (trades(MODE)) s_px[d] = C.close[static_cast<size_t>(t) * D + d];
-      const float pn = C.close[static_cast<size_t>(tn) * D + d];
-      s_pn[d] = pn;
-      s_mkt[d] = pn * C.price_scale;
+  // Inputs of step it are fetched into registers one step ahead, then moved to LDS.
+  float pa[TC::kActRegs], pm[TC::kMktRegs];
+  auto fetch = [&](int it) {
+    const int t = A.t0 + it;
+    const int tn = trades(MODE) ? t + 1 : A.t0;
+#pragma unroll
+    for (int j = 0; j < TC::kMktRegs; ++j) {
+      const int i = lane + kWave * j;
+      pm[j] = i < n_mkt ? market_entry(C, t, tn, i, trades(MODE)) : 0.0f;
     }
-    for (int i = lane; i < C.I * D; i += kWave)
-      s_mkt[D + i] = C.ind[static_cast<size_t>(tn) * C.I * D + i];
-
     if (MODE == kGiven) {
       const float* src = A.act + (static_cast<size_t>(it) * N + n0) * D;
-      for (int i = lane; i < MD; i += kWave) {
-        const int m = div_small(i, inv_d);
-        s_act[m * ST + (i - m * D)] = src[i];
+#pragma unroll
+      for (int j = 0; j < TC::kActRegs; ++j) {
+        const int i = lane + kWave * j;
+        pa[j] = i < MD ? src[i] : 0.0f;
       }
-    } else if (MODE == kEnsemble) {
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int j = 0; j < TC::kMktRegs; ++j) {
+      const int i = lane + kWave * j;
+      if (i < D) {
+        s_px[i] = pm[j];
+      } else if (i < 2 * D) {
+        s_pn[i - D] = pm[j];
+        s_mkt[i - D] = pm[j] * C.price_scale;
+      } else if (i < n_mkt) {
+        s_mkt[i - D] = pm[j];
+      }
+    }
+    if (MODE == kGiven) {
+#pragma unroll
+      for (int j = 0; j < TC::kActRegs; ++j) {
+        const int i = lane + kWave * j;
+        if (i < MD) {
+          const int m = div_small(i, inv_d);
+          s_act[m * ST + (i - m * D)] = pa[j];
+        }
+      }
+    }
+  };
+
+  fetch(0);
+  __syncthreads();
+  commit();
+  __syncthreads();
+
+  for (int it = 0; it < n_iter; ++it) {
+    const int t = A.t0 + it;
+    if (it + 1 < n_iter) fetch(it + 1);
+
+    if (MODE == kEnsemble) {
       // Noise: one Philox block per (env, group of 4 stocks).
       const int G = (D + 3) >> 2;
       const float inv_g = 1.0f / static_cast<float>(G);
@@ -162,21 +213,27 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
         s_act[m * ST + d] = a;
         if (A.act_out) A.act_out[(static_cast<size_t>(it) * N + n0) * D + i] = a;
       }
+      __syncthreads();
     }
-    __syncthreads();
 
     double r = 0.0;
-    if (trades(MODE) && active) {
-      trade<DMAX>(cash, h, x, &s_act[lane * ST], s_px, D, C.hmax_f, C.one_m, C.one_p);
-      // New day: value at its close, reward, cumulative reward.
-      const double v_new = portfolio_value<DMAX>(cash, h, s_pn, D);
-      r = (v_new - asset) * C.reward_scale;
-      cumrew = cumrew + r;
-      asset = v_new;
-    } else if (MODE == kReset && active) {
-      asset = portfolio_value<DMAX>(cash, h, s_pn, D);
-    }
     if (active) {
+      if (trades(MODE)) {
+        float a[DMAX], px[DMAX];
+        lds_row<DMAX>(a, &s_act[lane * ST]);
+        lds_row<DMAX>(px, s_px);
+        trade<DMAX>(cash, h, x, a, px, C.hmax_f, C.one_m, C.one_p);
+        float pn[DMAX];
+        lds_row<DMAX>(pn, s_pn);
+        const double v_new = portfolio_value<DMAX>(cash, h, pn);
+        r = (v_new - asset) * C.reward_scale;
+        cumrew = cumrew + r;
+        asset = v_new;
+      } else if (MODE == kReset) {
+        float pn[DMAX];
+        lds_row<DMAX>(pn, s_pn);
+        asset = portfolio_value<DMAX>(cash, h, pn);
+      }
       s_env[lane * ST] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
 #pragma unroll
       for (int d = 0; d < DMAX; ++d)
@@ -187,9 +244,7 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
     }
     __syncthreads();
 
-    // Rewards.
     if (A.rew && trades(MODE) && active) A.rew[static_cast<size_t>(it) * N + n] = r;
-    // Executed quantities.
     if (A.qty && trades(MODE)) {
       int* dst = A.qty + (static_cast<size_t>(it) * N + n0) * D;
       for (int i = lane; i < MD; i += kWave) {
@@ -214,6 +269,10 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
       }
     }
     __syncthreads();
+    if (it + 1 < n_iter) {
+      commit();
+      __syncthreads();
+    }
   }
 
   // Store the state back.

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <type_traits>
 
 #include "device_common.h"
 #include "mlp_device.h"
@@ -14,7 +15,11 @@ namespace fm {
 // Rows (environments) per workgroup of the fused kernel: 16 * row_tiles.
 struct FusedTuning {
   int row_tiles = 0;  // 0: choose from the problem size
+  int schedule = 0;   // 0: streamed when the shape allows, 2: always the generic schedule
 };
+
+// True when the streamed MLP schedule handles this ensemble and environment.
+bool fused_streamed_shape(const EnvConst& C, const EnsDev& E);
 
 // Returns hipSuccess and leaves *why empty on success; sets *why for unsupported shapes.
 hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0,

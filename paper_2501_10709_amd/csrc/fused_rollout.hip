@@ -1,16 +1,22 @@
-// Fused rollout: one launch runs every step of a closed-loop rollout for a tile of 16*ROWT
-// environments per workgroup.  Per step, inside the workgroup and without leaving the chip for
-// anything but the weights and the trajectory stores:
-//   1. Gaussian noise for the tile (Philox4x64-10 + Box-Muller) into LDS;
-//   2. for each actor k: three bfloat16 MFMA layers over the tile's state rows (activations in
-//      LDS, weights streamed from L2 in the packed B-operand layout), accumulating
-//      a_bar = sum_k w_k mu_k in float32;
-//   3. a = clip(a_bar + sigma * eps, -1, 1);
-//   4. the trading chain (lane m of wavefront 0 owns environment m): orders, sells, buys, the new
+// Fused rollout: one launch runs every step of a closed-loop rollout for a tile of MR = 16*ROWT
+// environments per workgroup.  Per step, inside the workgroup:
+//   1. the K actors' three bfloat16 MFMA layers over the tile's state rows (activations in LDS,
+//      weights streamed from L2), accumulating a_bar = sum_k w_k mu_k in float32;
+//   2. Gaussian noise (Philox4x64-10 + Box-Muller) and a = clip(a_bar + sigma * eps, -1, 1);
+//   3. the trading chain (lane m of wavefront 0 owns environment m): orders, sells, buys, the new
 //      day's value in float64, reward, cumulative reward;
-//   5. the next state, written once as bfloat16 into LDS for the next step's first layer and, if
+//   4. the next state, written once as bfloat16 into LDS for the next step's first layer and, if
 //      requested, as float32 into the [T][N][S] trajectory.
 // Environments are independent, so workgroups never communicate.
+//
+// Two MLP schedules:
+//   * streamed (the 211 -> 256 -> 256 -> 30, K = 3 shape): eight wavefronts; every wavefront
+//     owns fixed output tiles and walks a compile-time sequence of weight fragments (all layers
+//     of all actors), keeping DEPTH k-steps of fragments in flight in registers.  The sequence
+//     wraps around, so the first fragments of the next step load while the trading chain runs.
+//   * generic (any supported shape): four wavefronts, runtime loops, one fragment at a time.
+#include <utility>
+
 #include "device_common.h"
 #include "fused.h"
 #include "mlp_device.h"
@@ -30,6 +36,137 @@ struct FusedArgs {
   int* qty_traj;
 };
 
+// Calls f(std::integral_constant<int, i>) for i = 0 .. N-1, fully unrolled.
+template <class Fn, int... I>
+__device__ __forceinline__ void static_for_impl(Fn&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>()), ...);
+}
+template <int N, class Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>());
+}
+
+// LDS layout shared by both schedules.
+template <int DMAX>
+struct FusedLds {
+  static constexpr int kAST = DMAX + 4;  // 16-byte rows for the chain's action reads
+  __bf16 *x0, *x1, *x2;                  // state rows, layer-1 and layer-2 outputs
+  float* abar;                           // [MR][DS]
+  float* act;                            // [MR][kAST]
+  float* env;                            // [MR][DS]: cash entry, holdings entries
+  int* qty;                              // [MR][DS]
+  float *px, *pn;                        // [DMAX] closes of the trading day / new day, zero-padded
+  float* mkt;                            // [(1+I)*D] scaled new close, new indicators
+
+  __host__ __device__ static size_t bytes(int MR, int st0, int sth, int D, int I) {
+    const size_t DS = D + 1;
+    size_t b = sizeof(__bf16) * MR * (static_cast<size_t>(st0) + 2 * sth);
+    b += sizeof(float) * MR * (3 * DS + kAST);
+    b += sizeof(float) * (2 * DMAX + (1 + I) * D);
+    return (b + 15) / 16 * 16;
+  }
+  __device__ void carve(unsigned char* smem, int MR, int st0, int sth, int D) {
+    const int DS = D + 1;
+    x0 = reinterpret_cast<__bf16*>(smem);
+    x1 = x0 + MR * st0;
+    x2 = x1 + MR * sth;
+    act = reinterpret_cast<float*>(x2 + MR * sth);  // 16-byte aligned: st0, sth are multiples of 8
+    abar = act + MR * kAST;
+    env = abar + MR * DS;
+    qty = reinterpret_cast<int*>(env + MR * DS);
+    px = reinterpret_cast<float*>(qty + MR * DS);
+    pn = px + DMAX;
+    mkt = pn + DMAX;
+  }
+};
+
+// The environment half of a step, shared by both schedules.  NT threads per workgroup.
+template <int DMAX, int NT>
+struct EnvPhase {
+  const EnvConst& C;
+  const FusedArgs& F;
+  FusedLds<DMAX>& L;
+  int tid, lane, wave, n0, M, S_pad, st0;
+  float inv_d, inv_g;
+  int G;
+
+  // Market rows of day tn (and the trading day tn-1 when trading) into LDS.
+  __device__ void stage_market(int tn, bool with_trade_day) {
+    const int D = C.D;
+    for (int d = tid; d < D; d += NT) {
+      if (with_trade_day) L.px[d] = C.close[static_cast<size_t>(tn - 1) * D + d];
+      const float pn = C.close[static_cast<size_t>(tn) * D + d];
+      L.pn[d] = pn;
+      L.mkt[d] = pn * C.price_scale;
+    }
+    for (int i = tid; i < C.I * D; i += NT) L.mkt[D + i] = C.ind[static_cast<size_t>(tn) * C.I * D + i];
+  }
+
+  // a = clip(a_bar + sigma * eps, -1, 1) into LDS (and the action trajectory).
+  __device__ void actions(int t, size_t row_base) {
+    const int D = C.D, DS = D + 1;
+    for (int i = tid; i < M * G; i += NT) {
+      const int m = div_small(i, inv_g);
+      const int g = i - m * G;
+      float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (F.sigma != 0.0f)
+        noise_block(F.key, static_cast<uint64_t>(F.env_offset + n0 + m), static_cast<uint64_t>(t),
+                    static_cast<uint64_t>(g), z);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int d = 4 * g + r;
+        if (d < D) {
+          float a = L.abar[m * DS + d];
+          if (F.sigma != 0.0f) a = a + F.sigma * z[r];
+          a = fminf(fmaxf(a, -1.0f), 1.0f);
+          L.act[m * FusedLds<DMAX>::kAST + d] = a;
+          if (F.act_traj) F.act_traj[(row_base + m) * D + d] = a;
+        }
+      }
+    }
+  }
+
+  // Cash and holdings entries of the state rows (owner lanes).
+  __device__ void env_entries(bool owner, double cash, const int (&h)[DMAX]) {
+    if (!owner) return;
+    const int DS = C.D + 1;
+    L.env[lane * DS] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d)
+      if (d < C.D) L.env[lane * DS + 1 + d] = static_cast<float>(h[d]) * C.hold_scale;
+  }
+
+  // State rows: bfloat16 into x0 for the next first layer, float32 into the trajectory.
+  __device__ void assemble(float* traj) {
+    const int D = C.D, DS = D + 1, S = C.S;
+    for (int m = 0; m < M; ++m) {
+      for (int f = tid; f < S_pad; f += NT) {
+        float v = 0.0f;
+        if (f < S) {
+          if (f == 0) v = L.env[m * DS];
+          else if (f <= D) v = L.mkt[f - 1];
+          else if (f <= 2 * D) v = L.env[m * DS + f - D];
+          else v = L.mkt[f - 1 - D];
+          if (traj) traj[static_cast<size_t>(m) * S + f] = v;
+        }
+        L.x0[m * st0 + f] = static_cast<__bf16>(v);
+      }
+    }
+  }
+
+  __device__ void quantities(size_t row_base) {
+    if (!F.qty_traj) return;
+    const int D = C.D, DS = D + 1;
+    for (int i = tid; i < M * D; i += NT) {
+      const int m = div_small(i, inv_d);
+      F.qty_traj[row_base * D + i] = L.qty[m * DS + (i - m * D)];
+    }
+  }
+};
+
+// ------------------------------------------------------------------------------------------
+// Generic MLP schedule (runtime shapes): wavefront w owns output tiles w, w+4, ...
+// ------------------------------------------------------------------------------------------
 template <int ROWT, int TMAX, class Epi>
 __device__ __forceinline__ void layer_bf16(const __bf16* sin, int ist, int kin_pad, const bf16x8* W,
                                            int ntiles, int wave, int lane, Epi epi) {
@@ -65,37 +202,71 @@ __device__ __forceinline__ void layer_bf16(const __bf16* sin, int ist, int kin_p
   }
 }
 
-template <int DMAX, int ROWT, int TMAX>
-__global__ __launch_bounds__(256) void fused_rollout_kernel(EnvConst C, EnvState st, EnsDev E,
-                                                            FusedArgs F) {
-  constexpr int MR = 16 * ROWT;  // rows per workgroup
+// ------------------------------------------------------------------------------------------
+// Streamed MLP schedule for K = 3, S_pad = 32*KK1, H = 256, A_pad = 32 with eight wavefronts.
+// Wavefront w owns layer-1/2 output tiles w and w+8 and, if w < 2, layer-3 tile w.  Its weight
+// fragments form a fixed sequence of NS k-steps per environment step; fragments for k-step
+// s+DEPTH are requested when k-step s is consumed.
+// ------------------------------------------------------------------------------------------
+template <int KK1, int ROWT, int DEPTH, int NWAVES>
+struct Streamed {
+  static constexpr int K = 3, KK2 = 8, HT = 16, AT = 2, NW = NWAVES, TW = HT / NWAVES;
+  static constexpr int SPA = KK1 + 2 * KK2;  // k-steps per actor
+  static constexpr int NS = K * SPA;         // k-steps per environment step
+
+  // Packed-ensemble layout of this shape (bytes; checked against the workspace on the host).
+  static constexpr size_t kW1 = 0, kW2 = 32 * KK1 * 256 * 2, kW3 = kW2 + 256 * 256 * 2;
+  static constexpr size_t kB1 = kW3 + 256 * 32 * 2, kB2 = kB1 + 1024, kB3 = kB2 + 1024;
+  static constexpr size_t kActor = kB3 + 256;
+
+  // Weight fragments of k-step S2 for wavefront wv (uniform); voff = lane * 16.
+  template <int S2>
+  static __device__ __forceinline__ void load(bf16x8 (&b)[TW], const unsigned char* wb, int wv, int voff) {
+    constexpr int actor = S2 / SPA, r = S2 % SPA;
+    const unsigned char* P = wb + kActor * actor;
+    if constexpr (r < KK1) {
+#pragma unroll
+      for (int i = 0; i < TW; ++i)
+        b[i] = *reinterpret_cast<const bf16x8*>(P + kW1 + static_cast<size_t>((wv + NW * i) * KK1 + r) * 1024 + voff);
+    } else if constexpr (r < KK1 + KK2) {
+      constexpr int kk = r - KK1;
+#pragma unroll
+      for (int i = 0; i < TW; ++i)
+        b[i] = *reinterpret_cast<const bf16x8*>(P + kW2 + static_cast<size_t>((wv + NW * i) * KK2 + kk) * 1024 + voff);
+    } else {
+      constexpr int kk = r - KK1 - KK2;
+      if (wv < AT) b[0] = *reinterpret_cast<const bf16x8*>(P + kW3 + static_cast<size_t>(wv * KK2 + kk) * 1024 + voff);
+    }
+  }
+};
+
+template <int DMAX, int ROWT, int KK1, int DEPTH, int NWAVES>
+__global__ __launch_bounds__(64 * NWAVES) void fused_streamed_kernel(EnvConst C, EnvState st, EnsDev E,
+                                                                     FusedArgs F) {
+  using SP = Streamed<KK1, ROWT, DEPTH, NWAVES>;
+  constexpr int NT = 64 * NWAVES, MR = 16 * ROWT, TW = SP::TW, NW = SP::NW;
+  constexpr int KK2 = SP::KK2, SPA = SP::SPA, NS = SP::NS;
+  constexpr int S_PAD = 32 * KK1, H = 256;
+  constexpr int ST0 = S_PAD + 8, STH = H + 8;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int D = C.D, S = C.S, N = C.N, I = C.I;
+  const int D = C.D, N = C.N, DS = D + 1;
   const int n0 = blockIdx.x * MR;
   const int M = min(MR, N - n0);
-  const int st0 = E.S_pad + 8, sth = E.H + 8;
-  const int DS = D + 1;
-  const float inv_d = 1.0f / static_cast<float>(D);
-  const int G = (D + 3) >> 2;
-  const float inv_g = 1.0f / static_cast<float>(G);
 
-  // LDS carve-up.
-  __bf16* x0 = reinterpret_cast<__bf16*>(smem);
-  __bf16* x1 = x0 + MR * st0;
-  __bf16* x2 = x1 + MR * sth;
-  float* s_abar = reinterpret_cast<float*>(x2 + MR * sth);
-  float* s_eps = s_abar + MR * DS;
-  float* s_act = s_eps + MR * DS;
-  float* s_env = s_act + MR * DS;               // [MR][D+1]: cash entry, holdings entries
-  int* s_qty = reinterpret_cast<int*>(s_env + MR * DS);
-  float* s_px = reinterpret_cast<float*>(s_qty + MR * DS);
-  float* s_pn = s_px + D;
-  float* s_mkt = s_pn + D;                      // [(1+I)*D]: scaled close, indicators
+  FusedLds<DMAX> L;
+  L.carve(smem, MR, ST0, STH, D);
+  EnvPhase<DMAX, NT> P{C, F, L, tid, lane, wave, n0, M, S_PAD, ST0, 1.0f / static_cast<float>(D),
+                       1.0f / static_cast<float>((D + 3) >> 2), (D + 3) >> 2};
 
-  for (int i = tid; i < MR * st0; i += 256) x0[i] = static_cast<__bf16>(0.0f);
+  for (int i = tid; i < MR * ST0; i += NT) L.x0[i] = static_cast<__bf16>(0.0f);
+  for (int i = tid; i < MR * FusedLds<DMAX>::kAST; i += NT) L.act[i] = 0.0f;
+  for (int i = tid; i < DMAX; i += NT) {
+    L.px[i] = 0.0f;
+    L.pn[i] = 0.0f;
+  }
+  __syncthreads();
 
-  // Trading state of environment n0+lane lives in wavefront 0's registers for the whole rollout.
   const bool owner = wave == 0 && lane < M;
   const int n = n0 + lane;
   double cash = 0.0, asset = 0.0, cumrew = 0.0;
@@ -114,139 +285,131 @@ __global__ __launch_bounds__(256) void fused_rollout_kernel(EnvConst C, EnvState
       if (d < D) h[d] = st.hold[static_cast<size_t>(d) * N + n];
   }
 
-  // Market rows of day tn into s_pn / s_mkt (and of day tn-1 into s_px when trading).
-  auto stage_market = [&](int tn, bool with_trade_day) {
-    for (int d = tid; d < D; d += 256) {
-      if (with_trade_day) s_px[d] = C.close[static_cast<size_t>(tn - 1) * D + d];
-      const float pn = C.close[static_cast<size_t>(tn) * D + d];
-      s_pn[d] = pn;
-      s_mkt[d] = pn * C.price_scale;
-    }
-    for (int i = tid; i < I * D; i += 256) s_mkt[D + i] = C.ind[static_cast<size_t>(tn) * I * D + i];
-  };
-  auto write_env_entries = [&]() {
-    if (owner) {
-      s_env[lane * DS] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
-#pragma unroll
-      for (int d = 0; d < DMAX; ++d)
-        if (d < D) s_env[lane * DS + 1 + d] = static_cast<float>(h[d]) * C.hold_scale;
-    }
-  };
-  // State rows: bfloat16 into x0 for the next first layer, float32 into the trajectory.
-  auto assemble = [&](float* traj) {
-    for (int m = 0; m < M; ++m) {
-      for (int f = tid; f < E.S_pad; f += 256) {
-        float v = 0.0f;
-        if (f < S) {
-          if (f == 0) v = s_env[m * DS];
-          else if (f <= D) v = s_mkt[f - 1];
-          else if (f <= 2 * D) v = s_env[m * DS + f - D];
-          else v = s_mkt[f - 1 - D];
-          if (traj) traj[static_cast<size_t>(m) * S + f] = v;
-        }
-        x0[m * st0 + f] = static_cast<__bf16>(v);
-      }
-    }
-  };
-
-  stage_market(F.t0, false);
-  write_env_entries();
+  P.stage_market(F.t0, false);
+  P.env_entries(owner, cash, h);
   __syncthreads();
-  assemble(nullptr);
-  __syncthreads();
+  P.assemble(nullptr);
 
-  const int row_q = 4 * (lane >> 4), col_l = lane & 15;
-  const int ht = E.H / 16, at = E.A_pad / 16;
+  // Weight fragments in flight: ring[s % DEPTH] holds k-step s.
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int voff = lane * 16;
+  bf16x8 ring[DEPTH][TW];
+  static_for<DEPTH>([&](auto sc) __attribute__((always_inline)) {
+    constexpr int s = decltype(sc)::value;
+    SP::template load<s>(ring[s], E.base, wv, voff);
+  });
+
+  const int row_q = 4 * (lane >> 4), col_l = lane & 15, row = lane & 15, grp = lane >> 4;
+  const float* mix = E.mix;
 
   for (int it = 0; it < F.n_steps; ++it) {
     const int t = F.t0 + it;
     const size_t row_base = static_cast<size_t>(it) * N + n0;
-    stage_market(t + 1, true);
-    if (F.sigma != 0.0f) {
-      for (int i = tid; i < M * G; i += 256) {
-        const int m = div_small(i, inv_g);
-        const int g = i - m * G;
-        float z[4];
-        noise_block(F.key, static_cast<uint64_t>(F.env_offset + n0 + m), static_cast<uint64_t>(t),
-                    static_cast<uint64_t>(g), z);
+    __syncthreads();                       // x0 complete; LDS market rows free
+    P.stage_market(t + 1, true);
+    // The weight base is re-read as an opaque value every step, so that no fragment address is
+    // hoisted out of the step loop (there are hundreds of them).
+    const unsigned char* wb = E.base;
+    asm volatile("" : "+s"(wb));
+
+    floatx4 acc[ROWT][TW];
+    static_for<NS>([&](auto sc) __attribute__((always_inline)) {
+      constexpr int s = decltype(sc)::value;
+      // Keep the k-steps in program order: the scheduler would otherwise hoist every load of a
+      // layer to its top and run out of registers.
+      __builtin_amdgcn_sched_barrier(0);
+      constexpr int actor = s / SPA, r = s % SPA;
+      constexpr int layer = r < KK1 ? 1 : (r < KK1 + KK2 ? 2 : 3);
+      constexpr int kk = layer == 1 ? r : (layer == 2 ? r - KK1 : r - KK1 - KK2);
+      constexpr int first = layer == 1 ? 0 : (layer == 2 ? KK1 : KK1 + KK2);
+      constexpr int last = layer == 1 ? KK1 - 1 : (layer == 2 ? KK1 + KK2 - 1 : SPA - 1);
+      if constexpr (r == first) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (4 * g + r < D) s_eps[m * DS + 4 * g + r] = z[r];
+        for (int rt = 0; rt < ROWT; ++rt)
+#pragma unroll
+          for (int i = 0; i < TW; ++i) acc[rt][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
       }
-    }
+      bf16x8 cur[TW];
+#pragma unroll
+      for (int i = 0; i < TW; ++i) cur[i] = ring[s % DEPTH][i];
+      SP::template load<(s + DEPTH) % NS>(ring[s % DEPTH], wb, wv, voff);
 
-    for (int k = 0; k < E.K; ++k) {
-      const unsigned char* P = E.base + static_cast<size_t>(k) * E.actor_stride;
-      const float* b1 = reinterpret_cast<const float*>(P + E.off_b1);
-      const float* b2 = reinterpret_cast<const float*>(P + E.off_b2);
-      const float* b3 = reinterpret_cast<const float*>(P + E.off_b3);
-      const float wk = E.mix[k];
-      layer_bf16<ROWT, TMAX>(x0, st0, E.S_pad, reinterpret_cast<const bf16x8*>(P + E.off_w1), ht, wave, lane,
-                             [&](int rt, int c, floatx4 acc) {
-                               const int col = 16 * c + col_l;
-                               const float b = b1[col];
+      const __bf16* src = layer == 1 ? L.x0 : (layer == 2 ? L.x1 : L.x2);
+      constexpr int ist = layer == 1 ? ST0 : STH;
+      bf16x8 a[ROWT];
 #pragma unroll
-                               for (int r = 0; r < 4; ++r)
-                                 x1[(rt * 16 + row_q + r) * sth + col] = static_cast<__bf16>(fast_tanh(acc[r] + b));
-                             });
-      __syncthreads();
-      layer_bf16<ROWT, TMAX>(x1, sth, E.H, reinterpret_cast<const bf16x8*>(P + E.off_w2), ht, wave, lane,
-                             [&](int rt, int c, floatx4 acc) {
-                               const int col = 16 * c + col_l;
-                               const float b = b2[col];
+      for (int rt = 0; rt < ROWT; ++rt)
+        a[rt] = *reinterpret_cast<const bf16x8*>(src + (rt * 16 + row) * ist + 32 * kk + 8 * grp);
+      if constexpr (layer < 3) {
 #pragma unroll
-                               for (int r = 0; r < 4; ++r)
-                                 x2[(rt * 16 + row_q + r) * sth + col] = static_cast<__bf16>(fast_tanh(acc[r] + b));
-                             });
-      __syncthreads();
-      layer_bf16<ROWT, TMAX>(x2, sth, E.H, reinterpret_cast<const bf16x8*>(P + E.off_w3), at, wave, lane,
-                             [&](int rt, int c, floatx4 acc) {
-                               const int col = 16 * c + col_l;
-                               if (col >= E.A) return;
-                               const float b = b3[col];
+        for (int i = 0; i < TW; ++i)
 #pragma unroll
-                               for (int r = 0; r < 4; ++r) {
-                                 float* dst = &s_abar[(rt * 16 + row_q + r) * DS + col];
-                                 const float v = wk * fast_tanh(acc[r] + b);
-                                 *dst = (k == 0) ? v : (*dst + v);
-                               }
-                             });
-      __syncthreads();
-    }
+          for (int rt = 0; rt < ROWT; ++rt) acc[rt][i] = mfma_bf16(a[rt], cur[i], acc[rt][i]);
+      } else {
+        if (wave < SP::AT) {
+#pragma unroll
+          for (int rt = 0; rt < ROWT; ++rt) acc[rt][0] = mfma_bf16(a[rt], cur[0], acc[rt][0]);
+        }
+      }
 
-    // Noisy, clipped action.
-    for (int i = tid; i < M * D; i += 256) {
-      const int m = div_small(i, inv_d);
-      const int d = i - m * D;
-      float a = s_abar[m * DS + d];
-      if (F.sigma != 0.0f) a = a + F.sigma * s_eps[m * DS + d];
-      a = fminf(fmaxf(a, -1.0f), 1.0f);
-      s_act[m * DS + d] = a;
-      if (F.act_traj) F.act_traj[row_base * D + i] = a;
-    }
+      if constexpr (r == last) {
+        const unsigned char* PA = wb + SP::kActor * actor;
+        if constexpr (layer < 3) {
+          const float* bias = reinterpret_cast<const float*>(PA + (layer == 1 ? SP::kB1 : SP::kB2));
+          __bf16* out = layer == 1 ? L.x1 : L.x2;
+#pragma unroll
+          for (int i = 0; i < TW; ++i) {
+            const int col = 16 * (wave + NW * i) + col_l;
+            const float b = bias[col];
+#pragma unroll
+            for (int rt = 0; rt < ROWT; ++rt)
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                out[(rt * 16 + row_q + q) * STH + col] = static_cast<__bf16>(fast_tanh(acc[rt][i][q] + b));
+          }
+        } else {
+          if (wave < SP::AT) {
+            const float* b3 = reinterpret_cast<const float*>(PA + SP::kB3);
+            const int col = 16 * wave + col_l;
+            if (col < E.A) {
+              const float b = b3[col];
+              const float wk = mix[actor];
+#pragma unroll
+              for (int rt = 0; rt < ROWT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  float* dst = &L.abar[(rt * 16 + row_q + q) * DS + col];
+                  const float v = wk * fast_tanh(acc[rt][0][q] + b);
+                  *dst = (actor == 0) ? v : (*dst + v);
+                }
+            }
+          }
+        }
+        __syncthreads();
+      }
+    });
+
+    P.actions(t, row_base);
     __syncthreads();
-
     if (owner) {
-      trade<DMAX>(cash, h, x, &s_act[lane * DS], s_px, D, C.hmax_f, C.one_m, C.one_p);
-      const double v_new = portfolio_value<DMAX>(cash, h, s_pn, D);
-      const double r = (v_new - asset) * C.reward_scale;
-      cumrew = cumrew + r;
+      float a[DMAX], px[DMAX], pn[DMAX];
+      lds_row<DMAX>(a, &L.act[lane * FusedLds<DMAX>::kAST]);
+      lds_row<DMAX>(px, L.px);
+      trade<DMAX>(cash, h, x, a, px, C.hmax_f, C.one_m, C.one_p);
+      lds_row<DMAX>(pn, L.pn);
+      const double v_new = portfolio_value<DMAX>(cash, h, pn);
+      const double rwd = (v_new - asset) * C.reward_scale;
+      cumrew = cumrew + rwd;
       asset = v_new;
-      if (F.rew_traj) F.rew_traj[static_cast<size_t>(it) * N + n] = r;
+      if (F.rew_traj) F.rew_traj[static_cast<size_t>(it) * N + n] = rwd;
 #pragma unroll
       for (int d = 0; d < DMAX; ++d)
-        if (d < D) s_qty[lane * DS + d] = x[d];
+        if (d < D) L.qty[lane * DS + d] = x[d];
     }
-    write_env_entries();
+    P.env_entries(owner, cash, h);
     __syncthreads();
-
-    if (F.qty_traj)
-      for (int i = tid; i < M * D; i += 256) {
-        const int m = div_small(i, inv_d);
-        F.qty_traj[row_base * D + i] = s_qty[m * DS + (i - m * D)];
-      }
-    assemble(F.obs_traj ? F.obs_traj + row_base * S : nullptr);
-    __syncthreads();
+    P.quantities(row_base);
+    P.assemble(F.obs_traj ? F.obs_traj + row_base * C.S : nullptr);
   }
 
   if (owner) {
@@ -259,45 +422,178 @@ __global__ __launch_bounds__(256) void fused_rollout_kernel(EnvConst C, EnvState
   }
 }
 
-size_t fused_lds_bytes(const EnvConst& C, const EnsDev& E, int rowt) {
-  const int MR = 16 * rowt;
-  const size_t DS = C.D + 1;
-  size_t b = sizeof(__bf16) * MR * (static_cast<size_t>(E.S_pad + 8) + 2 * (E.H + 8));
-  b += sizeof(float) * MR * DS * 5;  // abar, eps, act, env, qty
-  b += sizeof(float) * (2 * C.D + (1 + C.I) * C.D);
-  return b;
+template <int DMAX, int ROWT, int TMAX>
+__global__ __launch_bounds__(256) void fused_generic_kernel(EnvConst C, EnvState st, EnsDev E,
+                                                            FusedArgs F) {
+  constexpr int NT = 256, MR = 16 * ROWT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int D = C.D, N = C.N, DS = D + 1;
+  const int n0 = blockIdx.x * MR;
+  const int M = min(MR, N - n0);
+  const int st0 = E.S_pad + 8, sth = E.H + 8;
+
+  FusedLds<DMAX> L;
+  L.carve(smem, MR, st0, sth, D);
+  EnvPhase<DMAX, NT> P{C, F, L, tid, lane, wave, n0, M, E.S_pad, st0, 1.0f / static_cast<float>(D),
+                       1.0f / static_cast<float>((D + 3) >> 2), (D + 3) >> 2};
+
+  for (int i = tid; i < MR * st0; i += NT) L.x0[i] = static_cast<__bf16>(0.0f);
+  for (int i = tid; i < MR * FusedLds<DMAX>::kAST; i += NT) L.act[i] = 0.0f;
+  for (int i = tid; i < DMAX; i += NT) {
+    L.px[i] = 0.0f;
+    L.pn[i] = 0.0f;
+  }
+  __syncthreads();
+
+  const bool owner = wave == 0 && lane < M;
+  const int n = n0 + lane;
+  double cash = 0.0, asset = 0.0, cumrew = 0.0;
+  int h[DMAX], x[DMAX];
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d) {
+    h[d] = 0;
+    x[d] = 0;
+  }
+  if (owner) {
+    cash = st.cash[n];
+    asset = st.asset[n];
+    cumrew = st.cumrew[n];
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d)
+      if (d < D) h[d] = st.hold[static_cast<size_t>(d) * N + n];
+  }
+
+  P.stage_market(F.t0, false);
+  P.env_entries(owner, cash, h);
+  __syncthreads();
+  P.assemble(nullptr);
+
+  const int row_q = 4 * (lane >> 4), col_l = lane & 15;
+  const int ht = E.H / 16, at = E.A_pad / 16;
+
+  for (int it = 0; it < F.n_steps; ++it) {
+    const int t = F.t0 + it;
+    const size_t row_base = static_cast<size_t>(it) * N + n0;
+    __syncthreads();
+    P.stage_market(t + 1, true);
+
+    for (int k = 0; k < E.K; ++k) {
+      const unsigned char* PA = E.base + static_cast<size_t>(k) * E.actor_stride;
+      const float* b1 = reinterpret_cast<const float*>(PA + E.off_b1);
+      const float* b2 = reinterpret_cast<const float*>(PA + E.off_b2);
+      const float* b3 = reinterpret_cast<const float*>(PA + E.off_b3);
+      const float wk = E.mix[k];
+      layer_bf16<ROWT, TMAX>(L.x0, st0, E.S_pad, reinterpret_cast<const bf16x8*>(PA + E.off_w1), ht, wave, lane,
+                             [&](int rt, int c, floatx4 acc) {
+                               const int col = 16 * c + col_l;
+                               const float b = b1[col];
+#pragma unroll
+                               for (int q = 0; q < 4; ++q)
+                                 L.x1[(rt * 16 + row_q + q) * sth + col] = static_cast<__bf16>(fast_tanh(acc[q] + b));
+                             });
+      __syncthreads();
+      layer_bf16<ROWT, TMAX>(L.x1, sth, E.H, reinterpret_cast<const bf16x8*>(PA + E.off_w2), ht, wave, lane,
+                             [&](int rt, int c, floatx4 acc) {
+                               const int col = 16 * c + col_l;
+                               const float b = b2[col];
+#pragma unroll
+                               for (int q = 0; q < 4; ++q)
+                                 L.x2[(rt * 16 + row_q + q) * sth + col] = static_cast<__bf16>(fast_tanh(acc[q] + b));
+                             });
+      __syncthreads();
+      layer_bf16<ROWT, TMAX>(L.x2, sth, E.H, reinterpret_cast<const bf16x8*>(PA + E.off_w3), at, wave, lane,
+                             [&](int rt, int c, floatx4 acc) {
+                               const int col = 16 * c + col_l;
+                               if (col >= E.A) return;
+                               const float b = b3[col];
+#pragma unroll
+                               for (int q = 0; q < 4; ++q) {
+                                 float* dst = &L.abar[(rt * 16 + row_q + q) * DS + col];
+                                 const float v = wk * fast_tanh(acc[q] + b);
+                                 *dst = (k == 0) ? v : (*dst + v);
+                               }
+                             });
+      __syncthreads();
+    }
+
+    P.actions(t, row_base);
+    __syncthreads();
+    if (owner) {
+      float a[DMAX], px[DMAX], pn[DMAX];
+      lds_row<DMAX>(a, &L.act[lane * FusedLds<DMAX>::kAST]);
+      lds_row<DMAX>(px, L.px);
+      trade<DMAX>(cash, h, x, a, px, C.hmax_f, C.one_m, C.one_p);
+      lds_row<DMAX>(pn, L.pn);
+      const double v_new = portfolio_value<DMAX>(cash, h, pn);
+      const double rwd = (v_new - asset) * C.reward_scale;
+      cumrew = cumrew + rwd;
+      asset = v_new;
+      if (F.rew_traj) F.rew_traj[static_cast<size_t>(it) * N + n] = rwd;
+#pragma unroll
+      for (int d = 0; d < DMAX; ++d)
+        if (d < D) L.qty[lane * DS + d] = x[d];
+    }
+    P.env_entries(owner, cash, h);
+    __syncthreads();
+    P.quantities(row_base);
+    P.assemble(F.obs_traj ? F.obs_traj + row_base * C.S : nullptr);
+  }
+
+  if (owner) {
+    st.cash[n] = cash;
+    st.asset[n] = asset;
+    st.cumrew[n] = cumrew;
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d)
+      if (d < D) st.hold[static_cast<size_t>(d) * N + n] = h[d];
+  }
+}
+
+template <class Kern>
+hipError_t go(Kern kern, int grid, int threads, size_t lds, hipStream_t stream, const EnvConst& C,
+              const EnvState& st, const EnsDev& E, const FusedArgs& F) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, stream, C, st, E, F);
+  return hipGetLastError();
 }
 
 template <int DMAX, int ROWT>
-hipError_t launch_rowt(const EnvConst& C, const EnvState& st, const EnsDev& E, const FusedArgs& F,
-                       hipStream_t stream, std::string* why) {
-  const size_t lds = fused_lds_bytes(C, E, ROWT);
+hipError_t launch_generic(const EnvConst& C, const EnvState& st, const EnsDev& E, const FusedArgs& F,
+                          hipStream_t stream, std::string* why) {
+  const size_t lds = FusedLds<DMAX>::bytes(16 * ROWT, E.S_pad + 8, E.H + 8, C.D, C.I);
   if (lds > 160 * 1024) {
     *why = "fused rollout: state and hidden sizes exceed the LDS budget";
     return hipSuccess;
   }
   const int grid = (C.N + 16 * ROWT - 1) / (16 * ROWT);
   const int tiles_per_wave = (E.H / 16 + 3) / 4;
-  auto go = [&](auto kern) -> hipError_t {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, stream, C, st, E, F);
-    return hipGetLastError();
-  };
-  if (tiles_per_wave <= 2) return go(fused_rollout_kernel<DMAX, ROWT, 2>);
-  if (tiles_per_wave <= 4) return go(fused_rollout_kernel<DMAX, ROWT, 4>);
-  return go(fused_rollout_kernel<DMAX, ROWT, 8>);
+  if (tiles_per_wave <= 2) return go(fused_generic_kernel<DMAX, ROWT, 2>, grid, 256, lds, stream, C, st, E, F);
+  if (tiles_per_wave <= 4) return go(fused_generic_kernel<DMAX, ROWT, 4>, grid, 256, lds, stream, C, st, E, F);
+  return go(fused_generic_kernel<DMAX, ROWT, 8>, grid, 256, lds, stream, C, st, E, F);
 }
 
-template <int DMAX>
-hipError_t launch_dmax(const EnvConst& C, const EnvState& st, const EnsDev& E, const FusedArgs& F, int rowt,
-                       hipStream_t stream, std::string* why) {
-  if (rowt == 1) return launch_rowt<DMAX, 1>(C, st, E, F, stream, why);
-  return launch_rowt<DMAX, 2>(C, st, E, F, stream, why);
+constexpr int kDepth = 6;
+constexpr int kWaves = 4;
+
+template <int ROWT>
+hipError_t launch_streamed(const EnvConst& C, const EnvState& st, const EnsDev& E, const FusedArgs& F,
+                           hipStream_t stream) {
+  const size_t lds = FusedLds<32>::bytes(16 * ROWT, 224 + 8, 256 + 8, C.D, C.I);
+  const int grid = (C.N + 16 * ROWT - 1) / (16 * ROWT);
+  return go(fused_streamed_kernel<32, ROWT, 7, kDepth, kWaves>, grid, 64 * kWaves, lds, stream, C, st, E, F);
 }
 
 }  // namespace
+
+bool fused_streamed_shape(const EnvConst& C, const EnsDev& E) {
+  using SP = Streamed<7, 1, kDepth, kWaves>;
+  return E.K == 3 && E.H == 256 && E.S_pad == 224 && E.A_pad == 32 && C.D <= 32 && C.D >= 1 &&
+         E.off_w1 == SP::kW1 && E.off_w2 == SP::kW2 && E.off_w3 == SP::kW3 && E.off_b1 == SP::kB1 &&
+         E.off_b2 == SP::kB2 && E.off_b3 == SP::kB3 && E.actor_stride == SP::kActor;
+}
 
 hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0, int n_steps,
                                 float sigma, uint64_t key, int64_t env_offset, float* obs_traj, float* act_traj,
@@ -310,12 +606,19 @@ hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const Ens
   }
   FusedArgs F{t0, n_steps, sigma, key, env_offset, obs_traj, act_traj, rew_traj, qty_traj};
   int rowt = tune.row_tiles;
-  if (rowt <= 0) rowt = C.N >= 8192 ? 2 : 1;
-  if (C.D <= 8) return launch_dmax<8>(C, st, E, F, rowt, stream, why);
-  if (C.D <= 16) return launch_dmax<16>(C, st, E, F, rowt, stream, why);
-  if (C.D <= 32) return launch_dmax<32>(C, st, E, F, rowt, stream, why);
-  if (C.D <= 64) return launch_dmax<64>(C, st, E, F, rowt, stream, why);
-  if (C.D <= 128) return launch_dmax<128>(C, st, E, F, rowt, stream, why);
+  if (rowt <= 0) rowt = C.N >= 4096 ? 2 : 1;
+  rowt = rowt >= 2 ? 2 : 1;
+  if (tune.schedule != 2 && fused_streamed_shape(C, E))
+    return rowt == 2 ? launch_streamed<2>(C, st, E, F, stream) : launch_streamed<1>(C, st, E, F, stream);
+  auto gen = [&](auto dm) -> hipError_t {
+    constexpr int DM = decltype(dm)::value;
+    return launch_generic<DM, 1>(C, st, E, F, stream, why);
+  };
+  if (C.D <= 8) return gen(std::integral_constant<int, 8>());
+  if (C.D <= 16) return gen(std::integral_constant<int, 16>());
+  if (C.D <= 32) return gen(std::integral_constant<int, 32>());
+  if (C.D <= 64) return gen(std::integral_constant<int, 64>());
+  if (C.D <= 128) return gen(std::integral_constant<int, 128>());
   *why = "fused rollout: at most 128 stocks";
   return hipSuccess;
 }

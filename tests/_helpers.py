@@ -61,19 +61,22 @@ def check_replay(cfg, m, traj, obs0, env_ids=None):
     return ref
 
 
-def check_actions(actors, dtype, traj, obs0, sigma, key, tol, env_ids=None, steps=None, env_offset=0):
+def check_actions(actors, dtype, traj, obs0, sigma, key, tol, env_ids=None, steps=None, env_offset=0,
+                  id_map=None):
     """The GPU's action at (t, n) against the oracle ensemble acting on the GPU's own state s_t.
 
-    env_ids / steps select a sample (default all).  Returns the largest absolute error.
+    env_ids / steps select a sample (default all).  id_map: global environment index of each
+    column of traj when traj holds a subset of the batch.  Returns the largest absolute error.
     """
     w = device_weights(actors, dtype)
     act = traj["act"]
     T, N, _ = act.shape
     ids = np.arange(N) if env_ids is None else np.asarray(env_ids)
+    glob = ids if id_map is None else np.asarray(id_map)[ids]
     worst = 0.0
     for t in (range(T) if steps is None else steps):
         s_t = obs0[ids] if t == 0 else traj["obs"][t - 1][ids]
-        a_ref = ensemble_act(w, s_t, t, 0, sigma, key, env_ids=env_offset + ids)
+        a_ref = ensemble_act(w, s_t, t, 0, sigma, key, env_ids=env_offset + glob)
         e = float(np.max(np.abs(a_ref.astype(np.float64) - act[t][ids].astype(np.float64))))
         worst = max(worst, e)
     assert worst <= tol, f"actions off by {worst:.3e} (tolerance {tol})"
