@@ -99,6 +99,41 @@ def cpu_baseline(w, seconds_hint=True):
                       f"float64 numpy, {dt:.1f} s", "host_cpus": os.cpu_count()}
 
 
+def profile_kernel(args):
+    """One kernel family in isolation, for rocprofv3 (kernel trace or counters)."""
+    import torch
+    from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
+    from workload import WORKLOADS, make_actions, make_actor_weights, make_market, pack_actor_weights
+    dev = torch.device("cuda:0")
+    if args.kernel == "copy":
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(max(1, args.steps)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel": "copy", "bytes_read": nbytes, "bytes_written": nbytes}), flush=True)
+        return
+    w = WORKLOADS[args.workload]
+    cfg, acfg = w.env, w.actors
+    N, D, T, S, H, K = cfg.n_envs, cfg.n_stocks, cfg.n_days, cfg.state_dim, acfg.hidden, acfg.n_actors
+    m = make_market(w.market_seed, D, T)
+    env = VecEnv(cfg, m.close, m.ind, device=dev)
+    kw = {}
+    if args.kernel == "driven":
+        kw = dict(actions=torch.from_numpy(make_actions(5, T, N, D)).to(dev), store=("obs", "rew", "qty"))
+    else:
+        dtype = "bf16" if args.kernel == "fused" else "f32"
+        ens = Ensemble(pack_actor_weights(make_actor_weights(acfg)), K, S, H, D, dtype=dtype, max_batch=N,
+                       device=dev)
+        kw = dict(ens=ens, sigma=w.sigma, noise_key=w.noise_key, path="fused" if args.kernel == "fused" else "plain",
+                  store=("obs", "act", "rew"))
+    tot, ker, _, _ = time_rollouts(env, T, max(1, args.steps), 1, torch.cuda.current_stream(), **kw)
+    print(json.dumps({"kernel": args.kernel, "workload": w.name, "rollout_ms": tot, "kernel_ms": ker,
+                      "flop_per_env_step": mlp_flops_per_env_step(S, H, D, K),
+                      "bytes_per_env_step": env_bytes_per_env_step(D, S), "env_steps": N * T}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +142,8 @@ def main():
     ap.add_argument("--workload", default="paper", choices=["paper", "precision"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=None, help="timed rollouts of the plain float32 path")
+    ap.add_argument("--kernel", choices=["fused", "driven", "plain", "copy"], default=None,
+                    help="profiling mode: one warm-up and --steps launches of one kernel, nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the rollout shards by environment "
@@ -118,6 +155,9 @@ def main():
     from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
     from workload import WORKLOADS, make_actor_weights, make_market, pack_actor_weights
 
+    if args.kernel is not None:
+        profile_kernel(args)
+        return
     w = WORKLOADS[args.workload]
     cfg, acfg = w.env, w.actors
     N, D, T, S, H, K = cfg.n_envs, cfg.n_stocks, cfg.n_days, cfg.state_dim, acfg.hidden, acfg.n_actors

@@ -58,19 +58,27 @@ __device__ __forceinline__ float market_entry(const EnvConst& C, int t, int tn, 
   return C.ind[static_cast<size_t>(tn) * C.I * D + (i - 2 * D)];
 }
 
+// Two wavefronts per workgroup.  Wavefront 0 fetches the next step's inputs into registers,
+// runs the trading chains and moves the fetched inputs into LDS; wavefront 1 writes the step's
+// results (states, quantities, rewards) from LDS to HBM.  Vector-memory completions are counted
+// in issue order, so a wavefront that both stores and loads would wait for its stores every time
+// it needs a loaded value; splitting the roles keeps the stores off the chain's critical path.
 template <int DMAX, int MODE>
-__global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st, StepArgs A) {
+__global__ __launch_bounds__(2 * kWave) void env_tile_kernel(EnvConst C, EnvState st, StepArgs A) {
   using TC = TileCfg<DMAX>;
   constexpr int ST = TC::kStride;
   __shared__ __align__(16) float s_act[TC::kMaxM * ST];   // actions of the tile [m][d], zero-padded
   __shared__ float s_env[TC::kMaxM * ST];                 // per-env state entries [cash, h_0..]
   __shared__ int s_qty[TC::kMaxM * ST];
+  __shared__ double s_rew[TC::kMaxM];
   __shared__ __align__(16) float s_px[DMAX];              // close of the trading day, zero-padded
   __shared__ __align__(16) float s_pn[DMAX];              // close of the new day, zero-padded
-  __shared__ float s_mkt[(1 + TC::kMaxI) * DMAX];         // scaled new close + new indicators
+  __shared__ float s_mkt[2][(1 + TC::kMaxI) * DMAX];      // scaled new close + new indicators,
+                                                          // double-buffered by step parity
   __shared__ float s_eps[TC::kMaxM * ST];
 
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool loader = threadIdx.x < kWave;                // wavefront 0
   const int D = C.D, S = C.S, N = C.N;
   const int n0 = blockIdx.x * A.M;
   const int M = min(A.M, N - n0);
@@ -79,13 +87,13 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
   const int n_mkt = (2 + C.I) * D;
 
   // Zero the padding once: columns >= D of the action rows and of the price rows.
-  for (int i = lane; i < TC::kMaxM * ST; i += kWave) s_act[i] = 0.0f;
-  for (int i = lane; i < DMAX; i += kWave) {
+  for (int i = threadIdx.x; i < TC::kMaxM * ST; i += 2 * kWave) s_act[i] = 0.0f;
+  for (int i = threadIdx.x; i < DMAX; i += 2 * kWave) {
     s_px[i] = 0.0f;
     s_pn[i] = 0.0f;
   }
 
-  // Per-lane plan for writing a state row: slot j covers entry f = lane + 64 j.
+  // Store-wave plan for a state row: slot j covers entry f = lane + 64 j.
   // kind 0: shared market entry, 1: per-env entry s_env[idx], 2: none.
   int kind[TC::kSlots], eidx[TC::kSlots];
 #pragma unroll
@@ -109,10 +117,10 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
     }
   }
 
-  // The tile's trading state, in the registers of lanes 0..M-1.
+  // The tile's trading state, in the registers of wavefront 0's lanes 0..M-1.
   double cash = 0.0, asset = 0.0, cumrew = 0.0;
   int h[DMAX], x[DMAX];
-  const bool active = lane < M;
+  const bool active = loader && lane < M;
   const int n = n0 + lane;
 #pragma unroll
   for (int d = 0; d < DMAX; ++d) {
@@ -131,7 +139,7 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
   }
 
   const int n_iter = trades(MODE) ? A.n_steps : 1;
-  // Inputs of step it are fetched into registers one step ahead, then moved to LDS.
+  // Inputs of step it are fetched into wavefront 0's registers one step ahead, then moved to LDS.
   float pa[TC::kActRegs], pm[TC::kMktRegs];
   auto fetch = [&](int it) {
     const int t = A.t0 + it;
@@ -150,7 +158,8 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
       }
     }
   };
-  auto commit = [&]() {
+  auto commit = [&](int it) {
+    float* mkt = s_mkt[it & 1];
 #pragma unroll
     for (int j = 0; j < TC::kMktRegs; ++j) {
       const int i = lane + kWave * j;
@@ -158,9 +167,9 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
         s_px[i] = pm[j];
       } else if (i < 2 * D) {
         s_pn[i - D] = pm[j];
-        s_mkt[i - D] = pm[j] * C.price_scale;
+        mkt[i - D] = pm[j] * C.price_scale;
       } else if (i < n_mkt) {
-        s_mkt[i - D] = pm[j];
+        mkt[i - D] = pm[j];
       }
     }
     if (MODE == kGiven) {
@@ -175,104 +184,115 @@ __global__ __launch_bounds__(kWave) void env_tile_kernel(EnvConst C, EnvState st
     }
   };
 
-  fetch(0);
-  __syncthreads();
-  commit();
+  if (loader) {
+    fetch(0);
+    commit(0);
+  }
   __syncthreads();
 
   for (int it = 0; it < n_iter; ++it) {
     const int t = A.t0 + it;
-    if (it + 1 < n_iter) fetch(it + 1);
+    if (loader) {
+      if (it + 1 < n_iter) fetch(it + 1);
 
-    if (MODE == kEnsemble) {
-      // Noise: one Philox block per (env, group of 4 stocks).
-      const int G = (D + 3) >> 2;
-      const float inv_g = 1.0f / static_cast<float>(G);
-      if (A.sigma != 0.0f) {
-        for (int i = lane; i < M * G; i += kWave) {
-          const int m = div_small(i, inv_g);
-          const int g = i - m * G;
-          float z[4];
-          noise_block(A.noise_key, static_cast<uint64_t>(A.env_offset + n0 + m),
-                      static_cast<uint64_t>(t), static_cast<uint64_t>(g), z);
+      if (MODE == kEnsemble) {
+        // Noise: one Philox block per (env, group of 4 stocks).
+        const int G = (D + 3) >> 2;
+        const float inv_g = 1.0f / static_cast<float>(G);
+        if (A.sigma != 0.0f) {
+          for (int i = lane; i < M * G; i += kWave) {
+            const int m = div_small(i, inv_g);
+            const int g = i - m * G;
+            float z[4];
+            noise_block(A.noise_key, static_cast<uint64_t>(A.env_offset + n0 + m),
+                        static_cast<uint64_t>(t), static_cast<uint64_t>(g), z);
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (4 * g + r < D) s_eps[m * ST + 4 * g + r] = z[r];
+            for (int r = 0; r < 4; ++r)
+              if (4 * g + r < D) s_eps[m * ST + 4 * g + r] = z[r];
+          }
+        }
+        for (int i = lane; i < MD; i += kWave) {
+          const int m = div_small(i, inv_d);
+          const int d = i - m * D;
+          float acc = 0.0f;
+          for (int k = 0; k < A.K; ++k)
+            acc = acc + A.mix[k] * A.mu[(static_cast<size_t>(k) * N + n0) * D + i];
+          float a = acc;
+          if (A.sigma != 0.0f) a = acc + A.sigma * s_eps[m * ST + d];
+          a = fminf(fmaxf(a, -1.0f), 1.0f);
+          s_act[m * ST + d] = a;
         }
       }
-      __syncthreads();
-      for (int i = lane; i < MD; i += kWave) {
-        const int m = div_small(i, inv_d);
-        const int d = i - m * D;
-        float acc = 0.0f;
-        for (int k = 0; k < A.K; ++k)
-          acc = acc + A.mix[k] * A.mu[(static_cast<size_t>(k) * N + n0) * D + i];
-        float a = acc;
-        if (A.sigma != 0.0f) a = acc + A.sigma * s_eps[m * ST + d];
-        a = fminf(fmaxf(a, -1.0f), 1.0f);
-        s_act[m * ST + d] = a;
-        if (A.act_out) A.act_out[(static_cast<size_t>(it) * N + n0) * D + i] = a;
-      }
-      __syncthreads();
-    }
 
-    double r = 0.0;
-    if (active) {
-      if (trades(MODE)) {
-        float a[DMAX], px[DMAX];
-        lds_row<DMAX>(a, &s_act[lane * ST]);
-        lds_row<DMAX>(px, s_px);
-        trade<DMAX>(cash, h, x, a, px, C.hmax_f, C.one_m, C.one_p);
-        float pn[DMAX];
-        lds_row<DMAX>(pn, s_pn);
-        const double v_new = portfolio_value<DMAX>(cash, h, pn);
-        r = (v_new - asset) * C.reward_scale;
-        cumrew = cumrew + r;
-        asset = v_new;
-      } else if (MODE == kReset) {
-        float pn[DMAX];
-        lds_row<DMAX>(pn, s_pn);
-        asset = portfolio_value<DMAX>(cash, h, pn);
-      }
-      s_env[lane * ST] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
-#pragma unroll
-      for (int d = 0; d < DMAX; ++d)
-        if (d < D) {
-          s_env[lane * ST + 1 + d] = static_cast<float>(h[d]) * C.hold_scale;
-          s_qty[lane * ST + d] = x[d];
+      if (active) {
+        if (trades(MODE)) {
+          float a[DMAX], px[DMAX];
+          lds_row<DMAX>(a, &s_act[lane * ST]);
+          lds_row<DMAX>(px, s_px);
+          trade<DMAX>(cash, h, x, a, px, C.hmax_f, C.one_m, C.one_p);
+          float pn[DMAX];
+          lds_row<DMAX>(pn, s_pn);
+          const double v_new = portfolio_value<DMAX>(cash, h, pn);
+          const double r = (v_new - asset) * C.reward_scale;
+          cumrew = cumrew + r;
+          asset = v_new;
+          s_rew[lane] = r;
+        } else if (MODE == kReset) {
+          float pn[DMAX];
+          lds_row<DMAX>(pn, s_pn);
+          asset = portfolio_value<DMAX>(cash, h, pn);
         }
+        s_env[lane * ST] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d)
+          if (d < D) {
+            s_env[lane * ST + 1 + d] = static_cast<float>(h[d]) * C.hold_scale;
+            s_qty[lane * ST + d] = x[d];
+          }
+      }
     }
     __syncthreads();
 
-    if (A.rew && trades(MODE) && active) A.rew[static_cast<size_t>(it) * N + n] = r;
-    if (A.qty && trades(MODE)) {
-      int* dst = A.qty + (static_cast<size_t>(it) * N + n0) * D;
-      for (int i = lane; i < MD; i += kWave) {
-        const int m = div_small(i, inv_d);
-        dst[i] = s_qty[m * ST + (i - m * D)];
-      }
-    }
-    // States s_{t+1}: shared entries cached per slot, per-env entries from LDS.
-    if (A.obs) {
-      float* dst = A.obs + (static_cast<size_t>(it) * N + n0) * S;
-      float mval[TC::kSlots];
-#pragma unroll
-      for (int j = 0; j < TC::kSlots; ++j) mval[j] = (kind[j] == 0) ? s_mkt[eidx[j]] : 0.0f;
-      for (int m = 0; m < M; ++m) {
-#pragma unroll
-        for (int j = 0; j < TC::kSlots; ++j) {
-          if (kind[j] != 2) {
-            const float v = (kind[j] == 0) ? mval[j] : s_env[m * ST + eidx[j]];
-            dst[static_cast<size_t>(m) * S + lane + kWave * j] = v;
+    if (!loader) {
+      // Results of step it.
+      if (trades(MODE)) {
+        if (A.rew && lane < M) A.rew[static_cast<size_t>(it) * N + n0 + lane] = s_rew[lane];
+        if (MODE == kEnsemble && A.act_out) {  // single-step mode: s_act is not refilled
+          float* dst = A.act_out + (static_cast<size_t>(it) * N + n0) * D;
+          for (int i = lane; i < MD; i += kWave) {
+            const int m = div_small(i, inv_d);
+            dst[i] = s_act[m * ST + (i - m * D)];
+          }
+        }
+        if (A.qty) {
+          int* dst = A.qty + (static_cast<size_t>(it) * N + n0) * D;
+          for (int i = lane; i < MD; i += kWave) {
+            const int m = div_small(i, inv_d);
+            dst[i] = s_qty[m * ST + (i - m * D)];
           }
         }
       }
+      // States s_{t+1}: shared entries cached per slot, per-env entries from LDS.
+      if (A.obs) {
+        const float* mkt = s_mkt[it & 1];
+        float* dst = A.obs + (static_cast<size_t>(it) * N + n0) * S;
+        float mval[TC::kSlots];
+#pragma unroll
+        for (int j = 0; j < TC::kSlots; ++j) mval[j] = (kind[j] == 0) ? mkt[eidx[j]] : 0.0f;
+        for (int m = 0; m < M; ++m) {
+#pragma unroll
+          for (int j = 0; j < TC::kSlots; ++j) {
+            if (kind[j] != 2) {
+              const float v = (kind[j] == 0) ? mval[j] : s_env[m * ST + eidx[j]];
+              dst[static_cast<size_t>(m) * S + lane + kWave * j] = v;
+            }
+          }
+        }
+      }
+    } else if (it + 1 < n_iter) {
+      commit(it + 1);  // s_act, s_px, s_pn are free (the chain has read them); s_mkt is the other buffer
     }
     __syncthreads();
-    if (it + 1 < n_iter) {
-      commit();
-      __syncthreads();
-    }
   }
 
   // Store the state back.
@@ -290,7 +310,7 @@ template <int DMAX, int MODE>
 hipError_t launch_tile(const EnvConst& C, const EnvState& st, StepArgs A, hipStream_t stream) {
   A.M = min(A.M, TileCfg<DMAX>::kMaxM);
   const int grid = (C.N + A.M - 1) / A.M;
-  hipLaunchKernelGGL((env_tile_kernel<DMAX, MODE>), dim3(grid), dim3(kWave), 0, stream, C, st,
+  hipLaunchKernelGGL((env_tile_kernel<DMAX, MODE>), dim3(grid), dim3(2 * kWave), 0, stream, C, st,
                      A);
   return hipGetLastError();
 }

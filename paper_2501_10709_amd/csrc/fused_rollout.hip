@@ -213,6 +213,9 @@ struct Streamed {
   static constexpr int K = 3, KK2 = 8, HT = 16, AT = 2, NW = NWAVES, TW = HT / NWAVES;
   static constexpr int SPA = KK1 + 2 * KK2;  // k-steps per actor
   static constexpr int NS = K * SPA;         // k-steps per environment step
+  // The schedule walks NSP >= NS positions per step, a multiple of DEPTH, so that k-step j always
+  // uses ring slot j % DEPTH, also across the wrap into the next step; positions >= NS are idle.
+  static constexpr int NSP = (NS + DEPTH - 1) / DEPTH * DEPTH;
 
   // Packed-ensemble layout of this shape (bytes; checked against the workspace on the host).
   static constexpr size_t kW1 = 0, kW2 = 32 * KK1 * 256 * 2, kW3 = kW2 + 256 * 256 * 2;
@@ -222,6 +225,7 @@ struct Streamed {
   // Weight fragments of k-step S2 for wavefront wv (uniform); voff = lane * 16.
   template <int S2>
   static __device__ __forceinline__ void load(bf16x8 (&b)[TW], const unsigned char* wb, int wv, int voff) {
+    if constexpr (S2 >= NS) return;  // idle position
     constexpr int actor = S2 / SPA, r = S2 % SPA;
     const unsigned char* P = wb + kActor * actor;
     if constexpr (r < KK1) {
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(64 * NWAVES) void fused_streamed_kernel(EnvConst C,
                                                                      FusedArgs F) {
   using SP = Streamed<KK1, ROWT, DEPTH, NWAVES>;
   constexpr int NT = 64 * NWAVES, MR = 16 * ROWT, TW = SP::TW, NW = SP::NW;
-  constexpr int KK2 = SP::KK2, SPA = SP::SPA, NS = SP::NS;
+  constexpr int KK2 = SP::KK2, SPA = SP::SPA, NS = SP::NS, NSP = SP::NSP;
   constexpr int S_PAD = 32 * KK1, H = 256;
   constexpr int ST0 = S_PAD + 8, STH = H + 8;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -307,17 +311,24 @@ __global__ __launch_bounds__(64 * NWAVES) void fused_streamed_kernel(EnvConst C,
     const size_t row_base = static_cast<size_t>(it) * N + n0;
     __syncthreads();                       // x0 complete; LDS market rows free
     P.stage_market(t + 1, true);
-    // The weight base is re-read as an opaque value every step, so that no fragment address is
-    // hoisted out of the step loop (there are hundreds of them).
-    const unsigned char* wb = E.base;
-    asm volatile("" : "+s"(wb));
+    // The weight base is offset by an opaque zero every step, so that no fragment address is
+    // hoisted out of the step loop (there are hundreds of them).  Laundering an integer rather
+    // than the pointer keeps the loads in the global address space (flat loads would also count
+    // against the LDS wait counter and stall every LDS read behind the whole weight pipeline).
+    int opaque_zero = 0;
+    asm volatile("" : "+s"(opaque_zero));
+    const unsigned char* wb = E.base + opaque_zero;
 
     floatx4 acc[ROWT][TW];
-    static_for<NS>([&](auto sc) __attribute__((always_inline)) {
+    static_for<NSP>([&](auto sc) __attribute__((always_inline)) {
       constexpr int s = decltype(sc)::value;
       // Keep the k-steps in program order: the scheduler would otherwise hoist every load of a
       // layer to its top and run out of registers.
       __builtin_amdgcn_sched_barrier(0);
+      if constexpr (s >= NS) {
+        SP::template load<(s + DEPTH) % NSP>(ring[s % DEPTH], wb, wv, voff);
+        return;
+      }
       constexpr int actor = s / SPA, r = s % SPA;
       constexpr int layer = r < KK1 ? 1 : (r < KK1 + KK2 ? 2 : 3);
       constexpr int kk = layer == 1 ? r : (layer == 2 ? r - KK1 : r - KK1 - KK2);
@@ -332,7 +343,7 @@ __global__ __launch_bounds__(64 * NWAVES) void fused_streamed_kernel(EnvConst C,
       bf16x8 cur[TW];
 #pragma unroll
       for (int i = 0; i < TW; ++i) cur[i] = ring[s % DEPTH][i];
-      SP::template load<(s + DEPTH) % NS>(ring[s % DEPTH], wb, wv, voff);
+      SP::template load<(s + DEPTH) % NSP>(ring[s % DEPTH], wb, wv, voff);
 
       const __bf16* src = layer == 1 ? L.x0 : (layer == 2 ? L.x1 : L.x2);
       constexpr int ist = layer == 1 ? ST0 : STH;

@@ -75,11 +75,13 @@ __device__ __forceinline__ floatx4 mfma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
 
 // One layer for the wavefront's column tiles c = wave, wave+4, ... (< ntiles).  sin: LDS tile
 // [16][in_stride] holding kin_pad valid (zero-padded) columns.  Calls epi(i, c, acc) for every
-// tile the wave owns.
+// tile the wave owns.  The B-operand fragments of the next RING k-steps are in flight while the
+// current k-step's MFMAs run.
 template <int DT, int TMAX, class Epi>
 __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int in_stride,
                                           int kin_pad, const void* wp, int ntiles, int wave,
                                           int lane, Epi epi) {
+  constexpr int RING = 4;
   floatx4 acc[TMAX];
 #pragma unroll
   for (int i = 0; i < TMAX; ++i) acc[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -87,33 +89,66 @@ __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int
   if constexpr (DT == kF32) {
     const float4* W = static_cast<const float4*>(wp);
     const int KQ = kin_pad / 16;
-    for (int kq = 0; kq < KQ; ++kq) {
-      float a[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) a[e] = sin[row * in_stride + 16 * kq + 4 * e + grp];
+    float4 ring[RING][TMAX];
+    auto fetch = [&](float4 (&dst)[TMAX], int kq) {
 #pragma unroll
       for (int i = 0; i < TMAX; ++i) {
         const int c = wave + 4 * i;
-        if (c < ntiles) {
-          const float4 b = W[(static_cast<size_t>(c) * KQ + kq) * 64 + lane];
-          acc[i] = mfma_f32(a[0], b.x, acc[i]);
-          acc[i] = mfma_f32(a[1], b.y, acc[i]);
-          acc[i] = mfma_f32(a[2], b.z, acc[i]);
-          acc[i] = mfma_f32(a[3], b.w, acc[i]);
+        if (c < ntiles && kq < KQ) dst[i] = W[(static_cast<size_t>(c) * KQ + kq) * 64 + lane];
+      }
+    };
+#pragma unroll
+    for (int j = 0; j < RING; ++j) fetch(ring[j], j);
+    for (int kq0 = 0; kq0 < KQ; kq0 += RING) {
+#pragma unroll
+      for (int j = 0; j < RING; ++j) {
+        const int kq = kq0 + j;
+        if (kq < KQ) {
+          float4 b[TMAX];
+#pragma unroll
+          for (int i = 0; i < TMAX; ++i) b[i] = ring[j][i];
+          fetch(ring[j], kq + RING);
+          float a[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) a[e] = sin[row * in_stride + 16 * kq + 4 * e + grp];
+#pragma unroll
+          for (int i = 0; i < TMAX; ++i) {
+            if (wave + 4 * i < ntiles) {
+              acc[i] = mfma_f32(a[0], b[i].x, acc[i]);
+              acc[i] = mfma_f32(a[1], b[i].y, acc[i]);
+              acc[i] = mfma_f32(a[2], b[i].z, acc[i]);
+              acc[i] = mfma_f32(a[3], b[i].w, acc[i]);
+            }
+          }
         }
       }
     }
   } else {
     const bf16x8* W = static_cast<const bf16x8*>(wp);
     const int KK = kin_pad / 32;
-    for (int kk = 0; kk < KK; ++kk) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(sin + row * in_stride + 32 * kk + 8 * grp);
+    bf16x8 ring[RING][TMAX];
+    auto fetch = [&](bf16x8 (&dst)[TMAX], int kk) {
 #pragma unroll
       for (int i = 0; i < TMAX; ++i) {
         const int c = wave + 4 * i;
-        if (c < ntiles) {
-          const bf16x8 b = W[(static_cast<size_t>(c) * KK + kk) * 64 + lane];
-          acc[i] = mfma_bf16(a, b, acc[i]);
+        if (c < ntiles && kk < KK) dst[i] = W[(static_cast<size_t>(c) * KK + kk) * 64 + lane];
+      }
+    };
+#pragma unroll
+    for (int j = 0; j < RING; ++j) fetch(ring[j], j);
+    for (int kk0 = 0; kk0 < KK; kk0 += RING) {
+#pragma unroll
+      for (int j = 0; j < RING; ++j) {
+        const int kk = kk0 + j;
+        if (kk < KK) {
+          bf16x8 b[TMAX];
+#pragma unroll
+          for (int i = 0; i < TMAX; ++i) b[i] = ring[j][i];
+          fetch(ring[j], kk + RING);
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(sin + row * in_stride + 32 * kk + 8 * grp);
+#pragma unroll
+          for (int i = 0; i < TMAX; ++i)
+            if (wave + 4 * i < ntiles) acc[i] = mfma_bf16(a, b[i], acc[i]);
         }
       }
     }
