@@ -163,6 +163,30 @@ fm_status ensemble_act(const fm_ensemble* ens, const float* d_obs, int32_t n, fl
 void ensemble_destroy(fm_ensemble* ens);
 
 /* ---------------------------------------------------------------------------------------------
+ * Evaluation (Section 6.1 metrics; Section 5.2.1 ensemble weights)
+ * ------------------------------------------------------------------------------------------- */
+
+/* Backtest metrics of every environment from its reward trajectory d_rew [n_steps][n_envs]
+ * (float64, as env_rollout stores it).  The equity curve is v_0 = d_init_asset[n] (or init_asset
+ * when d_init_asset is NULL), v_{t+1} = v_t + r_t / reward_scale, with period returns
+ * rho_t = v_{t+1}/v_t - 1.  Writes d_out [n_envs][10] float64:
+ *   0 cumulative return v_T/v_0 - 1        5 RoMaD = cumulative return / |max drawdown|
+ *   1 annual return (v_T/v_0)^(P/T) - 1    6 Sortino = (mean rho - rf/P) / downside dev * sqrt(P)
+ *   2 annual volatility sd(rho) * sqrt(P)  7 Calmar = annual return / |max drawdown|
+ *   3 Sharpe (eq. 6) annualised by sqrt(P) 8 Omega = sum max(rho,0) / sum max(-rho,0)
+ *   4 max drawdown min_t v_t/peak_t - 1    9 win/loss = #(rho>0) / #(rho<0)
+ * sd is the sample (n-1) deviation, the downside deviation is sqrt(mean(min(rho - rf/P, 0)^2)),
+ * P = periods_per_year, rf = risk_free (annual); a zero denominator gives inf or NaN. */
+fm_status fm_backtest_metrics(const double* d_rew, int32_t n_steps, int32_t n_envs, double init_asset,
+                              const double* d_init_asset, double reward_scale, double periods_per_year,
+                              double risk_free, double* d_out, hipStream_t stream);
+
+/* Ensemble weights from validation Sharpe ratios (Section 5.2.1): agents below min_sharpe get 0,
+ * the others a softmax of their Sharpe ratios; if every agent is below, the best gets 1.
+ * Host only; h_mix [n_actors] can be passed to ensemble_create. */
+fm_status fm_sharpe_weights(const double* h_sharpe, int32_t n_actors, double min_sharpe, float* h_mix);
+
+/* ---------------------------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------------------------- */
 

@@ -21,7 +21,8 @@ FM_PATH_PLAIN, FM_PATH_FUSED = 0, 1
 EXPORTS = (
     "env_workspace_bytes", "env_create", "env_reset", "env_step", "env_rollout", "env_read_state",
     "env_write_state", "env_day", "env_destroy", "ensemble_workspace_bytes", "ensemble_create",
-    "ensemble_act", "ensemble_destroy", "fm_last_error", "fm_noise", "fm_version",
+    "ensemble_act", "ensemble_destroy", "fm_last_error", "fm_noise", "fm_version", "fm_backtest_metrics",
+    "fm_sharpe_weights",
 )
 
 
@@ -80,6 +81,9 @@ def load(path: str = LIB_PATH):
         "fm_last_error": (ctypes.c_char_p, []),
         "fm_noise": (I32, [U64, I64, I32, I32, I32, P, P, P]),
         "fm_version": (ctypes.c_char_p, []),
+        "fm_backtest_metrics": (I32, [P, I32, I32, ctypes.c_double, P, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, P, P]),
+        "fm_sharpe_weights": (I32, [P, I32, ctypes.c_double, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -223,6 +227,33 @@ def fm_noise(noise_key, env_offset, n, t, n_stocks, d_eps, d_words=None, stream=
     _check(load().fm_noise(int(noise_key), int(env_offset), int(n), int(t), int(n_stocks),
                            _ptr(d_words, torch.int64, name="words"), _ptr(d_eps, torch.float32, name="eps"),
                            _stream(stream)))
+
+
+METRICS = ("cumulative_return", "annual_return", "annual_volatility", "sharpe", "max_drawdown", "romad",
+           "sortino", "calmar", "omega", "win_loss")
+
+
+def fm_backtest_metrics(d_rew, init_asset, reward_scale, periods_per_year=252.0, risk_free=0.0, d_init_asset=None,
+                        d_out=None, stream=None):
+    """Metrics [N][10] (order of METRICS) from rewards [T][N] float64 on the device."""
+    import torch
+    T, N = d_rew.shape
+    if d_out is None:
+        d_out = torch.empty((N, len(METRICS)), dtype=torch.float64, device=d_rew.device)
+    _check(load().fm_backtest_metrics(_ptr(d_rew, torch.float64, name="rew"), int(T), int(N), float(init_asset),
+                                      _ptr(d_init_asset, torch.float64, N, name="init_asset"), float(reward_scale),
+                                      float(periods_per_year), float(risk_free),
+                                      _ptr(d_out, torch.float64, N * len(METRICS), name="out"), _stream(stream)))
+    return d_out
+
+
+def fm_sharpe_weights(sharpe, min_sharpe=float("-inf")):
+    """Softmax-of-Sharpe ensemble weights (host)."""
+    K = len(sharpe)
+    s = (ctypes.c_double * K)(*[float(x) for x in sharpe])
+    w = (ctypes.c_float * K)()
+    _check(load().fm_sharpe_weights(s, K, float(min_sharpe), w))
+    return [float(x) for x in w]
 
 
 def fm_last_error() -> str:

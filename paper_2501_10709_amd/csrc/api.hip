@@ -439,6 +439,47 @@ fm_status ensemble_act(const fm_ensemble* ens, const float* d_obs, int32_t n, fl
 
 void ensemble_destroy(fm_ensemble* ens) { delete ens; }
 
+fm_status fm_backtest_metrics(const double* d_rew, int32_t n_steps, int32_t n_envs, double init_asset,
+                              const double* d_init_asset, double reward_scale, double periods_per_year,
+                              double risk_free, double* d_out, hipStream_t stream) {
+  if (!d_rew || !d_out) return fail(FM_ERR_INVALID, "d_rew and d_out are required");
+  if (n_steps < 1 || n_envs < 0) return fail(FM_ERR_INVALID, "n_steps must be >= 1 and n_envs >= 0");
+  if (!(reward_scale != 0.0) || !std::isfinite(reward_scale)) return fail(FM_ERR_INVALID, "reward_scale must be finite and nonzero");
+  if (!(periods_per_year > 0.0) || !std::isfinite(periods_per_year)) return fail(FM_ERR_INVALID, "periods_per_year must be > 0");
+  if (!std::isfinite(risk_free) || !std::isfinite(init_asset)) return fail(FM_ERR_INVALID, "risk_free and init_asset must be finite");
+  if (n_envs == 0) return FM_OK;
+  return device_status(fm::launch_metrics(d_rew, n_steps, n_envs, init_asset, d_init_asset, reward_scale,
+                                          periods_per_year, risk_free, d_out, stream),
+                       "fm_backtest_metrics");
+}
+
+fm_status fm_sharpe_weights(const double* h_sharpe, int32_t n_actors, double min_sharpe, float* h_mix) {
+  if (!h_sharpe || !h_mix) return fail(FM_ERR_INVALID, "h_sharpe and h_mix are required");
+  if (n_actors < 1 || n_actors > 8) return fail(FM_ERR_INVALID, "n_actors must be in 1..8");
+  int best = 0;
+  double top = -INFINITY;
+  bool any = false;
+  for (int k = 0; k < n_actors; ++k) {
+    if (std::isnan(h_sharpe[k])) return fail(FM_ERR_INVALID, "Sharpe ratios must not be NaN");
+    if (h_sharpe[k] > h_sharpe[best]) best = k;
+    if (h_sharpe[k] >= min_sharpe) {
+      any = true;
+      top = std::fmax(top, h_sharpe[k]);
+    }
+  }
+  if (!any) {
+    for (int k = 0; k < n_actors; ++k) h_mix[k] = k == best ? 1.0f : 0.0f;
+    return FM_OK;
+  }
+  double e[8], total = 0.0;
+  for (int k = 0; k < n_actors; ++k) {
+    e[k] = h_sharpe[k] >= min_sharpe ? std::exp(h_sharpe[k] - top) : 0.0;
+    total += e[k];
+  }
+  for (int k = 0; k < n_actors; ++k) h_mix[k] = static_cast<float>(e[k] / total);
+  return FM_OK;
+}
+
 fm_status fm_noise(uint64_t noise_key, int64_t env_offset, int32_t n, int32_t t, int32_t n_stocks,
                    uint64_t* d_words, float* d_eps, hipStream_t stream) {
   if (!d_eps) return fail(FM_ERR_INVALID, "d_eps is NULL");

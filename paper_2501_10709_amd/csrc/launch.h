@@ -41,4 +41,9 @@ hipError_t launch_combine(int K, int n, int A, const float* mu, const float* mix
                           uint64_t key, int t, int64_t env_offset, float* mean, float* act,
                           hipStream_t stream);
 
+// Backtest metrics (metrics_kernels.hip).
+hipError_t launch_metrics(const double* rew, int T, int N, double v0, const double* v0s,
+                          double reward_scale, double periods_per_year, double risk_free,
+                          double* out, hipStream_t stream);
+
 }  // namespace fm

@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2501_10709_amd import binding as B
@@ -90,3 +92,14 @@ def test_invalid_arguments_return_error_without_device(lib):
                                None, ctypes.byref(e)) == B.FM_ERR_INVALID
     assert "hidden" in B.fm_last_error()
     assert lib.fm_noise(7, 0, 4, 0, 30, None, None, None) == B.FM_ERR_INVALID
+
+
+def test_sharpe_weights_match_oracle():
+    from oracle.metrics import sharpe_softmax_weights
+    for s, cut in (([0.7, 0.7, 0.7], float("-inf")), ([1.0, 2.0, 0.5], float("-inf")), ([1.0, -0.5, 2.0], 0.0),
+                   ([-1.0, -0.2, -3.0], 0.0), ([3.0], 0.0), ([0.1, 0.4, 0.2, 0.9, -2.0], 0.15)):
+        got = np.array(B.fm_sharpe_weights(s, cut))
+        want = sharpe_softmax_weights(s, cut)
+        assert np.allclose(got, want, rtol=1e-6, atol=1e-7), (s, got, want)
+    with pytest.raises(B.FmError):
+        B.fm_sharpe_weights([float("nan"), 1.0])
