@@ -62,6 +62,10 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build the HIP library first "
                            "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch ships its own HIP runtime under the same soname; importing it first makes the library
+    # bind to that runtime, so the process holds one runtime and torch's pointers and streams are
+    # valid in the library's calls.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, I32, I64, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
     sig = {

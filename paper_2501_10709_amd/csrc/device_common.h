@@ -183,4 +183,156 @@ __device__ __forceinline__ int div_small(int i, float inv_d) {
   return static_cast<int>((static_cast<float>(i) + 0.5f) * inv_d);
 }
 
+// Writes the values val(e), e = 0..total-1, to dst[0..total-1] with one wavefront (lane =
+// 0..63): 16-byte stores for the 16-byte-aligned body, single stores for the unaligned head and
+// the tail.  val is evaluated for every element exactly once.
+template <class T, class Val>
+__device__ __forceinline__ void wave_store_row(T* dst, int total, int lane, Val val) {
+  static_assert(sizeof(T) == 4, "four-byte elements");
+  const int head = min(total, static_cast<int>(((16 - (reinterpret_cast<uintptr_t>(dst) & 15)) & 15) / 4));
+  if (lane < head) dst[lane] = val(lane);
+  const int nvec = (total - head) / 4;
+  T* body = dst + head;
+#pragma unroll 2
+  for (int q = lane; q < nvec; q += 64) {
+    const int e = head + 4 * q;
+    T v0 = val(e), v1 = val(e + 1), v2 = val(e + 2), v3 = val(e + 3);
+    typedef __attribute__((ext_vector_type(4))) T T4;
+    T4 v;
+    v.x = v0;
+    v.y = v1;
+    v.z = v2;
+    v.w = v3;
+    *reinterpret_cast<T4*>(body + 4 * q) = v;
+  }
+  const int done = head + 4 * nvec;
+  if (done + lane < total) dst[done + lane] = val(done + lane);
+}
+
+// ------------------------------------------------------------------------------------------
+// The chain of a tile of M environments, split so that only the cash recurrence is serial.
+// Every per-stock quantity that does not depend on cash (orders, the sale size, proceeds, the
+// debit of the whole order, the new day's position values) is computed by all threads of the
+// group over the M*D (env, stock) pairs; one lane per environment then runs the float64 cash
+// recurrence in ascending stock order, reading the precomputed terms.  The arithmetic and its
+// order are exactly those of trade() / portfolio_value().
+//
+// LDS rows (stride DS = D + 1 for per-env rows, D for scratch):
+//   act[m][d] actions, hold[m][d] holdings (updated), qty[m][d] executed shares (written),
+//   env[m][0..D] state entries (written: cash * scale, holdings * scale)
+//   pro[m][d], deb[m][d], val[m][d] float64 scratch; qd[m][d], kq[m][d] int scratch
+// ------------------------------------------------------------------------------------------
+struct ChainLds {
+  const float* act;
+  int* hold;
+  int* qty;
+  float* env;
+  const float* px;  // trading day closes [D]
+  const float* pn;  // new day closes [D]
+  double* pro;
+  double* deb;
+  double* val;
+  int* qd;
+  int* kq;
+};
+
+// Phase A (all threads, pairs i = first, first + stride, ...): orders, sells, whole-order debit.
+__device__ __forceinline__ void chain_pairs_a(const ChainLds& L, int M, int D, int first, int stride,
+                                              float inv_d, float hmax_f, double one_m, double one_p) {
+#pragma clang fp contract(off)
+  const int DS = D + 1;
+#pragma unroll 4
+  for (int i = first; i < M * D; i += stride) {
+    const int m = div_small(i, inv_d);
+    const int d = i - m * D;
+    const int q = order_from_action(L.act[m * DS + d], hmax_f);
+    const int h = L.hold[m * DS + d];
+    const int s = q < 0 ? min(h, -q) : 0;
+    const double p = static_cast<double>(L.px[d]);
+    L.hold[m * DS + d] = h - s;
+    L.qty[m * DS + d] = -s;
+    L.pro[i] = (p * static_cast<double>(s)) * one_m;
+    const int qd = q > 0 ? q : 0;
+    L.qd[i] = qd;
+    L.deb[i] = (p * static_cast<double>(qd)) * one_p;
+    L.val[i] = p * one_p;  // debit of one share, (p*1)*(1+c); the slot is reused in phase C
+  }
+}
+
+// Phase B (lane m of the owner group): the cash recurrence of environment m.  A buy that does not
+// fit is filled partially only when at least one share is affordable; that is the one rare,
+// divergent branch (the common cases are a whole fill or no fill, both branch-free selects).
+__device__ __forceinline__ void chain_serial(double& cash, const double* __restrict__ pro,
+                                             const double* __restrict__ deb, const double* __restrict__ c1s,
+                                             const int* __restrict__ qd, const float* __restrict__ px,
+                                             int* __restrict__ kq, int D, double one_p) {
+#pragma clang fp contract(off)
+#pragma unroll 8
+  for (int d = 0; d < D; ++d) cash = cash + pro[d];  // sells, ascending stock order
+#pragma unroll 4
+  for (int d = 0; d < D; ++d) {                       // buys, ascending stock order
+    const double debit_q = deb[d];
+    const double c1 = c1s[d];
+    const int q = qd[d];
+    const bool fits = debit_q <= cash;
+    int k = fits ? q : 0;
+    double debit = fits ? debit_q : 0.0;
+    if (!fits && c1 <= cash) {
+      const double p = static_cast<double>(px[d]);
+      k = partial_fill(cash, p, q, one_p);
+      debit = (p * static_cast<double>(k)) * one_p;
+    }
+    cash = cash - debit;
+    kq[d] = k;
+  }
+}
+
+// Phase C (all threads): apply the buys, state entries of the holdings, new-day position values.
+__device__ __forceinline__ void chain_pairs_c(const ChainLds& L, int M, int D, int first, int stride,
+                                              float inv_d, float hold_scale) {
+#pragma clang fp contract(off)
+  const int DS = D + 1;
+#pragma unroll 4
+  for (int i = first; i < M * D; i += stride) {
+    const int m = div_small(i, inv_d);
+    const int d = i - m * D;
+    const int k = L.kq[i];
+    const int h = L.hold[m * DS + d] + k;
+    L.hold[m * DS + d] = h;
+    L.qty[m * DS + d] += k;
+    L.env[m * DS + 1 + d] = static_cast<float>(h) * hold_scale;
+    L.val[i] = static_cast<double>(L.pn[d]) * static_cast<double>(h);
+  }
+}
+
+// Phase D (lane m): v = cash + sum_d p'_d h_d in ascending stock order.
+__device__ __forceinline__ double chain_value(double cash, const double* __restrict__ val, int D) {
+#pragma clang fp contract(off)
+  double acc = cash;
+#pragma unroll 8
+  for (int d = 0; d < D; ++d) acc = acc + val[d];
+  return acc;
+}
+
+// Holdings entries and values without trading (reset / observe): all threads.
+__device__ __forceinline__ void chain_pairs_hold(const ChainLds& L, int M, int D, int first, int stride,
+                                                 float inv_d, float hold_scale) {
+#pragma clang fp contract(off)
+  const int DS = D + 1;
+  for (int i = first; i < M * D; i += stride) {
+    const int m = div_small(i, inv_d);
+    const int d = i - m * D;
+    const int h = L.hold[m * DS + d];
+    L.env[m * DS + 1 + d] = static_cast<float>(h) * hold_scale;
+    L.val[i] = static_cast<double>(L.pn[d]) * static_cast<double>(h);
+  }
+}
+
+// Synchronisation of one wavefront's LDS traffic between the phases (no hardware barrier:
+// a wavefront's LDS operations complete in order; this stops the compiler reordering them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 }  // namespace fm

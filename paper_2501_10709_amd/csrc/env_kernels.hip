@@ -18,17 +18,7 @@ namespace fm {
 namespace {
 
 constexpr int kWave = 64;
-
-template <int DMAX>
-struct TileCfg {
-  static constexpr int kStride = DMAX + 4;                        // 16-byte rows for the chain
-  static constexpr int kMaxM = DMAX <= 32 ? 64 : (2048 / DMAX);   // envs per workgroup
-  static constexpr int kMaxI = 16;
-  static constexpr int kMaxS = (kMaxI + 2) * DMAX + 1;
-  static constexpr int kSlots = (kMaxS + kWave - 1) / kWave;      // state entries per lane
-  static constexpr int kActRegs = kMaxM * DMAX / kWave;           // prefetched actions per lane
-  static constexpr int kMktRegs = ((kMaxI + 2) * DMAX + kWave - 1) / kWave;
-};
+constexpr int kPrefetch = 8;  // registers per lane for the next step's inputs (512 values)
 
 enum Mode { kReset = 0, kGiven = 1, kEnsemble = 2, kObserve = 3 };
 constexpr bool trades(int mode) { return mode == kGiven || mode == kEnsemble; }
@@ -50,7 +40,7 @@ struct StepArgs {
   int* qty;            // [n_steps][N][D] or null
 };
 
-// Market entries of the step (it) in flat order: close[t] (D), close[t+1] (D), ind[t+1] (I*D).
+// Market entries of the step in flat order: close[t] (D), close[t+1] (D), ind[t+1] (I*D).
 __device__ __forceinline__ float market_entry(const EnvConst& C, int t, int tn, int i, bool with_trade) {
   const int D = C.D;
   if (i < D) return with_trade ? C.close[static_cast<size_t>(t) * D + i] : 0.0f;
@@ -58,143 +48,130 @@ __device__ __forceinline__ float market_entry(const EnvConst& C, int t, int tn, 
   return C.ind[static_cast<size_t>(tn) * C.I * D + (i - 2 * D)];
 }
 
-// Two wavefronts per workgroup.  Wavefront 0 fetches the next step's inputs into registers,
-// runs the trading chains and moves the fetched inputs into LDS; wavefront 1 writes the step's
-// results (states, quantities, rewards) from LDS to HBM.  Vector-memory completions are counted
-// in issue order, so a wavefront that both stores and loads would wait for its stores every time
-// it needs a loaded value; splitting the roles keeps the stores off the chain's critical path.
-template <int DMAX, int MODE>
-__global__ __launch_bounds__(2 * kWave) void env_tile_kernel(EnvConst C, EnvState st, StepArgs A) {
-  using TC = TileCfg<DMAX>;
-  constexpr int ST = TC::kStride;
-  __shared__ __align__(16) float s_act[TC::kMaxM * ST];   // actions of the tile [m][d], zero-padded
-  __shared__ float s_env[TC::kMaxM * ST];                 // per-env state entries [cash, h_0..]
-  __shared__ int s_qty[TC::kMaxM * ST];
-  __shared__ double s_rew[TC::kMaxM];
-  __shared__ __align__(16) float s_px[DMAX];              // close of the trading day, zero-padded
-  __shared__ __align__(16) float s_pn[DMAX];              // close of the new day, zero-padded
-  __shared__ float s_mkt[2][(1 + TC::kMaxI) * DMAX];      // scaled new close + new indicators,
-                                                          // double-buffered by step parity
-  __shared__ float s_eps[TC::kMaxM * ST];
+// LDS bytes of one workgroup of env_tile_kernel.
+__host__ __device__ inline size_t tile_lds_bytes(int M, int D, int I) {
+  const size_t DS = D + 1;
+  return sizeof(double) * M                // rewards
+         + sizeof(double) * M * D * 3      // chain scratch: proceeds, debits, position values
+         + sizeof(int) * M * D * 2         // chain scratch: whole orders, fills
+         + sizeof(float) * M * DS * 2      // actions, two buffers
+         + sizeof(float) * M * DS * 4      // hold, qty, env, eps
+         + sizeof(float) * 4 * D           // closes of the trading day and the new day, two buffers
+         + sizeof(float) * 2 * (1 + I) * D;  // new-day state entries, two buffers
+}
 
+// Three wavefronts per workgroup, one role each:
+//   wavefront 0 (chain): the trading chains of the tile's M environments (lane m owns
+//     environment m; holdings stay in LDS) -- LDS traffic only inside the step loop;
+//   wavefront 1 (store): the step's results (states, quantities, rewards) from LDS to HBM;
+//   wavefront 2 (fetch): the next step's inputs (actions, market rows) from HBM into the other
+//     half of double-buffered LDS.
+// Vector-memory completions are counted per wavefront in issue order, so a wavefront that mixed
+// these roles would wait for stores and prefetches whenever it needed any loaded value; with the
+// roles split, the chain never waits on HBM.  Loops over stocks stay rolled so that the whole
+// step fits the instruction cache.
+template <int MODE>
+__global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvState st, StepArgs A) {
+  extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & (kWave - 1);
-  const bool loader = threadIdx.x < kWave;                // wavefront 0
-  const int D = C.D, S = C.S, N = C.N;
+  const int role = threadIdx.x / kWave;  // 0 chain, 1 store, 2 fetch
+  const int D = C.D, S = C.S, N = C.N, DS = D + 1;
   const int n0 = blockIdx.x * A.M;
   const int M = min(A.M, N - n0);
   const float inv_d = 1.0f / static_cast<float>(D);
   const int MD = M * D;
   const int n_mkt = (2 + C.I) * D;
+  const int n_new = (1 + C.I) * D;  // scaled new close + new indicators
 
-  // Zero the padding once: columns >= D of the action rows and of the price rows.
-  for (int i = threadIdx.x; i < TC::kMaxM * ST; i += 2 * kWave) s_act[i] = 0.0f;
-  for (int i = threadIdx.x; i < DMAX; i += 2 * kWave) {
-    s_px[i] = 0.0f;
-    s_pn[i] = 0.0f;
-  }
+  double* s_rew = reinterpret_cast<double*>(smem);
+  double* s_pro = s_rew + A.M;
+  double* s_deb = s_pro + A.M * D;
+  double* s_val = s_deb + A.M * D;
+  int* s_qd = reinterpret_cast<int*>(s_val + A.M * D);
+  int* s_kq = s_qd + A.M * D;
+  float* s_act0 = reinterpret_cast<float*>(s_kq + A.M * D);  // two buffers of [M][DS]
+  int* s_hold = reinterpret_cast<int*>(s_act0 + 2 * A.M * DS);
+  int* s_qty = s_hold + A.M * DS;
+  float* s_env = reinterpret_cast<float*>(s_qty + A.M * DS);  // [cash, h_0..h_{D-1}] per env
+  float* s_eps = s_env + A.M * DS;
+  float* s_px0 = s_eps + A.M * DS;   // two buffers of [D]
+  float* s_pn0 = s_px0 + 2 * D;      // two buffers of [D]
+  float* s_mkt0 = s_pn0 + 2 * D;     // two buffers of [n_new]
 
-  // Store-wave plan for a state row: slot j covers entry f = lane + 64 j.
-  // kind 0: shared market entry, 1: per-env entry s_env[idx], 2: none.
-  int kind[TC::kSlots], eidx[TC::kSlots];
-#pragma unroll
-  for (int j = 0; j < TC::kSlots; ++j) {
-    const int f = lane + kWave * j;
-    kind[j] = 2;
-    eidx[j] = 0;
-    if (f < S) {
-      if (f == 0) {
-        kind[j] = 1;
-      } else if (f <= D) {
-        kind[j] = 0;
-        eidx[j] = f - 1;
-      } else if (f <= 2 * D) {
-        kind[j] = 1;
-        eidx[j] = f - D;
-      } else {
-        kind[j] = 0;
-        eidx[j] = f - 1 - D;
-      }
-    }
-  }
-
-  // The tile's trading state, in the registers of wavefront 0's lanes 0..M-1.
+  // The tile's trading state: cash, asset, cumulative reward in the chain wavefront's registers,
+  // holdings in LDS.
   double cash = 0.0, asset = 0.0, cumrew = 0.0;
-  int h[DMAX], x[DMAX];
-  const bool active = loader && lane < M;
+  const bool active = role == 0 && lane < M;
   const int n = n0 + lane;
-#pragma unroll
-  for (int d = 0; d < DMAX; ++d) {
-    h[d] = 0;
-    x[d] = 0;
-  }
+  int* hrow = s_hold + lane * DS;
   if (MODE == kReset) {
     cash = C.init_cash;
+    if (active)
+      for (int d = 0; d < D; ++d) hrow[d] = 0;
   } else if (active) {
     cash = st.cash[n];
     asset = st.asset[n];
     cumrew = st.cumrew[n];
-#pragma unroll
-    for (int d = 0; d < DMAX; ++d)
-      if (d < D) h[d] = st.hold[static_cast<size_t>(d) * N + n];
+    for (int d = 0; d < D; ++d) hrow[d] = st.hold[static_cast<size_t>(d) * N + n];
   }
 
   const int n_iter = trades(MODE) ? A.n_steps : 1;
-  // Inputs of step it are fetched into wavefront 0's registers one step ahead, then moved to LDS.
-  float pa[TC::kActRegs], pm[TC::kMktRegs];
-  auto fetch = [&](int it) {
+  // Fetch wavefront: inputs of step it into buffer it & 1.  One flat index runs over the
+  // trading-day closes (D), the new-day closes (D), the new-day indicators (I*D) and, in driven
+  // mode, the tile's actions (M*D); each batch issues all its loads before any LDS write.
+  auto fetch_into = [&](int it) {
+    const int b = it & 1;
     const int t = A.t0 + it;
     const int tn = trades(MODE) ? t + 1 : A.t0;
+    float* px = s_px0 + b * D;
+    float* pn = s_pn0 + b * D;
+    float* mkt = s_mkt0 + b * n_new;
+    float* act = s_act0 + b * A.M * DS;
+    const float* c_t = C.close + static_cast<size_t>(t) * D;
+    const float* c_n = C.close + static_cast<size_t>(tn) * D;
+    const float* ind = C.ind + static_cast<size_t>(tn) * C.I * D;
+    // The tile's actions (driven mode); flat index i >= n_mkt is action i - n_mkt.
+    const float* acts = (MODE == kGiven) ? A.act + (static_cast<size_t>(it) * N + n0) * D : C.close;
+
+    const int total = n_mkt + ((MODE == kGiven) ? MD : 0);
+    for (int i0 = 0; i0 < total; i0 += kPrefetch * kWave) {
+      float v[kPrefetch];
 #pragma unroll
-    for (int j = 0; j < TC::kMktRegs; ++j) {
-      const int i = lane + kWave * j;
-      pm[j] = i < n_mkt ? market_entry(C, t, tn, i, trades(MODE)) : 0.0f;
-    }
-    if (MODE == kGiven) {
-      const float* src = A.act + (static_cast<size_t>(it) * N + n0) * D;
-#pragma unroll
-      for (int j = 0; j < TC::kActRegs; ++j) {
-        const int i = lane + kWave * j;
-        pa[j] = i < MD ? src[i] : 0.0f;
+      for (int j = 0; j < kPrefetch; ++j) {
+        const int i = i0 + lane + kWave * j;
+        const float* src = i < D ? c_t + i : (i < 2 * D ? c_n + (i - D) : (i < n_mkt ? ind + (i - 2 * D) : acts + (i - n_mkt)));
+        v[j] = (i < total && (i >= D || trades(MODE))) ? *src : 0.0f;
       }
-    }
-  };
-  auto commit = [&](int it) {
-    float* mkt = s_mkt[it & 1];
 #pragma unroll
-    for (int j = 0; j < TC::kMktRegs; ++j) {
-      const int i = lane + kWave * j;
-      if (i < D) {
-        s_px[i] = pm[j];
-      } else if (i < 2 * D) {
-        s_pn[i - D] = pm[j];
-        mkt[i - D] = pm[j] * C.price_scale;
-      } else if (i < n_mkt) {
-        mkt[i - D] = pm[j];
-      }
-    }
-    if (MODE == kGiven) {
-#pragma unroll
-      for (int j = 0; j < TC::kActRegs; ++j) {
-        const int i = lane + kWave * j;
-        if (i < MD) {
-          const int m = div_small(i, inv_d);
-          s_act[m * ST + (i - m * D)] = pa[j];
+      for (int j = 0; j < kPrefetch; ++j) {
+        const int i = i0 + lane + kWave * j;
+        if (i >= total) {
+        } else if (i < D) {
+          px[i] = v[j];
+        } else if (i < 2 * D) {
+          pn[i - D] = v[j];
+          mkt[i - D] = v[j] * C.price_scale;
+        } else if (i < n_mkt) {
+          mkt[i - D] = v[j];
+        } else {
+          const int k = i - n_mkt;
+          const int m = div_small(k, inv_d);
+          act[m * DS + (k - m * D)] = v[j];
         }
       }
     }
   };
 
-  if (loader) {
-    fetch(0);
-    commit(0);
-  }
+  if (role == 2) fetch_into(0);
   __syncthreads();
 
   for (int it = 0; it < n_iter; ++it) {
     const int t = A.t0 + it;
-    if (loader) {
-      if (it + 1 < n_iter) fetch(it + 1);
-
+    const int b = it & 1;
+    float* s_act = s_act0 + b * A.M * DS;
+    const float* s_px = s_px0 + b * D;
+    const float* s_pn = s_pn0 + b * D;
+    if (role == 0) {
       if (MODE == kEnsemble) {
         // Noise: one Philox block per (env, group of 4 stocks).
         const int G = (D + 3) >> 2;
@@ -208,9 +185,10 @@ __global__ __launch_bounds__(2 * kWave) void env_tile_kernel(EnvConst C, EnvStat
                         static_cast<uint64_t>(t), static_cast<uint64_t>(g), z);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              if (4 * g + r < D) s_eps[m * ST + 4 * g + r] = z[r];
+              if (4 * g + r < D) s_eps[m * DS + 4 * g + r] = z[r];
           }
         }
+        wave_lds_sync();
         for (int i = lane; i < MD; i += kWave) {
           const int m = div_small(i, inv_d);
           const int d = i - m * D;
@@ -218,79 +196,71 @@ __global__ __launch_bounds__(2 * kWave) void env_tile_kernel(EnvConst C, EnvStat
           for (int k = 0; k < A.K; ++k)
             acc = acc + A.mix[k] * A.mu[(static_cast<size_t>(k) * N + n0) * D + i];
           float a = acc;
-          if (A.sigma != 0.0f) a = acc + A.sigma * s_eps[m * ST + d];
+          if (A.sigma != 0.0f) a = acc + A.sigma * s_eps[m * DS + d];
           a = fminf(fmaxf(a, -1.0f), 1.0f);
-          s_act[m * ST + d] = a;
+          s_act[m * DS + d] = a;
         }
       }
-
+      // The chain: parallel pre-terms, serial cash recurrence per env, parallel post-terms.
+      const ChainLds CL{s_act, s_hold, s_qty, s_env, s_px, s_pn, s_pro, s_deb, s_val, s_qd, s_kq};
+      wave_lds_sync();
+      if (trades(MODE)) {
+        chain_pairs_a(CL, M, D, lane, kWave, inv_d, C.hmax_f, C.one_m, C.one_p);
+        wave_lds_sync();
+        if (active)
+          chain_serial(cash, s_pro + lane * D, s_deb + lane * D, s_val + lane * D, s_qd + lane * D, s_px,
+                       s_kq + lane * D, D, C.one_p);
+        wave_lds_sync();
+        chain_pairs_c(CL, M, D, lane, kWave, inv_d, C.hold_scale);
+      } else {
+        chain_pairs_hold(CL, M, D, lane, kWave, inv_d, C.hold_scale);
+      }
+      wave_lds_sync();
       if (active) {
+        const double v_new = chain_value(cash, s_val + lane * D, D);
         if (trades(MODE)) {
-          float a[DMAX], px[DMAX];
-          lds_row<DMAX>(a, &s_act[lane * ST]);
-          lds_row<DMAX>(px, s_px);
-          trade<DMAX>(cash, h, x, a, px, C.hmax_f, C.one_m, C.one_p);
-          float pn[DMAX];
-          lds_row<DMAX>(pn, s_pn);
-          const double v_new = portfolio_value<DMAX>(cash, h, pn);
           const double r = (v_new - asset) * C.reward_scale;
           cumrew = cumrew + r;
-          asset = v_new;
           s_rew[lane] = r;
-        } else if (MODE == kReset) {
-          float pn[DMAX];
-          lds_row<DMAX>(pn, s_pn);
-          asset = portfolio_value<DMAX>(cash, h, pn);
         }
-        s_env[lane * ST] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
-#pragma unroll
-        for (int d = 0; d < DMAX; ++d)
-          if (d < D) {
-            s_env[lane * ST + 1 + d] = static_cast<float>(h[d]) * C.hold_scale;
-            s_qty[lane * ST + d] = x[d];
-          }
+        if (MODE != kObserve) asset = v_new;
+        s_env[lane * DS] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
       }
+    } else if (role == 2 && it + 1 < n_iter) {
+      fetch_into(it + 1);  // the other buffer: nobody reads it during this step
     }
     __syncthreads();
 
-    if (!loader) {
-      // Results of step it.
+    if (role == 1) {
+      // Results of step it: the tile's rows are contiguous in every [N][.] trajectory.
+      const size_t row0 = static_cast<size_t>(it) * N + n0;
       if (trades(MODE)) {
-        if (A.rew && lane < M) A.rew[static_cast<size_t>(it) * N + n0 + lane] = s_rew[lane];
-        if (MODE == kEnsemble && A.act_out) {  // single-step mode: s_act is not refilled
-          float* dst = A.act_out + (static_cast<size_t>(it) * N + n0) * D;
-          for (int i = lane; i < MD; i += kWave) {
+        if (A.rew && lane < M) A.rew[row0 + lane] = s_rew[lane];
+        if (MODE == kEnsemble && A.act_out)
+          wave_store_row(A.act_out + row0 * D, MD, lane, [&](int i) {
             const int m = div_small(i, inv_d);
-            dst[i] = s_act[m * ST + (i - m * D)];
-          }
-        }
-        if (A.qty) {
-          int* dst = A.qty + (static_cast<size_t>(it) * N + n0) * D;
-          for (int i = lane; i < MD; i += kWave) {
+            return s_act[m * DS + (i - m * D)];
+          });
+        if (A.qty)
+          wave_store_row(A.qty + row0 * D, MD, lane, [&](int i) {
             const int m = div_small(i, inv_d);
-            dst[i] = s_qty[m * ST + (i - m * D)];
-          }
-        }
+            return s_qty[m * DS + (i - m * D)];
+          });
       }
-      // States s_{t+1}: shared entries cached per slot, per-env entries from LDS.
+      // States s_{t+1} = [cash, new closes, holdings, new indicators], one row per env.
       if (A.obs) {
-        const float* mkt = s_mkt[it & 1];
-        float* dst = A.obs + (static_cast<size_t>(it) * N + n0) * S;
-        float mval[TC::kSlots];
-#pragma unroll
-        for (int j = 0; j < TC::kSlots; ++j) mval[j] = (kind[j] == 0) ? mkt[eidx[j]] : 0.0f;
-        for (int m = 0; m < M; ++m) {
-#pragma unroll
-          for (int j = 0; j < TC::kSlots; ++j) {
-            if (kind[j] != 2) {
-              const float v = (kind[j] == 0) ? mval[j] : s_env[m * ST + eidx[j]];
-              dst[static_cast<size_t>(m) * S + lane + kWave * j] = v;
-            }
-          }
-        }
+        const float* mkt = s_mkt0 + b * n_new;
+        const float inv_s = 1.0f / static_cast<float>(S);
+        wave_store_row(A.obs + row0 * S, M * S, lane, [&](int e) {
+          const int m = div_small(e, inv_s);
+          const int f = e - m * S;
+          const float* erow = s_env + m * DS;
+          if (f == 0) return erow[0];
+          if (f <= D) return mkt[f - 1];
+          if (f <= 2 * D) return erow[f - D];
+          return mkt[f - 1 - D];
+        });
       }
-    } else if (it + 1 < n_iter) {
-      commit(it + 1);  // s_act, s_px, s_pn are free (the chain has read them); s_mkt is the other buffer
     }
     __syncthreads();
   }
@@ -300,30 +270,22 @@ __global__ __launch_bounds__(2 * kWave) void env_tile_kernel(EnvConst C, EnvStat
     st.cash[n] = cash;
     st.asset[n] = asset;
     st.cumrew[n] = cumrew;
-#pragma unroll
-    for (int d = 0; d < DMAX; ++d)
-      if (d < D) st.hold[static_cast<size_t>(d) * N + n] = h[d];
+    for (int d = 0; d < D; ++d) st.hold[static_cast<size_t>(d) * N + n] = hrow[d];
   }
 }
 
-template <int DMAX, int MODE>
-hipError_t launch_tile(const EnvConst& C, const EnvState& st, StepArgs A, hipStream_t stream) {
-  A.M = min(A.M, TileCfg<DMAX>::kMaxM);
-  const int grid = (C.N + A.M - 1) / A.M;
-  hipLaunchKernelGGL((env_tile_kernel<DMAX, MODE>), dim3(grid), dim3(2 * kWave), 0, stream, C, st,
-                     A);
-  return hipGetLastError();
-}
-
 template <int MODE>
-hipError_t dispatch_tile(const EnvConst& C, const EnvState& st, const StepArgs& A,
-                         hipStream_t stream) {
-  if (C.D <= 8) return launch_tile<8, MODE>(C, st, A, stream);
-  if (C.D <= 16) return launch_tile<16, MODE>(C, st, A, stream);
-  if (C.D <= 32) return launch_tile<32, MODE>(C, st, A, stream);
-  if (C.D <= 64) return launch_tile<64, MODE>(C, st, A, stream);
-  if (C.D <= 128) return launch_tile<128, MODE>(C, st, A, stream);
-  return hipErrorInvalidValue;
+hipError_t dispatch_tile(const EnvConst& C, const EnvState& st, StepArgs A, hipStream_t stream) {
+  A.M = max(1, min(A.M, 64));
+  const size_t lds = tile_lds_bytes(A.M, C.D, C.I);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(env_tile_kernel<MODE>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
+  const int grid = (C.N + A.M - 1) / A.M;
+  hipLaunchKernelGGL((env_tile_kernel<MODE>), dim3(grid), dim3(3 * kWave), lds, stream, C, st, A);
+  return hipGetLastError();
 }
 
 __global__ void read_state_kernel(int N, int D, EnvState st, double* cash, int* hold,

@@ -47,45 +47,56 @@ __device__ __forceinline__ void static_for(Fn&& f) {
 }
 
 // LDS layout shared by both schedules.
-template <int DMAX>
 struct FusedLds {
-  static constexpr int kAST = DMAX + 4;  // 16-byte rows for the chain's action reads
-  __bf16 *x0, *x1, *x2;                  // state rows, layer-1 and layer-2 outputs
-  float* abar;                           // [MR][DS]
-  float* act;                            // [MR][kAST]
-  float* env;                            // [MR][DS]: cash entry, holdings entries
-  int* qty;                              // [MR][DS]
-  float *px, *pn;                        // [DMAX] closes of the trading day / new day, zero-padded
-  float* mkt;                            // [(1+I)*D] scaled new close, new indicators
+  __bf16 *x0, *x1, *x2;  // state rows, layer-1 and layer-2 outputs
+  float* abar;           // [MR][DS] ensemble mean
+  float* act;            // [MR][DS] noisy clipped action
+  int* hold;             // [MR][DS] holdings (the trading state, resident for the whole rollout)
+  int* qty;              // [MR][DS] executed shares
+  float* env;            // [MR][DS] cash entry, holdings entries of the state rows
+  float *px, *pn;        // [D] closes of the trading day / new day
+  float* mkt;            // [(1+I)*D] scaled new close, new indicators
+
+  double *pro, *deb, *val;  // [MR][D] chain scratch
+  int *qd, *kq;             // [MR][D] chain scratch
 
   __host__ __device__ static size_t bytes(int MR, int st0, int sth, int D, int I) {
     const size_t DS = D + 1;
-    size_t b = sizeof(__bf16) * MR * (static_cast<size_t>(st0) + 2 * sth);
-    b += sizeof(float) * MR * (3 * DS + kAST);
-    b += sizeof(float) * (2 * DMAX + (1 + I) * D);
-    return (b + 15) / 16 * 16;
+    size_t b = sizeof(double) * MR * D * 3 + sizeof(int) * MR * D * 2;
+    b += sizeof(__bf16) * MR * (static_cast<size_t>(st0) + 2 * sth);
+    b += sizeof(float) * MR * DS * 5;
+    b += sizeof(float) * (2 * D + (1 + I) * D);
+    return (b + 16 + 15) / 16 * 16;
   }
   __device__ void carve(unsigned char* smem, int MR, int st0, int sth, int D) {
     const int DS = D + 1;
-    x0 = reinterpret_cast<__bf16*>(smem);
+    pro = reinterpret_cast<double*>(smem);
+    deb = pro + MR * D;
+    val = deb + MR * D;
+    qd = reinterpret_cast<int*>(val + MR * D);
+    kq = qd + MR * D;
+    // 16-byte alignment for the bf16 MFMA operand rows.
+    const size_t off = (reinterpret_cast<uintptr_t>(kq + MR * D) - reinterpret_cast<uintptr_t>(smem) + 15) / 16 * 16;
+    x0 = reinterpret_cast<__bf16*>(smem + off);
     x1 = x0 + MR * st0;
     x2 = x1 + MR * sth;
-    act = reinterpret_cast<float*>(x2 + MR * sth);  // 16-byte aligned: st0, sth are multiples of 8
-    abar = act + MR * kAST;
-    env = abar + MR * DS;
-    qty = reinterpret_cast<int*>(env + MR * DS);
-    px = reinterpret_cast<float*>(qty + MR * DS);
-    pn = px + DMAX;
-    mkt = pn + DMAX;
+    abar = reinterpret_cast<float*>(x2 + MR * sth);
+    act = abar + MR * DS;
+    hold = reinterpret_cast<int*>(act + MR * DS);
+    qty = hold + MR * DS;
+    env = reinterpret_cast<float*>(qty + MR * DS);
+    px = env + MR * DS;
+    pn = px + D;
+    mkt = pn + D;
   }
 };
 
 // The environment half of a step, shared by both schedules.  NT threads per workgroup.
-template <int DMAX, int NT>
+template <int NT>
 struct EnvPhase {
   const EnvConst& C;
   const FusedArgs& F;
-  FusedLds<DMAX>& L;
+  FusedLds& L;
   int tid, lane, wave, n0, M, S_pad, st0;
   float inv_d, inv_g;
   int G;
@@ -119,7 +130,7 @@ struct EnvPhase {
           float a = L.abar[m * DS + d];
           if (F.sigma != 0.0f) a = a + F.sigma * z[r];
           a = fminf(fmaxf(a, -1.0f), 1.0f);
-          L.act[m * FusedLds<DMAX>::kAST + d] = a;
+          L.act[m * DS + d] = a;
           if (F.act_traj) F.act_traj[(row_base + m) * D + d] = a;
         }
       }
@@ -127,13 +138,38 @@ struct EnvPhase {
   }
 
   // Cash and holdings entries of the state rows (owner lanes).
-  __device__ void env_entries(bool owner, double cash, const int (&h)[DMAX]) {
+  __device__ void env_entries(bool owner, double cash) {
     if (!owner) return;
-    const int DS = C.D + 1;
-    L.env[lane * DS] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
-#pragma unroll
-    for (int d = 0; d < DMAX; ++d)
-      if (d < C.D) L.env[lane * DS + 1 + d] = static_cast<float>(h[d]) * C.hold_scale;
+    const int D = C.D, DS = D + 1;
+    float* erow = L.env + lane * DS;
+    const int* hrow = L.hold + lane * DS;
+    erow[0] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
+    for (int d = 0; d < D; ++d) erow[1 + d] = static_cast<float>(hrow[d]) * C.hold_scale;
+  }
+
+  // One step of the trading chain: parallel pre-terms (all threads), the serial cash recurrence
+  // (owner lanes), parallel post-terms (all threads).  Returns the reward in the owner lanes.
+  // Entered and left with all threads synchronised.
+  __device__ double chain(bool owner, double& cash, double& asset, double& cumrew) {
+    const int D = C.D;
+    const ChainLds CL{L.act, L.hold, L.qty, L.env, L.px, L.pn, L.pro, L.deb, L.val, L.qd, L.kq};
+    chain_pairs_a(CL, M, D, tid, NT, inv_d, C.hmax_f, C.one_m, C.one_p);
+    __syncthreads();
+    if (owner)
+      chain_serial(cash, L.pro + lane * D, L.deb + lane * D, L.val + lane * D, L.qd + lane * D, L.px,
+                   L.kq + lane * D, D, C.one_p);
+    __syncthreads();
+    chain_pairs_c(CL, M, D, tid, NT, inv_d, C.hold_scale);
+    __syncthreads();
+    double r = 0.0;
+    if (owner) {
+      const double v_new = chain_value(cash, L.val + lane * D, D);
+      r = (v_new - asset) * C.reward_scale;
+      cumrew = cumrew + r;
+      asset = v_new;
+      L.env[lane * (D + 1)] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
+    }
+    return r;
   }
 
   // State rows: bfloat16 into x0 for the next first layer, float32 into the trajectory.
@@ -161,6 +197,24 @@ struct EnvPhase {
       const int m = div_small(i, inv_d);
       F.qty_traj[row_base * D + i] = L.qty[m * DS + (i - m * D)];
     }
+  }
+
+  // Load the tile's state into the owner lanes (holdings into LDS).
+  __device__ void load_state(bool owner, const EnvState& st, double& cash, double& asset, double& cumrew) {
+    if (!owner) return;
+    const int D = C.D, N = C.N, DS = D + 1, n = n0 + lane;
+    cash = st.cash[n];
+    asset = st.asset[n];
+    cumrew = st.cumrew[n];
+    for (int d = 0; d < D; ++d) L.hold[lane * DS + d] = st.hold[static_cast<size_t>(d) * N + n];
+  }
+  __device__ void store_state(bool owner, const EnvState& st, double cash, double asset, double cumrew) {
+    if (!owner) return;
+    const int D = C.D, N = C.N, DS = D + 1, n = n0 + lane;
+    st.cash[n] = cash;
+    st.asset[n] = asset;
+    st.cumrew[n] = cumrew;
+    for (int d = 0; d < D; ++d) st.hold[static_cast<size_t>(d) * N + n] = L.hold[lane * DS + d];
   }
 };
 
@@ -244,7 +298,7 @@ struct Streamed {
   }
 };
 
-template <int DMAX, int ROWT, int KK1, int DEPTH, int NWAVES>
+template <int ROWT, int KK1, int DEPTH, int NWAVES>
 __global__ __launch_bounds__(64 * NWAVES) void fused_streamed_kernel(EnvConst C, EnvState st, EnsDev E,
                                                                      FusedArgs F) {
   using SP = Streamed<KK1, ROWT, DEPTH, NWAVES>;
@@ -258,43 +312,23 @@ __global__ __launch_bounds__(64 * NWAVES) void fused_streamed_kernel(EnvConst C,
   const int n0 = blockIdx.x * MR;
   const int M = min(MR, N - n0);
 
-  FusedLds<DMAX> L;
+  FusedLds L;
   L.carve(smem, MR, ST0, STH, D);
-  EnvPhase<DMAX, NT> P{C, F, L, tid, lane, wave, n0, M, S_PAD, ST0, 1.0f / static_cast<float>(D),
-                       1.0f / static_cast<float>((D + 3) >> 2), (D + 3) >> 2};
+  EnvPhase<NT> P{C, F, L, tid, lane, wave, n0, M, S_PAD, ST0, 1.0f / static_cast<float>(D),
+                 1.0f / static_cast<float>((D + 3) >> 2), (D + 3) >> 2};
 
   for (int i = tid; i < MR * ST0; i += NT) L.x0[i] = static_cast<__bf16>(0.0f);
-  for (int i = tid; i < MR * FusedLds<DMAX>::kAST; i += NT) L.act[i] = 0.0f;
-  for (int i = tid; i < DMAX; i += NT) {
-    L.px[i] = 0.0f;
-    L.pn[i] = 0.0f;
-  }
-  __syncthreads();
 
   const bool owner = wave == 0 && lane < M;
   const int n = n0 + lane;
   double cash = 0.0, asset = 0.0, cumrew = 0.0;
-  int h[DMAX], x[DMAX];
-#pragma unroll
-  for (int d = 0; d < DMAX; ++d) {
-    h[d] = 0;
-    x[d] = 0;
-  }
-  if (owner) {
-    cash = st.cash[n];
-    asset = st.asset[n];
-    cumrew = st.cumrew[n];
-#pragma unroll
-    for (int d = 0; d < DMAX; ++d)
-      if (d < D) h[d] = st.hold[static_cast<size_t>(d) * N + n];
-  }
+  P.load_state(owner, st, cash, asset, cumrew);
 
   P.stage_market(F.t0, false);
-  P.env_entries(owner, cash, h);
+  P.env_entries(owner, cash);
   __syncthreads();
   P.assemble(nullptr);
 
-  // Weight fragments in flight: ring[s % DEPTH] holds k-step s.
   const int wv = __builtin_amdgcn_readfirstlane(wave);
   const int voff = lane * 16;
   bf16x8 ring[DEPTH][TW];
@@ -402,38 +436,17 @@ __global__ __launch_bounds__(64 * NWAVES) void fused_streamed_kernel(EnvConst C,
 
     P.actions(t, row_base);
     __syncthreads();
-    if (owner) {
-      float a[DMAX], px[DMAX], pn[DMAX];
-      lds_row<DMAX>(a, &L.act[lane * FusedLds<DMAX>::kAST]);
-      lds_row<DMAX>(px, L.px);
-      trade<DMAX>(cash, h, x, a, px, C.hmax_f, C.one_m, C.one_p);
-      lds_row<DMAX>(pn, L.pn);
-      const double v_new = portfolio_value<DMAX>(cash, h, pn);
-      const double rwd = (v_new - asset) * C.reward_scale;
-      cumrew = cumrew + rwd;
-      asset = v_new;
-      if (F.rew_traj) F.rew_traj[static_cast<size_t>(it) * N + n] = rwd;
-#pragma unroll
-      for (int d = 0; d < DMAX; ++d)
-        if (d < D) L.qty[lane * DS + d] = x[d];
-    }
-    P.env_entries(owner, cash, h);
+    const double rwd = P.chain(owner, cash, asset, cumrew);
+    if (owner && F.rew_traj) F.rew_traj[static_cast<size_t>(it) * N + n] = rwd;
     __syncthreads();
     P.quantities(row_base);
     P.assemble(F.obs_traj ? F.obs_traj + row_base * C.S : nullptr);
   }
 
-  if (owner) {
-    st.cash[n] = cash;
-    st.asset[n] = asset;
-    st.cumrew[n] = cumrew;
-#pragma unroll
-    for (int d = 0; d < DMAX; ++d)
-      if (d < D) st.hold[static_cast<size_t>(d) * N + n] = h[d];
-  }
+  P.store_state(owner, st, cash, asset, cumrew);
 }
 
-template <int DMAX, int ROWT, int TMAX>
+template <int ROWT, int TMAX>
 __global__ __launch_bounds__(256) void fused_generic_kernel(EnvConst C, EnvState st, EnsDev E,
                                                             FusedArgs F) {
   constexpr int NT = 256, MR = 16 * ROWT;
@@ -444,39 +457,20 @@ __global__ __launch_bounds__(256) void fused_generic_kernel(EnvConst C, EnvState
   const int M = min(MR, N - n0);
   const int st0 = E.S_pad + 8, sth = E.H + 8;
 
-  FusedLds<DMAX> L;
+  FusedLds L;
   L.carve(smem, MR, st0, sth, D);
-  EnvPhase<DMAX, NT> P{C, F, L, tid, lane, wave, n0, M, E.S_pad, st0, 1.0f / static_cast<float>(D),
-                       1.0f / static_cast<float>((D + 3) >> 2), (D + 3) >> 2};
+  EnvPhase<NT> P{C, F, L, tid, lane, wave, n0, M, E.S_pad, st0, 1.0f / static_cast<float>(D),
+                 1.0f / static_cast<float>((D + 3) >> 2), (D + 3) >> 2};
 
   for (int i = tid; i < MR * st0; i += NT) L.x0[i] = static_cast<__bf16>(0.0f);
-  for (int i = tid; i < MR * FusedLds<DMAX>::kAST; i += NT) L.act[i] = 0.0f;
-  for (int i = tid; i < DMAX; i += NT) {
-    L.px[i] = 0.0f;
-    L.pn[i] = 0.0f;
-  }
-  __syncthreads();
 
   const bool owner = wave == 0 && lane < M;
   const int n = n0 + lane;
   double cash = 0.0, asset = 0.0, cumrew = 0.0;
-  int h[DMAX], x[DMAX];
-#pragma unroll
-  for (int d = 0; d < DMAX; ++d) {
-    h[d] = 0;
-    x[d] = 0;
-  }
-  if (owner) {
-    cash = st.cash[n];
-    asset = st.asset[n];
-    cumrew = st.cumrew[n];
-#pragma unroll
-    for (int d = 0; d < DMAX; ++d)
-      if (d < D) h[d] = st.hold[static_cast<size_t>(d) * N + n];
-  }
+  P.load_state(owner, st, cash, asset, cumrew);
 
   P.stage_market(F.t0, false);
-  P.env_entries(owner, cash, h);
+  P.env_entries(owner, cash);
   __syncthreads();
   P.assemble(nullptr);
 
@@ -530,35 +524,14 @@ __global__ __launch_bounds__(256) void fused_generic_kernel(EnvConst C, EnvState
 
     P.actions(t, row_base);
     __syncthreads();
-    if (owner) {
-      float a[DMAX], px[DMAX], pn[DMAX];
-      lds_row<DMAX>(a, &L.act[lane * FusedLds<DMAX>::kAST]);
-      lds_row<DMAX>(px, L.px);
-      trade<DMAX>(cash, h, x, a, px, C.hmax_f, C.one_m, C.one_p);
-      lds_row<DMAX>(pn, L.pn);
-      const double v_new = portfolio_value<DMAX>(cash, h, pn);
-      const double rwd = (v_new - asset) * C.reward_scale;
-      cumrew = cumrew + rwd;
-      asset = v_new;
-      if (F.rew_traj) F.rew_traj[static_cast<size_t>(it) * N + n] = rwd;
-#pragma unroll
-      for (int d = 0; d < DMAX; ++d)
-        if (d < D) L.qty[lane * DS + d] = x[d];
-    }
-    P.env_entries(owner, cash, h);
+    const double rwd = P.chain(owner, cash, asset, cumrew);
+    if (owner && F.rew_traj) F.rew_traj[static_cast<size_t>(it) * N + n] = rwd;
     __syncthreads();
     P.quantities(row_base);
     P.assemble(F.obs_traj ? F.obs_traj + row_base * C.S : nullptr);
   }
 
-  if (owner) {
-    st.cash[n] = cash;
-    st.asset[n] = asset;
-    st.cumrew[n] = cumrew;
-#pragma unroll
-    for (int d = 0; d < DMAX; ++d)
-      if (d < D) st.hold[static_cast<size_t>(d) * N + n] = h[d];
-  }
+  P.store_state(owner, st, cash, asset, cumrew);
 }
 
 template <class Kern>
@@ -571,19 +544,18 @@ hipError_t go(Kern kern, int grid, int threads, size_t lds, hipStream_t stream, 
   return hipGetLastError();
 }
 
-template <int DMAX, int ROWT>
 hipError_t launch_generic(const EnvConst& C, const EnvState& st, const EnsDev& E, const FusedArgs& F,
                           hipStream_t stream, std::string* why) {
-  const size_t lds = FusedLds<DMAX>::bytes(16 * ROWT, E.S_pad + 8, E.H + 8, C.D, C.I);
+  const size_t lds = FusedLds::bytes(16, E.S_pad + 8, E.H + 8, C.D, C.I);
   if (lds > 160 * 1024) {
     *why = "fused rollout: state and hidden sizes exceed the LDS budget";
     return hipSuccess;
   }
-  const int grid = (C.N + 16 * ROWT - 1) / (16 * ROWT);
+  const int grid = (C.N + 15) / 16;
   const int tiles_per_wave = (E.H / 16 + 3) / 4;
-  if (tiles_per_wave <= 2) return go(fused_generic_kernel<DMAX, ROWT, 2>, grid, 256, lds, stream, C, st, E, F);
-  if (tiles_per_wave <= 4) return go(fused_generic_kernel<DMAX, ROWT, 4>, grid, 256, lds, stream, C, st, E, F);
-  return go(fused_generic_kernel<DMAX, ROWT, 8>, grid, 256, lds, stream, C, st, E, F);
+  if (tiles_per_wave <= 2) return go(fused_generic_kernel<1, 2>, grid, 256, lds, stream, C, st, E, F);
+  if (tiles_per_wave <= 4) return go(fused_generic_kernel<1, 4>, grid, 256, lds, stream, C, st, E, F);
+  return go(fused_generic_kernel<1, 8>, grid, 256, lds, stream, C, st, E, F);
 }
 
 constexpr int kDepth = 6;
@@ -592,16 +564,16 @@ constexpr int kWaves = 4;
 template <int ROWT>
 hipError_t launch_streamed(const EnvConst& C, const EnvState& st, const EnsDev& E, const FusedArgs& F,
                            hipStream_t stream) {
-  const size_t lds = FusedLds<32>::bytes(16 * ROWT, 224 + 8, 256 + 8, C.D, C.I);
+  const size_t lds = FusedLds::bytes(16 * ROWT, 224 + 8, 256 + 8, C.D, C.I);
   const int grid = (C.N + 16 * ROWT - 1) / (16 * ROWT);
-  return go(fused_streamed_kernel<32, ROWT, 7, kDepth, kWaves>, grid, 64 * kWaves, lds, stream, C, st, E, F);
+  return go(fused_streamed_kernel<ROWT, 7, kDepth, kWaves>, grid, 64 * kWaves, lds, stream, C, st, E, F);
 }
 
 }  // namespace
 
 bool fused_streamed_shape(const EnvConst& C, const EnsDev& E) {
   using SP = Streamed<7, 1, kDepth, kWaves>;
-  return E.K == 3 && E.H == 256 && E.S_pad == 224 && E.A_pad == 32 && C.D <= 32 && C.D >= 1 &&
+  return E.K == 3 && E.H == 256 && E.S_pad == 224 && E.A_pad == 32 && C.D >= 1 && C.D <= 32 &&
          E.off_w1 == SP::kW1 && E.off_w2 == SP::kW2 && E.off_w3 == SP::kW3 && E.off_b1 == SP::kB1 &&
          E.off_b2 == SP::kB2 && E.off_b3 == SP::kB3 && E.actor_stride == SP::kActor;
 }
@@ -621,17 +593,11 @@ hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const Ens
   rowt = rowt >= 2 ? 2 : 1;
   if (tune.schedule != 2 && fused_streamed_shape(C, E))
     return rowt == 2 ? launch_streamed<2>(C, st, E, F, stream) : launch_streamed<1>(C, st, E, F, stream);
-  auto gen = [&](auto dm) -> hipError_t {
-    constexpr int DM = decltype(dm)::value;
-    return launch_generic<DM, 1>(C, st, E, F, stream, why);
-  };
-  if (C.D <= 8) return gen(std::integral_constant<int, 8>());
-  if (C.D <= 16) return gen(std::integral_constant<int, 16>());
-  if (C.D <= 32) return gen(std::integral_constant<int, 32>());
-  if (C.D <= 64) return gen(std::integral_constant<int, 64>());
-  if (C.D <= 128) return gen(std::integral_constant<int, 128>());
-  *why = "fused rollout: at most 128 stocks";
-  return hipSuccess;
+  if (C.D > 128) {
+    *why = "fused rollout: at most 128 stocks";
+    return hipSuccess;
+  }
+  return launch_generic(C, st, E, F, stream, why);
 }
 
 }  // namespace fm
