@@ -99,84 +99,6 @@ __device__ __forceinline__ int order_from_action(float a, float hmax_f) {
   return static_cast<int>(truncf(prod));
 }
 
-// Largest k in [0, q] with (p*k)*one_p <= cash, for the case (p*q)*one_p > cash.  The debit is
-// monotone in k, so a quotient estimate (from an approximate reciprocal) followed by unit steps
-// in both directions is exact whatever the estimate's error; the steps are bounded by q.
-__device__ __forceinline__ int partial_fill(double cash, double p, int q, double one_p) {
-#pragma clang fp contract(off)
-  const double c1 = p * one_p;
-  if (!(c1 <= cash)) return 0;
-  const double est = floor(cash * __builtin_amdgcn_rcp(c1));
-  int k = static_cast<int>(fmin(fmax(est, 0.0), static_cast<double>(q)));
-  while (k < q && (p * static_cast<double>(k + 1)) * one_p <= cash) ++k;
-  while (k > 0 && (p * static_cast<double>(k)) * one_p > cash) --k;
-  return k;
-}
-
-// One day's trades for one environment held in registers: all sells in ascending stock order,
-// then all buys in ascending stock order, at prices px (float32, day t).  a, px: this env's
-// actions and the day's closes, zero-padded beyond the real stock count; a padded stock has no
-// order, so it adds +0.0 to (and subtracts +0.0 from) a non-negative cash, which leaves it
-// unchanged bit for bit.  x: executed shares (signed).
-template <int DMAX>
-__device__ __forceinline__ void trade(double& cash, int (&h)[DMAX], int (&x)[DMAX],
-                                      const float (&a)[DMAX], const float (&px)[DMAX],
-                                      float hmax_f, double one_m, double one_p) {
-#pragma clang fp contract(off)
-  int q[DMAX];
-#pragma unroll
-  for (int d = 0; d < DMAX; ++d) q[d] = order_from_action(a[d], hmax_f);
-  // Sells: proceeds (p*s)*(1-c); a zero sale adds +0.0.
-#pragma unroll
-  for (int d = 0; d < DMAX; ++d) {
-    const int s = q[d] < 0 ? min(h[d], -q[d]) : 0;
-    const double proceeds = (static_cast<double>(px[d]) * static_cast<double>(s)) * one_m;
-    cash = cash + proceeds;
-    h[d] -= s;
-    x[d] = -s;
-  }
-  // Buys: the whole order if its debit fits, otherwise the largest affordable part.
-#pragma unroll
-  for (int d = 0; d < DMAX; ++d) {
-    const int qd = q[d] > 0 ? q[d] : 0;
-    const double p = static_cast<double>(px[d]);
-    double debit = (p * static_cast<double>(qd)) * one_p;
-    int k = qd;
-    if (!(debit <= cash)) {
-      k = partial_fill(cash, p, qd, one_p);
-      debit = (p * static_cast<double>(k)) * one_p;
-    }
-    cash = cash - debit;
-    h[d] += k;
-    x[d] += k;
-  }
-}
-
-// v = b + p^T h, accumulated in ascending stock order (zero-padded stocks add +0.0).
-template <int DMAX>
-__device__ __forceinline__ double portfolio_value(double cash, const int (&h)[DMAX],
-                                                  const float (&px)[DMAX]) {
-#pragma clang fp contract(off)
-  double acc = cash;
-#pragma unroll
-  for (int d = 0; d < DMAX; ++d) acc = acc + static_cast<double>(px[d]) * static_cast<double>(h[d]);
-  return acc;
-}
-
-// DMAX consecutive floats from a 16-byte-aligned LDS row.
-template <int DMAX>
-__device__ __forceinline__ void lds_row(float (&v)[DMAX], const float* row) {
-  static_assert(DMAX % 4 == 0, "rows are read four floats at a time");
-#pragma unroll
-  for (int d = 0; d < DMAX; d += 4) {
-    const float4 t = *reinterpret_cast<const float4*>(row + d);
-    v[d] = t.x;
-    v[d + 1] = t.y;
-    v[d + 2] = t.z;
-    v[d + 3] = t.w;
-  }
-}
-
 // Exact floor(i / D) for 0 <= i < 2^20 and 1 <= D <= 1024, via a float reciprocal: i/D is at
 // least 1/(2D) away from the next integer above it and the float error is far smaller.
 __device__ __forceinline__ int div_small(int i, float inv_d) {
@@ -212,119 +134,252 @@ __device__ __forceinline__ void wave_store_row(T* dst, int total, int lane, Val 
 // ------------------------------------------------------------------------------------------
 // The chain of a tile of M environments, split so that only the cash recurrence is serial.
 // Every per-stock quantity that does not depend on cash (orders, the sale size, proceeds, the
-// debit of the whole order, the new day's position values) is computed by all threads of the
-// group over the M*D (env, stock) pairs; one lane per environment then runs the float64 cash
-// recurrence in ascending stock order, reading the precomputed terms.  The arithmetic and its
-// order are exactly those of trade() / portfolio_value().
+// debit of the whole order and of one share, the new day's position values) is computed by all
+// threads of the group over the (env, stock) pairs; one lane per environment then runs the
+// float64 cash recurrence in ascending stock order over the precomputed terms, eight stocks per
+// register chunk, with the next chunk's terms read from LDS while the current one is consumed.
 //
-// LDS rows (stride DS = D + 1 for per-env rows, D for scratch):
-//   act[m][d] actions, hold[m][d] holdings (updated), qty[m][d] executed shares (written),
-//   env[m][0..D] state entries (written: cash * scale, holdings * scale)
-//   pro[m][d], deb[m][d], val[m][d] float64 scratch; qd[m][d], kq[m][d] int scratch
+// LDS rows:
+//   act[m][d], hold[m][d], qty[m][d]: stride D (dense, as the tile's rows in HBM);
+//   env[m][0..D]: stride D + 1, the cash entry then the holdings entries of the state row;
+//   pro/deb/val[m][d] float64 scratch: stride RD; qd/kq[m][d] int scratch: stride RI.
+// Scratch rows hold DP >= D stocks, DP a multiple of the chunk; stocks d >= D carry a zero
+// order (proceeds 0, debit 0, order 0), and adding or subtracting +0.0 leaves a non-negative
+// cash (and a value) unchanged bit for bit, so the recurrence may run over whole chunks.  The
+// scratch strides are offset from a multiple of 64 bytes by 16 bytes, so that the lanes of the
+// serial phase, each reading its own row, start in different LDS banks.
 // ------------------------------------------------------------------------------------------
+constexpr int kChunk = 8;
+
+struct ChainShape {
+  int D, DP, RD, RI, DS;
+  float inv_dp;
+  __host__ __device__ static ChainShape of(int D) {
+    ChainShape z;
+    z.D = D;
+    z.DP = (D + kChunk - 1) / kChunk * kChunk;
+    z.RD = z.DP + 2;
+    z.RI = z.DP + 4;
+    z.DS = D + 1;
+    z.inv_dp = 1.0f / static_cast<float>(z.DP);
+    return z;
+  }
+  // LDS bytes of the scratch of M rows (16-byte multiple).
+  __host__ __device__ size_t scratch_bytes(int M) const {
+    return sizeof(double) * 3 * static_cast<size_t>(M) * RD + sizeof(int) * 2 * static_cast<size_t>(M) * RI;
+  }
+};
+
 struct ChainLds {
   const float* act;
   int* hold;
   int* qty;
   float* env;
-  const float* px;  // trading day closes [D]
+  const float* px;  // trading day closes, >= DP readable entries (those beyond D unused)
   const float* pn;  // new day closes [D]
   double* pro;
   double* deb;
   double* val;
   int* qd;
   int* kq;
+  // Carves the scratch (16-byte aligned base) of M rows; returns the first byte after it.
+  __device__ unsigned char* carve_scratch(unsigned char* base, const ChainShape& Z, int M) {
+    pro = reinterpret_cast<double*>(base);
+    deb = pro + M * Z.RD;
+    val = deb + M * Z.RD;
+    qd = reinterpret_cast<int*>(val + M * Z.RD);
+    kq = qd + M * Z.RI;
+    return reinterpret_cast<unsigned char*>(kq + M * Z.RI);
+  }
 };
 
-// Phase A (all threads, pairs i = first, first + stride, ...): orders, sells, whole-order debit.
-__device__ __forceinline__ void chain_pairs_a(const ChainLds& L, int M, int D, int first, int stride,
-                                              float inv_d, float hmax_f, double one_m, double one_p) {
+// Phase A (all threads, pairs i = first, first + stride, ... over M*DP): orders, sells, the
+// whole-order debit and the one-share debit (p*1)*(1+c).
+__device__ __forceinline__ void chain_pairs_a(const ChainLds& L, const ChainShape& Z, int M, int first,
+                                              int stride, float hmax_f, double one_m, double one_p) {
 #pragma clang fp contract(off)
-  const int DS = D + 1;
 #pragma unroll 4
-  for (int i = first; i < M * D; i += stride) {
-    const int m = div_small(i, inv_d);
-    const int d = i - m * D;
-    const int q = order_from_action(L.act[m * DS + d], hmax_f);
-    const int h = L.hold[m * DS + d];
-    const int s = q < 0 ? min(h, -q) : 0;
-    const double p = static_cast<double>(L.px[d]);
-    L.hold[m * DS + d] = h - s;
-    L.qty[m * DS + d] = -s;
-    L.pro[i] = (p * static_cast<double>(s)) * one_m;
-    const int qd = q > 0 ? q : 0;
-    L.qd[i] = qd;
-    L.deb[i] = (p * static_cast<double>(qd)) * one_p;
-    L.val[i] = p * one_p;  // debit of one share, (p*1)*(1+c); the slot is reused in phase C
+  for (int i = first; i < M * Z.DP; i += stride) {
+    const int m = div_small(i, Z.inv_dp);
+    const int d = i - m * Z.DP;
+    double pro = 0.0, deb = 0.0, c1 = 0.0;
+    int qd = 0;
+    if (d < Z.D) {
+      const int e = m * Z.D + d;
+      const int q = order_from_action(L.act[e], hmax_f);
+      const int h = L.hold[e];
+      const int s = q < 0 ? min(h, -q) : 0;
+      const double p = static_cast<double>(L.px[d]);
+      L.hold[e] = h - s;
+      L.qty[e] = -s;
+      pro = (p * static_cast<double>(s)) * one_m;
+      qd = q > 0 ? q : 0;
+      deb = (p * static_cast<double>(qd)) * one_p;
+      c1 = p * one_p;
+    }
+    L.pro[m * Z.RD + d] = pro;
+    L.deb[m * Z.RD + d] = deb;
+    L.val[m * Z.RD + d] = c1;  // the slot is reused for the position values in phase C
+    L.qd[m * Z.RI + d] = qd;
   }
 }
 
-// Phase B (lane m of the owner group): the cash recurrence of environment m.  A buy that does not
-// fit is filled partially only when at least one share is affordable; that is the one rare,
-// divergent branch (the common cases are a whole fill or no fill, both branch-free selects).
+// The partial fill: c1 = (p*1)*one_p <= cash < (p*q)*one_p, so the answer is the largest k in
+// [1, q-1] with (p*k)*one_p <= cash.  The debit is monotone in k.  The estimate floor(cash/c1)
+// uses the hardware reciprocal refined by one Newton step and is within a share of the answer
+// for cash/c1 < 2^31; the unit steps after it, taken only when the two debits around the
+// estimate do not bracket cash, make the result exact whatever the estimate's error.
+__device__ __forceinline__ int partial_fill(double cash, double p, double c1, int q, double one_p,
+                                           double& debit) {
+#pragma clang fp contract(off)
+  double r = __builtin_amdgcn_rcp(c1);
+  r = fma(fma(-c1, r, 1.0), r, r);
+  const double est = floor(cash * r);
+  int k = static_cast<int>(fmin(fmax(est, 1.0), static_cast<double>(q - 1)));
+  double dk = (p * static_cast<double>(k)) * one_p;
+  const double dk1 = (p * static_cast<double>(k + 1)) * one_p;
+  if (dk > cash || (k + 1 < q && dk1 <= cash)) {
+    while (k + 1 < q && (p * static_cast<double>(k + 1)) * one_p <= cash) ++k;
+    while (k > 1 && (p * static_cast<double>(k)) * one_p > cash) --k;
+    dk = (p * static_cast<double>(k)) * one_p;
+  }
+  debit = dk;
+  return k;
+}
+
+// Eight float64 / int / float entries from a 16-byte-aligned LDS address.
+__device__ __forceinline__ void lds8(double (&v)[kChunk], const double* src) {
+#pragma unroll
+  for (int j = 0; j < kChunk / 2; ++j) {
+    const double2 t = reinterpret_cast<const double2*>(src)[j];
+    v[2 * j] = t.x;
+    v[2 * j + 1] = t.y;
+  }
+}
+__device__ __forceinline__ void lds8(int (&v)[kChunk], const int* src) {
+#pragma unroll
+  for (int j = 0; j < kChunk / 4; ++j) {
+    const int4 t = reinterpret_cast<const int4*>(src)[j];
+    v[4 * j] = t.x;
+    v[4 * j + 1] = t.y;
+    v[4 * j + 2] = t.z;
+    v[4 * j + 3] = t.w;
+  }
+}
+__device__ __forceinline__ void lds8(float (&v)[kChunk], const float* src) {
+#pragma unroll
+  for (int j = 0; j < kChunk / 4; ++j) {
+    const float4 t = reinterpret_cast<const float4*>(src)[j];
+    v[4 * j] = t.x;
+    v[4 * j + 1] = t.y;
+    v[4 * j + 2] = t.z;
+    v[4 * j + 3] = t.w;
+  }
+}
+
+// acc + v[0] + ... + v[DP-1] in index order, the terms read chunk by chunk one chunk ahead.
+__device__ __forceinline__ double chain_sum(double acc, const double* __restrict__ v, int DP) {
+#pragma clang fp contract(off)
+  double cur[kChunk];
+  lds8(cur, v);
+  for (int d0 = 0; d0 < DP; d0 += kChunk) {
+    double nxt[kChunk];
+    lds8(nxt, v + (d0 + kChunk < DP ? d0 + kChunk : d0));
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) acc = acc + cur[j];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) cur[j] = nxt[j];
+  }
+  return acc;
+}
+
+struct BuyChunk {
+  double deb[kChunk], c1[kChunk];
+  int q[kChunk];
+  float p[kChunk];
+  __device__ __forceinline__ void load(const double* deb_, const double* c1_, const int* q_, const float* p_) {
+    lds8(deb, deb_);
+    lds8(c1, c1_);
+    lds8(q, q_);
+    lds8(p, p_);
+  }
+};
+
+// Phase B (lane m of the owner group): the cash recurrence of environment m -- all sells, then
+// all buys, in ascending stock order.  A buy fills whole when its debit fits the cash, not at
+// all when one share does not, and partially otherwise (the one divergent branch).
 __device__ __forceinline__ void chain_serial(double& cash, const double* __restrict__ pro,
                                              const double* __restrict__ deb, const double* __restrict__ c1s,
                                              const int* __restrict__ qd, const float* __restrict__ px,
-                                             int* __restrict__ kq, int D, double one_p) {
+                                             int* __restrict__ kq, int DP, double one_p) {
 #pragma clang fp contract(off)
-#pragma unroll 8
-  for (int d = 0; d < D; ++d) cash = cash + pro[d];  // sells, ascending stock order
-#pragma unroll 4
-  for (int d = 0; d < D; ++d) {                       // buys, ascending stock order
-    const double debit_q = deb[d];
-    const double c1 = c1s[d];
-    const int q = qd[d];
-    const bool fits = debit_q <= cash;
-    int k = fits ? q : 0;
-    double debit = fits ? debit_q : 0.0;
-    if (!fits && c1 <= cash) {
-      const double p = static_cast<double>(px[d]);
-      k = partial_fill(cash, p, q, one_p);
-      debit = (p * static_cast<double>(k)) * one_p;
+  cash = chain_sum(cash, pro, DP);
+  BuyChunk cur;
+  cur.load(deb, c1s, qd, px);
+  for (int d0 = 0; d0 < DP; d0 += kChunk) {
+    BuyChunk nxt;
+    const int dn = d0 + kChunk < DP ? d0 + kChunk : d0;
+    nxt.load(deb + dn, c1s + dn, qd + dn, px + dn);
+    int k[kChunk];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+      const bool fits = cur.deb[j] <= cash;
+      int kj = fits ? cur.q[j] : 0;
+      double debit = fits ? cur.deb[j] : 0.0;
+      if (!fits && cur.c1[j] <= cash)
+        kj = partial_fill(cash, static_cast<double>(cur.p[j]), cur.c1[j], cur.q[j], one_p, debit);
+      cash = cash - debit;
+      k[j] = kj;
     }
-    cash = cash - debit;
-    kq[d] = k;
+#pragma unroll
+    for (int j = 0; j < kChunk / 4; ++j)
+      reinterpret_cast<int4*>(kq + d0)[j] = int4{k[4 * j], k[4 * j + 1], k[4 * j + 2], k[4 * j + 3]};
+    cur = nxt;
   }
 }
 
-// Phase C (all threads): apply the buys, state entries of the holdings, new-day position values.
-__device__ __forceinline__ void chain_pairs_c(const ChainLds& L, int M, int D, int first, int stride,
-                                              float inv_d, float hold_scale) {
+// Phase C (all threads, pairs over M*DP): apply the buys, the holdings entries of the state
+// rows, and the new day's position values p'_d h_d (zero beyond D).
+__device__ __forceinline__ void chain_pairs_c(const ChainLds& L, const ChainShape& Z, int M, int first,
+                                              int stride, float hold_scale) {
 #pragma clang fp contract(off)
-  const int DS = D + 1;
 #pragma unroll 4
-  for (int i = first; i < M * D; i += stride) {
-    const int m = div_small(i, inv_d);
-    const int d = i - m * D;
-    const int k = L.kq[i];
-    const int h = L.hold[m * DS + d] + k;
-    L.hold[m * DS + d] = h;
-    L.qty[m * DS + d] += k;
-    L.env[m * DS + 1 + d] = static_cast<float>(h) * hold_scale;
-    L.val[i] = static_cast<double>(L.pn[d]) * static_cast<double>(h);
+  for (int i = first; i < M * Z.DP; i += stride) {
+    const int m = div_small(i, Z.inv_dp);
+    const int d = i - m * Z.DP;
+    double v = 0.0;
+    if (d < Z.D) {
+      const int e = m * Z.D + d;
+      const int k = L.kq[m * Z.RI + d];
+      const int h = L.hold[e] + k;
+      L.hold[e] = h;
+      L.qty[e] += k;
+      L.env[m * Z.DS + 1 + d] = static_cast<float>(h) * hold_scale;
+      v = static_cast<double>(L.pn[d]) * static_cast<double>(h);
+    }
+    L.val[m * Z.RD + d] = v;
   }
 }
 
 // Phase D (lane m): v = cash + sum_d p'_d h_d in ascending stock order.
-__device__ __forceinline__ double chain_value(double cash, const double* __restrict__ val, int D) {
-#pragma clang fp contract(off)
-  double acc = cash;
-#pragma unroll 8
-  for (int d = 0; d < D; ++d) acc = acc + val[d];
-  return acc;
+__device__ __forceinline__ double chain_value(double cash, const double* __restrict__ val, int DP) {
+  return chain_sum(cash, val, DP);
 }
 
-// Holdings entries and values without trading (reset / observe): all threads.
-__device__ __forceinline__ void chain_pairs_hold(const ChainLds& L, int M, int D, int first, int stride,
-                                                 float inv_d, float hold_scale) {
+// Holdings entries and position values without trading (reset / observe): all threads.
+__device__ __forceinline__ void chain_pairs_hold(const ChainLds& L, const ChainShape& Z, int M, int first,
+                                                 int stride, float hold_scale) {
 #pragma clang fp contract(off)
-  const int DS = D + 1;
-  for (int i = first; i < M * D; i += stride) {
-    const int m = div_small(i, inv_d);
-    const int d = i - m * D;
-    const int h = L.hold[m * DS + d];
-    L.env[m * DS + 1 + d] = static_cast<float>(h) * hold_scale;
-    L.val[i] = static_cast<double>(L.pn[d]) * static_cast<double>(h);
+  for (int i = first; i < M * Z.DP; i += stride) {
+    const int m = div_small(i, Z.inv_dp);
+    const int d = i - m * Z.DP;
+    double v = 0.0;
+    if (d < Z.D) {
+      const int h = L.hold[m * Z.D + d];
+      L.env[m * Z.DS + 1 + d] = static_cast<float>(h) * hold_scale;
+      v = static_cast<double>(L.pn[d]) * static_cast<double>(h);
+    }
+    L.val[m * Z.RD + d] = v;
   }
 }
 

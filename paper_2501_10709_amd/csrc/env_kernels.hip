@@ -1,15 +1,13 @@
 // Environment kernels: reset, step (caller actions or ensemble means plus noise), the
 // multi-step driven rollout, state copies, and the noise probe.
 //
-// Thread mapping.  A workgroup is one 64-lane wavefront that owns M consecutive environments
-// (M <= 64).  Lane m < M runs environment n0+m's trading chain, which is serial in the stock
-// index because cash after stock d decides the fill of stock d+1 (sells then buys, ascending).
-// All 64 lanes stage the tile's actions from HBM into LDS and write the tile's states,
-// executed quantities and actions back with consecutive lanes on consecutive addresses: a
-// tile's rows are contiguous in the [N][.] layouts, so every wave-wide load or store covers a
-// contiguous run of 256 bytes.  The state entries shared by all environments (prices and
-// indicators of the new day) are read once per lane per step from LDS; only cash and holdings
-// differ between the rows.
+// Thread mapping.  A workgroup owns M consecutive environments (M <= 64) and runs three
+// wavefronts with one role each (below).  Lane m < M of the chain wavefront runs environment
+// n0+m's trading chain, which is serial in the stock index because cash after stock d decides
+// the fill of stock d+1 (sells then buys, ascending); the cash-independent terms are computed by
+// all 64 lanes over the (env, stock) pairs.  A tile's rows are contiguous in every [N][.] layout,
+// so the loads of its actions and the stores of its states, quantities and actions are
+// wave-wide runs of consecutive addresses.
 #include "device_common.h"
 #include "launch.h"
 
@@ -18,7 +16,9 @@ namespace fm {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kPrefetch = 8;  // registers per lane for the next step's inputs (512 values)
+constexpr int kStage = 16;       // registers per fetch lane holding a later step's inputs
+constexpr int kInBufs = 3;       // input buffers: fetched (t+1), in use (t), being stored (t-1)
+constexpr size_t kMaxLds = 160 * 1024;
 
 enum Mode { kReset = 0, kGiven = 1, kEnsemble = 2, kObserve = 3 };
 constexpr bool trades(int mode) { return mode == kGiven || mode == kEnsemble; }
@@ -40,70 +40,74 @@ struct StepArgs {
   int* qty;            // [n_steps][N][D] or null
 };
 
-// Market entries of the step in flat order: close[t] (D), close[t+1] (D), ind[t+1] (I*D).
-__device__ __forceinline__ float market_entry(const EnvConst& C, int t, int tn, int i, bool with_trade) {
-  const int D = C.D;
-  if (i < D) return with_trade ? C.close[static_cast<size_t>(t) * D + i] : 0.0f;
-  if (i < 2 * D) return C.close[static_cast<size_t>(tn) * D + (i - D)];
-  return C.ind[static_cast<size_t>(tn) * C.I * D + (i - 2 * D)];
+__host__ __device__ inline size_t align16(size_t b) { return (b + 15) / 16 * 16; }
+
+// One step's inputs as one LDS buffer, in the order of the flat fetch index:
+// [close[t] (D) | close[t+1] (D) | ind[t+1] (I*D) | the tile's actions (M*D)], at least DP floats.
+__host__ __device__ inline size_t in_buf_floats(int M, int D, int I) {
+  const size_t n = static_cast<size_t>(2 + I) * D + static_cast<size_t>(M) * D;
+  const size_t dp = ChainShape::of(D).DP;
+  return align16(sizeof(float) * (n > dp ? n : dp)) / sizeof(float);
 }
 
 // LDS bytes of one workgroup of env_tile_kernel.
 __host__ __device__ inline size_t tile_lds_bytes(int M, int D, int I) {
-  const size_t DS = D + 1;
-  return sizeof(double) * M                // rewards
-         + sizeof(double) * M * D * 3      // chain scratch: proceeds, debits, position values
-         + sizeof(int) * M * D * 2         // chain scratch: whole orders, fills
-         + sizeof(float) * M * DS * 2      // actions, two buffers
-         + sizeof(float) * M * DS * 4      // hold, qty, env, eps
-         + sizeof(float) * 4 * D           // closes of the trading day and the new day, two buffers
-         + sizeof(float) * 2 * (1 + I) * D;  // new-day state entries, two buffers
+  const ChainShape Z = ChainShape::of(D);
+  return Z.scratch_bytes(M)                                   // chain scratch
+         + 2 * align16(sizeof(double) * M)                    // rewards, two buffers
+         + align16(sizeof(int) * M * D)                       // holdings
+         + align16(sizeof(float) * M * D)                     // noise
+         + 2 * align16(sizeof(int) * M * D)                   // executed shares, two buffers
+         + 2 * align16(sizeof(float) * M * Z.DS)              // state entries, two buffers
+         + kInBufs * sizeof(float) * in_buf_floats(M, D, I);  // inputs
 }
 
 // Three wavefronts per workgroup, one role each:
-//   wavefront 0 (chain): the trading chains of the tile's M environments (lane m owns
-//     environment m; holdings stay in LDS) -- LDS traffic only inside the step loop;
-//   wavefront 1 (store): the step's results (states, quantities, rewards) from LDS to HBM;
-//   wavefront 2 (fetch): the next step's inputs (actions, market rows) from HBM into the other
-//     half of double-buffered LDS.
-// Vector-memory completions are counted per wavefront in issue order, so a wavefront that mixed
-// these roles would wait for stores and prefetches whenever it needed any loaded value; with the
-// roles split, the chain never waits on HBM.  Loops over stocks stay rolled so that the whole
-// step fits the instruction cache.
+//   wavefront 0 (chain): step t of the tile's M environments (holdings stay in LDS);
+//   wavefront 1 (store): the results of step t-1 (states, quantities, rewards) from LDS to HBM;
+//   wavefront 2 (fetch): writes step t+1's inputs into LDS from registers and requests step
+//     t+2's inputs from HBM into those registers.
+// One workgroup barrier per step separates them: the results are double-buffered and the inputs
+// triple-buffered, so no role waits for another inside a step.  Vector-memory completions are
+// counted per wavefront in issue order, so with the roles split the chain never waits on HBM and
+// the store wavefront never waits for the fetches.
 template <int MODE>
 __global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvState st, StepArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & (kWave - 1);
   const int role = threadIdx.x / kWave;  // 0 chain, 1 store, 2 fetch
   const int D = C.D, S = C.S, N = C.N, DS = D + 1;
-  const int n0 = blockIdx.x * A.M;
-  const int M = min(A.M, N - n0);
-  const float inv_d = 1.0f / static_cast<float>(D);
+  const ChainShape Z = ChainShape::of(D);
+  const int MM = A.M;                    // rows allocated per workgroup
+  const int n0 = blockIdx.x * MM;
+  const int M = min(MM, N - n0);         // rows of this workgroup
   const int MD = M * D;
   const int n_mkt = (2 + C.I) * D;
-  const int n_new = (1 + C.I) * D;  // scaled new close + new indicators
+  const int IB = static_cast<int>(in_buf_floats(MM, D, C.I));
 
-  double* s_rew = reinterpret_cast<double*>(smem);
-  double* s_pro = s_rew + A.M;
-  double* s_deb = s_pro + A.M * D;
-  double* s_val = s_deb + A.M * D;
-  int* s_qd = reinterpret_cast<int*>(s_val + A.M * D);
-  int* s_kq = s_qd + A.M * D;
-  float* s_act0 = reinterpret_cast<float*>(s_kq + A.M * D);  // two buffers of [M][DS]
-  int* s_hold = reinterpret_cast<int*>(s_act0 + 2 * A.M * DS);
-  int* s_qty = s_hold + A.M * DS;
-  float* s_env = reinterpret_cast<float*>(s_qty + A.M * DS);  // [cash, h_0..h_{D-1}] per env
-  float* s_eps = s_env + A.M * DS;
-  float* s_px0 = s_eps + A.M * DS;   // two buffers of [D]
-  float* s_pn0 = s_px0 + 2 * D;      // two buffers of [D]
-  float* s_mkt0 = s_pn0 + 2 * D;     // two buffers of [n_new]
+  ChainLds CL{};
+  unsigned char* p = CL.carve_scratch(smem, Z, MM);
+  double* s_rew0 = reinterpret_cast<double*>(p);
+  const int RB = static_cast<int>(align16(sizeof(double) * MM) / sizeof(double));
+  p += 2 * align16(sizeof(double) * MM);
+  int* s_hold = reinterpret_cast<int*>(p);
+  p += align16(sizeof(int) * MM * D);
+  float* s_eps = reinterpret_cast<float*>(p);
+  p += align16(sizeof(float) * MM * D);
+  int* s_qty0 = reinterpret_cast<int*>(p);
+  const int QB = static_cast<int>(align16(sizeof(int) * MM * D) / sizeof(int));
+  p += 2 * align16(sizeof(int) * MM * D);
+  float* s_env0 = reinterpret_cast<float*>(p);
+  const int EB = static_cast<int>(align16(sizeof(float) * MM * DS) / sizeof(float));
+  p += 2 * align16(sizeof(float) * MM * DS);
+  float* s_in0 = reinterpret_cast<float*>(p);
 
   // The tile's trading state: cash, asset, cumulative reward in the chain wavefront's registers,
   // holdings in LDS.
   double cash = 0.0, asset = 0.0, cumrew = 0.0;
   const bool active = role == 0 && lane < M;
   const int n = n0 + lane;
-  int* hrow = s_hold + lane * DS;
+  int* hrow = s_hold + lane * D;
   if (MODE == kReset) {
     cash = C.init_cash;
     if (active)
@@ -116,150 +120,156 @@ __global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvStat
   }
 
   const int n_iter = trades(MODE) ? A.n_steps : 1;
-  // Fetch wavefront: inputs of step it into buffer it & 1.  One flat index runs over the
-  // trading-day closes (D), the new-day closes (D), the new-day indicators (I*D) and, in driven
-  // mode, the tile's actions (M*D); each batch issues all its loads before any LDS write.
-  auto fetch_into = [&](int it) {
-    const int b = it & 1;
+  const int total = n_mkt + ((MODE == kGiven) ? MD : 0);  // fetched floats per step
+  const int staged = min(total, kStage * kWave);
+
+  // Fetch wavefront.  Flat index i of step it's inputs: close[t] (D; zeros when not trading),
+  // close[tn] (D), ind[tn] (I*D), then, driven, the tile's actions (M*D) -- which is also the
+  // layout of the LDS buffer.
+  auto src_of = [&](int it, int i) -> const float* {
     const int t = A.t0 + it;
     const int tn = trades(MODE) ? t + 1 : A.t0;
-    float* px = s_px0 + b * D;
-    float* pn = s_pn0 + b * D;
-    float* mkt = s_mkt0 + b * n_new;
-    float* act = s_act0 + b * A.M * DS;
-    const float* c_t = C.close + static_cast<size_t>(t) * D;
-    const float* c_n = C.close + static_cast<size_t>(tn) * D;
-    const float* ind = C.ind + static_cast<size_t>(tn) * C.I * D;
-    // The tile's actions (driven mode); flat index i >= n_mkt is action i - n_mkt.
-    const float* acts = (MODE == kGiven) ? A.act + (static_cast<size_t>(it) * N + n0) * D : C.close;
-
-    const int total = n_mkt + ((MODE == kGiven) ? MD : 0);
-    for (int i0 = 0; i0 < total; i0 += kPrefetch * kWave) {
-      float v[kPrefetch];
+    if (i < D) return C.close + static_cast<size_t>(t) * D + i;
+    if (i < 2 * D) return C.close + static_cast<size_t>(tn) * D + (i - D);
+    if (i < n_mkt) return C.ind + static_cast<size_t>(tn) * C.I * D + (i - 2 * D);
+    return A.act + (static_cast<size_t>(it) * N + n0) * D + (i - n_mkt);
+  };
+  float stage[kStage];
+  auto fetch_issue = [&](int it) {
 #pragma unroll
-      for (int j = 0; j < kPrefetch; ++j) {
-        const int i = i0 + lane + kWave * j;
-        const float* src = i < D ? c_t + i : (i < 2 * D ? c_n + (i - D) : (i < n_mkt ? ind + (i - 2 * D) : acts + (i - n_mkt)));
-        v[j] = (i < total && (i >= D || trades(MODE))) ? *src : 0.0f;
-      }
-#pragma unroll
-      for (int j = 0; j < kPrefetch; ++j) {
-        const int i = i0 + lane + kWave * j;
-        if (i >= total) {
-        } else if (i < D) {
-          px[i] = v[j];
-        } else if (i < 2 * D) {
-          pn[i - D] = v[j];
-          mkt[i - D] = v[j] * C.price_scale;
-        } else if (i < n_mkt) {
-          mkt[i - D] = v[j];
-        } else {
-          const int k = i - n_mkt;
-          const int m = div_small(k, inv_d);
-          act[m * DS + (k - m * D)] = v[j];
-        }
-      }
+    for (int j = 0; j < kStage; ++j) {
+      const int i = lane + kWave * j;
+      stage[j] = (i < staged && (i >= D || trades(MODE))) ? *src_of(it, i) : 0.0f;
     }
   };
+  auto fetch_commit = [&](int it) {
+    float* buf = s_in0 + (it % kInBufs) * IB;
+#pragma unroll
+    for (int j = 0; j < kStage; ++j) {
+      const int i = lane + kWave * j;
+      if (i < staged) buf[i] = stage[j];
+    }
+    for (int i = staged + lane; i < total; i += kWave) buf[i] = *src_of(it, i);  // large tiles
+  };
 
-  if (role == 2) fetch_into(0);
+  if (role == 2) {
+    fetch_issue(0);
+    fetch_commit(0);
+    if (n_iter > 1) fetch_issue(1);
+  }
   __syncthreads();
 
-  for (int it = 0; it < n_iter; ++it) {
-    const int t = A.t0 + it;
-    const int b = it & 1;
-    float* s_act = s_act0 + b * A.M * DS;
-    const float* s_px = s_px0 + b * D;
-    const float* s_pn = s_pn0 + b * D;
+  for (int it = 0; it <= n_iter; ++it) {
     if (role == 0) {
-      if (MODE == kEnsemble) {
-        // Noise: one Philox block per (env, group of 4 stocks).
-        const int G = (D + 3) >> 2;
-        const float inv_g = 1.0f / static_cast<float>(G);
-        if (A.sigma != 0.0f) {
-          for (int i = lane; i < M * G; i += kWave) {
-            const int m = div_small(i, inv_g);
-            const int g = i - m * G;
-            float z[4];
-            noise_block(A.noise_key, static_cast<uint64_t>(A.env_offset + n0 + m),
-                        static_cast<uint64_t>(t), static_cast<uint64_t>(g), z);
+      if (it < n_iter) {
+        const int t = A.t0 + it;
+        float* in = s_in0 + (it % kInBufs) * IB;
+        CL.act = in + n_mkt;
+        CL.px = in;
+        CL.pn = in + D;
+        CL.hold = s_hold;
+        CL.qty = s_qty0 + (it & 1) * QB;
+        CL.env = s_env0 + (it & 1) * EB;
+        double* s_rew = s_rew0 + (it & 1) * RB;
+        if (MODE == kEnsemble) {
+          float* act = in + n_mkt;
+          // Noise: one Philox block per (env, group of 4 stocks).
+          const int G = (D + 3) >> 2;
+          const float inv_g = 1.0f / static_cast<float>(G);
+          const float inv_d = 1.0f / static_cast<float>(D);
+          if (A.sigma != 0.0f) {
+            for (int i = lane; i < M * G; i += kWave) {
+              const int m = div_small(i, inv_g);
+              const int g = i - m * G;
+              float z[4];
+              noise_block(A.noise_key, static_cast<uint64_t>(A.env_offset + n0 + m),
+                          static_cast<uint64_t>(t), static_cast<uint64_t>(g), z);
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (4 * g + r < D) s_eps[m * DS + 4 * g + r] = z[r];
+              for (int r = 0; r < 4; ++r)
+                if (4 * g + r < D) s_eps[m * D + 4 * g + r] = z[r];
+            }
+          }
+          wave_lds_sync();
+          for (int i = lane; i < MD; i += kWave) {
+            float acc = 0.0f;
+            for (int k = 0; k < A.K; ++k)
+              acc = acc + A.mix[k] * A.mu[(static_cast<size_t>(k) * N + n0) * D + i];
+            float a = acc;
+            if (A.sigma != 0.0f) a = acc + A.sigma * s_eps[i];
+            a = fminf(fmaxf(a, -1.0f), 1.0f);
+            act[i] = a;
+          }
+          (void)inv_d;
+        }
+        // The chain: parallel pre-terms, serial cash recurrence per env, parallel post-terms.
+        wave_lds_sync();
+        if (trades(MODE)) {
+          chain_pairs_a(CL, Z, M, lane, kWave, C.hmax_f, C.one_m, C.one_p);
+          wave_lds_sync();
+          if (active)
+            chain_serial(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.val + lane * Z.RD,
+                         CL.qd + lane * Z.RI, CL.px, CL.kq + lane * Z.RI, Z.DP, C.one_p);
+          wave_lds_sync();
+          chain_pairs_c(CL, Z, M, lane, kWave, C.hold_scale);
+        } else {
+          chain_pairs_hold(CL, Z, M, lane, kWave, C.hold_scale);
+        }
+        wave_lds_sync();
+        if (active) {
+          const double v_new = chain_value(cash, CL.val + lane * Z.RD, Z.DP);
+          if (trades(MODE)) {
+            const double r = (v_new - asset) * C.reward_scale;
+            cumrew = cumrew + r;
+            s_rew[lane] = r;
+          }
+          if (MODE != kObserve) asset = v_new;
+          CL.env[lane * DS] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
+        }
+      }
+    } else if (role == 1) {
+      if (it >= 1) {
+        // Results of step j = it - 1: the tile's rows are contiguous in every [N][.] trajectory.
+        const int j = it - 1;
+        const float* in = s_in0 + (j % kInBufs) * IB;
+        const int* qty = s_qty0 + (j & 1) * QB;
+        const float* env = s_env0 + (j & 1) * EB;
+        const size_t row0 = static_cast<size_t>(j) * N + n0;
+        if (trades(MODE)) {
+          const double* s_rew = s_rew0 + (j & 1) * RB;
+          if (A.rew && lane < M) A.rew[row0 + lane] = s_rew[lane];
+          if (MODE == kEnsemble && A.act_out)
+            wave_store_row(A.act_out + row0 * D, MD, lane, [&](int i) { return in[n_mkt + i]; });
+          if (A.qty) wave_store_row(A.qty + row0 * D, MD, lane, [&](int i) { return qty[i]; });
+        }
+        // States s_{t+1} = [cash, new closes, holdings, new indicators]: lane f writes entry f
+        // (f, f+64, ...) of every row, so each store covers a contiguous run of the tile.
+        if (A.obs) {
+          for (int f = lane; f < S; f += kWave) {
+            const float* src;
+            int stride = 0;
+            float scale = 1.0f;
+            if (f == 0) {
+              src = env;
+              stride = DS;
+            } else if (f <= D) {
+              src = in + D + (f - 1);
+              scale = C.price_scale;
+            } else if (f <= 2 * D) {
+              src = env + (f - D);
+              stride = DS;
+            } else {
+              src = in + (f - 1);  // ind[tn][f-1-2D]
+            }
+            float* dst = A.obs + row0 * S + f;
+#pragma unroll 8
+            for (int m = 0; m < M; ++m) dst[static_cast<size_t>(m) * S] = src[m * stride] * scale;
           }
         }
-        wave_lds_sync();
-        for (int i = lane; i < MD; i += kWave) {
-          const int m = div_small(i, inv_d);
-          const int d = i - m * D;
-          float acc = 0.0f;
-          for (int k = 0; k < A.K; ++k)
-            acc = acc + A.mix[k] * A.mu[(static_cast<size_t>(k) * N + n0) * D + i];
-          float a = acc;
-          if (A.sigma != 0.0f) a = acc + A.sigma * s_eps[m * DS + d];
-          a = fminf(fmaxf(a, -1.0f), 1.0f);
-          s_act[m * DS + d] = a;
-        }
       }
-      // The chain: parallel pre-terms, serial cash recurrence per env, parallel post-terms.
-      const ChainLds CL{s_act, s_hold, s_qty, s_env, s_px, s_pn, s_pro, s_deb, s_val, s_qd, s_kq};
-      wave_lds_sync();
-      if (trades(MODE)) {
-        chain_pairs_a(CL, M, D, lane, kWave, inv_d, C.hmax_f, C.one_m, C.one_p);
-        wave_lds_sync();
-        if (active)
-          chain_serial(cash, s_pro + lane * D, s_deb + lane * D, s_val + lane * D, s_qd + lane * D, s_px,
-                       s_kq + lane * D, D, C.one_p);
-        wave_lds_sync();
-        chain_pairs_c(CL, M, D, lane, kWave, inv_d, C.hold_scale);
-      } else {
-        chain_pairs_hold(CL, M, D, lane, kWave, inv_d, C.hold_scale);
-      }
-      wave_lds_sync();
-      if (active) {
-        const double v_new = chain_value(cash, s_val + lane * D, D);
-        if (trades(MODE)) {
-          const double r = (v_new - asset) * C.reward_scale;
-          cumrew = cumrew + r;
-          s_rew[lane] = r;
-        }
-        if (MODE != kObserve) asset = v_new;
-        s_env[lane * DS] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
-      }
-    } else if (role == 2 && it + 1 < n_iter) {
-      fetch_into(it + 1);  // the other buffer: nobody reads it during this step
-    }
-    __syncthreads();
-
-    if (role == 1) {
-      // Results of step it: the tile's rows are contiguous in every [N][.] trajectory.
-      const size_t row0 = static_cast<size_t>(it) * N + n0;
-      if (trades(MODE)) {
-        if (A.rew && lane < M) A.rew[row0 + lane] = s_rew[lane];
-        if (MODE == kEnsemble && A.act_out)
-          wave_store_row(A.act_out + row0 * D, MD, lane, [&](int i) {
-            const int m = div_small(i, inv_d);
-            return s_act[m * DS + (i - m * D)];
-          });
-        if (A.qty)
-          wave_store_row(A.qty + row0 * D, MD, lane, [&](int i) {
-            const int m = div_small(i, inv_d);
-            return s_qty[m * DS + (i - m * D)];
-          });
-      }
-      // States s_{t+1} = [cash, new closes, holdings, new indicators], one row per env.
-      if (A.obs) {
-        const float* mkt = s_mkt0 + b * n_new;
-        const float inv_s = 1.0f / static_cast<float>(S);
-        wave_store_row(A.obs + row0 * S, M * S, lane, [&](int e) {
-          const int m = div_small(e, inv_s);
-          const int f = e - m * S;
-          const float* erow = s_env + m * DS;
-          if (f == 0) return erow[0];
-          if (f <= D) return mkt[f - 1];
-          if (f <= 2 * D) return erow[f - D];
-          return mkt[f - 1 - D];
-        });
+    } else {
+      if (it + 1 < n_iter) {
+        fetch_commit(it + 1);
+        if (it + 2 < n_iter) fetch_issue(it + 2);
       }
     }
     __syncthreads();
@@ -277,7 +287,9 @@ __global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvStat
 template <int MODE>
 hipError_t dispatch_tile(const EnvConst& C, const EnvState& st, StepArgs A, hipStream_t stream) {
   A.M = max(1, min(A.M, 64));
+  while (A.M > 1 && tile_lds_bytes(A.M, C.D, C.I) > kMaxLds) A.M /= 2;
   const size_t lds = tile_lds_bytes(A.M, C.D, C.I);
+  if (lds > kMaxLds) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(env_tile_kernel<MODE>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));

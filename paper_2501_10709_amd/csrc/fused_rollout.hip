@@ -50,44 +50,48 @@ __device__ __forceinline__ void static_for(Fn&& f) {
 struct FusedLds {
   __bf16 *x0, *x1, *x2;  // state rows, layer-1 and layer-2 outputs
   float* abar;           // [MR][DS] ensemble mean
-  float* act;            // [MR][DS] noisy clipped action
-  int* hold;             // [MR][DS] holdings (the trading state, resident for the whole rollout)
-  int* qty;              // [MR][DS] executed shares
+  float* act;            // [MR][D] noisy clipped action
+  int* hold;             // [MR][D] holdings (the trading state, resident for the whole rollout)
+  int* qty;              // [MR][D] executed shares
   float* env;            // [MR][DS] cash entry, holdings entries of the state rows
-  float *px, *pn;        // [D] closes of the trading day / new day
+  float *px, *pn;        // closes of the trading day ([DP], entries beyond D unused) / new day [D]
   float* mkt;            // [(1+I)*D] scaled new close, new indicators
-
-  double *pro, *deb, *val;  // [MR][D] chain scratch
-  int *qd, *kq;             // [MR][D] chain scratch
+  ChainLds chain;        // the chain's scratch and the views above
 
   __host__ __device__ static size_t bytes(int MR, int st0, int sth, int D, int I) {
+    const ChainShape Z = ChainShape::of(D);
     const size_t DS = D + 1;
-    size_t b = sizeof(double) * MR * D * 3 + sizeof(int) * MR * D * 2;
+    size_t b = Z.scratch_bytes(MR);
     b += sizeof(__bf16) * MR * (static_cast<size_t>(st0) + 2 * sth);
-    b += sizeof(float) * MR * DS * 5;
-    b += sizeof(float) * (2 * D + (1 + I) * D);
-    return (b + 16 + 15) / 16 * 16;
+    b += sizeof(float) * MR * DS * 2 + sizeof(int) * MR * D * 2 + sizeof(float) * MR * D;
+    b += sizeof(float) * (Z.DP + D + (1 + I) * D);
+    return (b + 64 + 15) / 16 * 16;
   }
   __device__ void carve(unsigned char* smem, int MR, int st0, int sth, int D) {
+    const ChainShape Z = ChainShape::of(D);
     const int DS = D + 1;
-    pro = reinterpret_cast<double*>(smem);
-    deb = pro + MR * D;
-    val = deb + MR * D;
-    qd = reinterpret_cast<int*>(val + MR * D);
-    kq = qd + MR * D;
+    unsigned char* p = chain.carve_scratch(smem, Z, MR);
     // 16-byte alignment for the bf16 MFMA operand rows.
-    const size_t off = (reinterpret_cast<uintptr_t>(kq + MR * D) - reinterpret_cast<uintptr_t>(smem) + 15) / 16 * 16;
+    const size_t off = (static_cast<size_t>(p - smem) + 15) / 16 * 16;
     x0 = reinterpret_cast<__bf16*>(smem + off);
     x1 = x0 + MR * st0;
     x2 = x1 + MR * sth;
     abar = reinterpret_cast<float*>(x2 + MR * sth);
-    act = abar + MR * DS;
-    hold = reinterpret_cast<int*>(act + MR * DS);
-    qty = hold + MR * DS;
-    env = reinterpret_cast<float*>(qty + MR * DS);
-    px = env + MR * DS;
-    pn = px + D;
+    env = abar + MR * DS;
+    act = env + MR * DS;
+    hold = reinterpret_cast<int*>(act + MR * D);
+    qty = hold + MR * D;
+    // px: 16-byte aligned for the serial phase's vector reads.
+    const size_t poff = (reinterpret_cast<uintptr_t>(qty + MR * D) - reinterpret_cast<uintptr_t>(smem) + 15) / 16 * 16;
+    px = reinterpret_cast<float*>(smem + poff);
+    pn = px + Z.DP;
     mkt = pn + D;
+    chain.act = act;
+    chain.hold = hold;
+    chain.qty = qty;
+    chain.env = env;
+    chain.px = px;
+    chain.pn = pn;
   }
 };
 
@@ -130,7 +134,7 @@ struct EnvPhase {
           float a = L.abar[m * DS + d];
           if (F.sigma != 0.0f) a = a + F.sigma * z[r];
           a = fminf(fmaxf(a, -1.0f), 1.0f);
-          L.act[m * DS + d] = a;
+          L.act[m * D + d] = a;
           if (F.act_traj) F.act_traj[(row_base + m) * D + d] = a;
         }
       }
@@ -142,7 +146,7 @@ struct EnvPhase {
     if (!owner) return;
     const int D = C.D, DS = D + 1;
     float* erow = L.env + lane * DS;
-    const int* hrow = L.hold + lane * DS;
+    const int* hrow = L.hold + lane * D;
     erow[0] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
     for (int d = 0; d < D; ++d) erow[1 + d] = static_cast<float>(hrow[d]) * C.hold_scale;
   }
@@ -151,23 +155,23 @@ struct EnvPhase {
   // (owner lanes), parallel post-terms (all threads).  Returns the reward in the owner lanes.
   // Entered and left with all threads synchronised.
   __device__ double chain(bool owner, double& cash, double& asset, double& cumrew) {
-    const int D = C.D;
-    const ChainLds CL{L.act, L.hold, L.qty, L.env, L.px, L.pn, L.pro, L.deb, L.val, L.qd, L.kq};
-    chain_pairs_a(CL, M, D, tid, NT, inv_d, C.hmax_f, C.one_m, C.one_p);
+    const ChainShape Z = ChainShape::of(C.D);
+    const ChainLds& CL = L.chain;
+    chain_pairs_a(CL, Z, M, tid, NT, C.hmax_f, C.one_m, C.one_p);
     __syncthreads();
     if (owner)
-      chain_serial(cash, L.pro + lane * D, L.deb + lane * D, L.val + lane * D, L.qd + lane * D, L.px,
-                   L.kq + lane * D, D, C.one_p);
+      chain_serial(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.val + lane * Z.RD, CL.qd + lane * Z.RI,
+                   CL.px, CL.kq + lane * Z.RI, Z.DP, C.one_p);
     __syncthreads();
-    chain_pairs_c(CL, M, D, tid, NT, inv_d, C.hold_scale);
+    chain_pairs_c(CL, Z, M, tid, NT, C.hold_scale);
     __syncthreads();
     double r = 0.0;
     if (owner) {
-      const double v_new = chain_value(cash, L.val + lane * D, D);
+      const double v_new = chain_value(cash, CL.val + lane * Z.RD, Z.DP);
       r = (v_new - asset) * C.reward_scale;
       cumrew = cumrew + r;
       asset = v_new;
-      L.env[lane * (D + 1)] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
+      L.env[lane * Z.DS] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
     }
     return r;
   }
@@ -192,11 +196,8 @@ struct EnvPhase {
 
   __device__ void quantities(size_t row_base) {
     if (!F.qty_traj) return;
-    const int D = C.D, DS = D + 1;
-    for (int i = tid; i < M * D; i += NT) {
-      const int m = div_small(i, inv_d);
-      F.qty_traj[row_base * D + i] = L.qty[m * DS + (i - m * D)];
-    }
+    const int D = C.D;
+    for (int i = tid; i < M * D; i += NT) F.qty_traj[row_base * D + i] = L.qty[i];
   }
 
   // Load the tile's state into the owner lanes (holdings into LDS).
@@ -206,7 +207,7 @@ struct EnvPhase {
     cash = st.cash[n];
     asset = st.asset[n];
     cumrew = st.cumrew[n];
-    for (int d = 0; d < D; ++d) L.hold[lane * DS + d] = st.hold[static_cast<size_t>(d) * N + n];
+    for (int d = 0; d < D; ++d) L.hold[lane * D + d] = st.hold[static_cast<size_t>(d) * N + n];
   }
   __device__ void store_state(bool owner, const EnvState& st, double cash, double asset, double cumrew) {
     if (!owner) return;
@@ -214,7 +215,7 @@ struct EnvPhase {
     st.cash[n] = cash;
     st.asset[n] = asset;
     st.cumrew[n] = cumrew;
-    for (int d = 0; d < D; ++d) st.hold[static_cast<size_t>(d) * N + n] = L.hold[lane * DS + d];
+    for (int d = 0; d < D; ++d) st.hold[static_cast<size_t>(d) * N + n] = L.hold[lane * D + d];
   }
 };
 
