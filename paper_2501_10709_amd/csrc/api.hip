@@ -38,7 +38,7 @@ int env_tile(int N) {
 }
 
 struct EnvLayout {
-  size_t cash, asset, cumrew, hold, act, obs, total;
+  size_t cash, asset, cumrew, hold, act, obs, eps, mt, total;
 };
 
 EnvLayout env_layout(const fm_env_config& c) {
@@ -57,6 +57,11 @@ EnvLayout env_layout(const fm_env_config& c) {
   off = align_up(off + sizeof(float) * static_cast<size_t>(c.n_stocks) * c.n_envs);
   L.obs = off;
   off = align_up(off + sizeof(float) * static_cast<size_t>(S) * c.n_envs);
+  // Scratch of the fused rollout's streamed schedule (noise and market table of a chunk).
+  L.eps = off;
+  off = align_up(off + sizeof(float) * fm::fused_eps_floats(c.n_envs, c.n_stocks));
+  L.mt = off;
+  off = align_up(off + sizeof(float) * fm::fused_table_floats());
   L.total = off;
   return L;
 }
@@ -99,6 +104,8 @@ struct fm_env {
   fm::EnvState st;
   float* act_stage;
   float* obs_stage;
+  float* eps_chunk;
+  float* mt_chunk;
   hipStream_t stream;
   int device;
   int day;
@@ -114,9 +121,15 @@ struct fm_ensemble {
 namespace {
 
 struct EnsLayout {
-  int S_pad, A_pad;
-  size_t w1, w2, w3, b1, b2, b3, actor, mix, mu, total;
+  int S_pad, A_pad, split_a, ke_pad;
+  size_t w1, w2, w3, b1, b2, b3, actor, mix, mu, w1e, w1m, total;
 };
+
+// The split first layer applies to bfloat16 ensembles over a trading state
+// [cash, closes(A), holdings(A), indicators(I*A)].
+bool splits_first_layer(int S, int A, int dtype) {
+  return dtype == FM_BF16 && A >= 1 && (S - 1) % A == 0 && (S - 1) / A >= 2 && 1 + A <= 64;
+}
 
 EnsLayout ens_layout(int K, int S, int H, int A, int dtype, int max_batch) {
   EnsLayout L{};
@@ -140,7 +153,16 @@ EnsLayout ens_layout(int K, int S, int H, int A, int dtype, int max_batch) {
   L.actor = off;
   L.mix = L.actor * K;
   L.mu = align_up(L.mix + 4 * 8);
-  L.total = align_up(L.mu + sizeof(float) * static_cast<size_t>(K) * max_batch * A);
+  off = align_up(L.mu + sizeof(float) * static_cast<size_t>(K) * max_batch * A);
+  if (splits_first_layer(S, A, dtype)) {
+    L.split_a = A;
+    L.ke_pad = fm::round_up(1 + A, 32);
+    L.w1e = off;
+    off = align_up(off + 2 * static_cast<size_t>(K) * H * L.ke_pad);
+    L.w1m = off;
+    off = align_up(off + 2 * static_cast<size_t>(K) * (S - 1 - A) * H);
+  }
+  L.total = off;
   return L;
 }
 
@@ -207,6 +229,8 @@ fm_status env_create(const fm_env_config* cfg, const float* d_close, const float
   e->st.hold = reinterpret_cast<int*>(base + L.hold);
   e->act_stage = reinterpret_cast<float*>(base + L.act);
   e->obs_stage = reinterpret_cast<float*>(base + L.obs);
+  e->eps_chunk = reinterpret_cast<float*>(base + L.eps);
+  e->mt_chunk = reinterpret_cast<float*>(base + L.mt);
   e->stream = stream;
   if (hipGetDevice(&e->device) != hipSuccess) e->device = 0;
   e->day = 0;
@@ -280,7 +304,7 @@ fm_status env_rollout(fm_env* env, const fm_ensemble* ens, int32_t n_steps,
     const hipError_t e = fm::launch_fused_rollout(C, env->st, ens->E, env->day, n_steps, opts->sigma,
                                                   opts->noise_key, opts->env_offset, opts->d_obs_traj,
                                                   opts->d_act_traj, opts->d_rew_traj, opts->d_qty_traj,
-                                                  st, &why);
+                                                  env->eps_chunk, env->mt_chunk, st, &why);
     if (!why.empty()) return fail(FM_ERR_UNSUPPORTED, why);
     fm_status s = device_status(e, "env_rollout (fused)");
     if (s != FM_OK) return s;
@@ -388,6 +412,10 @@ fm_status ensemble_create(int32_t K, int32_t S, int32_t H, int32_t A, int32_t dt
   E.off_b2 = L.b2;
   E.off_b3 = L.b3;
   E.mix = reinterpret_cast<const float*>(base + L.mix);
+  E.split_a = L.split_a;
+  E.ke_pad = L.ke_pad;
+  E.off_w1e = L.w1e;
+  E.off_w1m = L.w1m;
   e->mu = reinterpret_cast<float*>(base + L.mu);
   // Master layout per actor: W1[S][H], b1[H], W2[H][H], b2[H], W3[H][A], b3[A].
   const size_t per_actor = static_cast<size_t>(S) * H + H + static_cast<size_t>(H) * H + H +
@@ -408,6 +436,15 @@ fm_status ensemble_create(int32_t K, int32_t S, int32_t H, int32_t A, int32_t dt
     if (err == hipSuccess) err = fm::launch_copy_pad(b1, H, H, reinterpret_cast<float*>(dst + L.b1), stream);
     if (err == hipSuccess) err = fm::launch_copy_pad(b2, H, H, reinterpret_cast<float*>(dst + L.b2), stream);
     if (err == hipSuccess) err = fm::launch_copy_pad(b3, A, L.A_pad, reinterpret_cast<float*>(dst + L.b3), stream);
+    if (err == hipSuccess && L.split_a > 0) {
+      err = fm::launch_pack_env_rows(w1, A, H, L.ke_pad, base + L.w1e + 2 * static_cast<size_t>(k) * H * L.ke_pad,
+                                     stream);
+      if (err == hipSuccess)
+        err = fm::launch_gather_market_rows(w1, S, H, A,
+                                            reinterpret_cast<__bf16*>(base + L.w1m) +
+                                                static_cast<size_t>(k) * (S - 1 - A) * H,
+                                            stream);
+    }
   }
   if (err == hipSuccess)
     err = hipMemcpyAsync(base + L.mix, mix, sizeof(float) * K, hipMemcpyHostToDevice, stream);

@@ -183,7 +183,7 @@ struct ChainLds {
   int* qd;
   int* kq;
   // Carves the scratch (16-byte aligned base) of M rows; returns the first byte after it.
-  __device__ unsigned char* carve_scratch(unsigned char* base, const ChainShape& Z, int M) {
+  __host__ __device__ unsigned char* carve_scratch(unsigned char* base, const ChainShape& Z, int M) {
     pro = reinterpret_cast<double*>(base);
     deb = pro + M * Z.RD;
     val = deb + M * Z.RD;
@@ -194,19 +194,22 @@ struct ChainLds {
 };
 
 // Phase A (all threads, pairs i = first, first + stride, ... over M*DP): orders, sells, the
-// whole-order debit and the one-share debit (p*1)*(1+c).
+// whole-order debit and the reciprocal of the one-share debit c1 = (p*1)*(1+c) (refined by one
+// Newton step; only an estimate's input).  act(m, d, e)
+// yields the action of env m, stock d (e = m*D + d).
+template <class Act>
 __device__ __forceinline__ void chain_pairs_a(const ChainLds& L, const ChainShape& Z, int M, int first,
-                                              int stride, float hmax_f, double one_m, double one_p) {
+                                              int stride, float hmax_f, double one_m, double one_p, Act act) {
 #pragma clang fp contract(off)
 #pragma unroll 4
   for (int i = first; i < M * Z.DP; i += stride) {
     const int m = div_small(i, Z.inv_dp);
     const int d = i - m * Z.DP;
-    double pro = 0.0, deb = 0.0, c1 = 0.0;
+    double pro = 0.0, deb = 0.0, rc1 = 0.0;
     int qd = 0;
     if (d < Z.D) {
       const int e = m * Z.D + d;
-      const int q = order_from_action(L.act[e], hmax_f);
+      const int q = order_from_action(act(m, d, e), hmax_f);
       const int h = L.hold[e];
       const int s = q < 0 ? min(h, -q) : 0;
       const double p = static_cast<double>(L.px[d]);
@@ -215,33 +218,38 @@ __device__ __forceinline__ void chain_pairs_a(const ChainLds& L, const ChainShap
       pro = (p * static_cast<double>(s)) * one_m;
       qd = q > 0 ? q : 0;
       deb = (p * static_cast<double>(qd)) * one_p;
-      c1 = p * one_p;
+      const double c1 = p * one_p;
+      rc1 = __builtin_amdgcn_rcp(c1);
+      rc1 = fma(fma(-c1, rc1, 1.0), rc1, rc1);  // one Newton step
     }
     L.pro[m * Z.RD + d] = pro;
     L.deb[m * Z.RD + d] = deb;
-    L.val[m * Z.RD + d] = c1;  // the slot is reused for the position values in phase C
+    L.val[m * Z.RD + d] = rc1;  // the slot is reused for the position values in phase C
     L.qd[m * Z.RI + d] = qd;
   }
 }
+__device__ __forceinline__ void chain_pairs_a(const ChainLds& L, const ChainShape& Z, int M, int first,
+                                              int stride, float hmax_f, double one_m, double one_p) {
+  chain_pairs_a(L, Z, M, first, stride, hmax_f, one_m, one_p, [&](int, int, int e) { return L.act[e]; });
+}
 
-// The partial fill: c1 = (p*1)*one_p <= cash < (p*q)*one_p, so the answer is the largest k in
-// [1, q-1] with (p*k)*one_p <= cash.  The debit is monotone in k.  The estimate floor(cash/c1)
-// uses the hardware reciprocal refined by one Newton step and is within a share of the answer
-// for cash/c1 < 2^31; the unit steps after it, taken only when the two debits around the
-// estimate do not bracket cash, make the result exact whatever the estimate's error.
-__device__ __forceinline__ int partial_fill(double cash, double p, double c1, int q, double one_p,
+// The buy of one stock that does not fit whole: (p*q)*one_p > cash.  The answer is the largest k
+// in [0, q-1] with (p*k)*one_p <= cash (a zero-share buy debits nothing; q <= 0 gives 0).  The
+// debit is monotone in k.  The estimate k = floor(cash * rc1), rc1 ~ 1/((p*1)*one_p), clamped to
+// [0, max(q-1, 0)], is kept when the debits of k and k+1 bracket cash; otherwise unit steps from
+// it reach the answer, whatever the estimate's error.  k stays in float64 (an exact small integer) on the common path.
+__device__ __forceinline__ int partial_fill(double cash, double p, double rc1, int q, double one_p,
                                            double& debit) {
 #pragma clang fp contract(off)
-  double r = __builtin_amdgcn_rcp(c1);
-  r = fma(fma(-c1, r, 1.0), r, r);
-  const double est = floor(cash * r);
-  int k = static_cast<int>(fmin(fmax(est, 1.0), static_cast<double>(q - 1)));
-  double dk = (p * static_cast<double>(k)) * one_p;
-  const double dk1 = (p * static_cast<double>(k + 1)) * one_p;
-  if (dk > cash || (k + 1 < q && dk1 <= cash)) {
+  const double qm1 = static_cast<double>(q - 1);
+  const double kd = fmax(fmin(floor(cash * rc1), qm1), 0.0);
+  double dk = kd > 0.0 ? (p * kd) * one_p : 0.0;
+  const double dk1 = (p * (kd + 1.0)) * one_p;
+  int k = static_cast<int>(kd);
+  if (!(dk <= cash) || (kd < qm1 && dk1 <= cash)) {
     while (k + 1 < q && (p * static_cast<double>(k + 1)) * one_p <= cash) ++k;
-    while (k > 1 && (p * static_cast<double>(k)) * one_p > cash) --k;
-    dk = (p * static_cast<double>(k)) * one_p;
+    while (k > 0 && !((p * static_cast<double>(k)) * one_p <= cash)) --k;
+    dk = k > 0 ? (p * static_cast<double>(k)) * one_p : 0.0;
   }
   debit = dk;
   return k;
@@ -306,8 +314,8 @@ struct BuyChunk {
 };
 
 // Phase B (lane m of the owner group): the cash recurrence of environment m -- all sells, then
-// all buys, in ascending stock order.  A buy fills whole when its debit fits the cash, not at
-// all when one share does not, and partially otherwise (the one divergent branch).
+// all buys, in ascending stock order.  A buy fills whole when its debit fits the cash (a select);
+// otherwise the partial fill decides (the one divergent branch).  c1s: the reciprocals rc1.
 __device__ __forceinline__ void chain_serial(double& cash, const double* __restrict__ pro,
                                              const double* __restrict__ deb, const double* __restrict__ c1s,
                                              const int* __restrict__ qd, const float* __restrict__ px,
@@ -326,8 +334,7 @@ __device__ __forceinline__ void chain_serial(double& cash, const double* __restr
       const bool fits = cur.deb[j] <= cash;
       int kj = fits ? cur.q[j] : 0;
       double debit = fits ? cur.deb[j] : 0.0;
-      if (!fits && cur.c1[j] <= cash)
-        kj = partial_fill(cash, static_cast<double>(cur.p[j]), cur.c1[j], cur.q[j], one_p, debit);
+      if (!fits) kj = partial_fill(cash, static_cast<double>(cur.p[j]), cur.c1[j], cur.q[j], one_p, debit);
       cash = cash - debit;
       k[j] = kj;
     }
@@ -339,9 +346,11 @@ __device__ __forceinline__ void chain_serial(double& cash, const double* __restr
 }
 
 // Phase C (all threads, pairs over M*DP): apply the buys, the holdings entries of the state
-// rows, and the new day's position values p'_d h_d (zero beyond D).
+// rows (also passed to entry(m, d, value)), and the new day's position values p'_d h_d (zero
+// beyond D).
+template <class Entry>
 __device__ __forceinline__ void chain_pairs_c(const ChainLds& L, const ChainShape& Z, int M, int first,
-                                              int stride, float hold_scale) {
+                                              int stride, float hold_scale, Entry entry) {
 #pragma clang fp contract(off)
 #pragma unroll 4
   for (int i = first; i < M * Z.DP; i += stride) {
@@ -354,11 +363,17 @@ __device__ __forceinline__ void chain_pairs_c(const ChainLds& L, const ChainShap
       const int h = L.hold[e] + k;
       L.hold[e] = h;
       L.qty[e] += k;
-      L.env[m * Z.DS + 1 + d] = static_cast<float>(h) * hold_scale;
+      const float he = static_cast<float>(h) * hold_scale;
+      L.env[m * Z.DS + 1 + d] = he;
+      entry(m, d, he);
       v = static_cast<double>(L.pn[d]) * static_cast<double>(h);
     }
     L.val[m * Z.RD + d] = v;
   }
+}
+__device__ __forceinline__ void chain_pairs_c(const ChainLds& L, const ChainShape& Z, int M, int first,
+                                              int stride, float hold_scale) {
+  chain_pairs_c(L, Z, M, first, stride, hold_scale, [](int, int, float) {});
 }
 
 // Phase D (lane m): v = cash + sum_d p'_d h_d in ascending stock order.
@@ -380,6 +395,34 @@ __device__ __forceinline__ void chain_pairs_hold(const ChainLds& L, const ChainS
       v = static_cast<double>(L.pn[d]) * static_cast<double>(h);
     }
     L.val[m * Z.RD + d] = v;
+  }
+}
+
+// The state rows s_{t+1} = [cash, new closes, holdings, new indicators] of M environments from
+// LDS into dst[m][0..S) (row stride S), with one wavefront: lane f writes entry f (f, f+64, ...) of
+// every row, so each store instruction covers 64 consecutive entries.  env[m][0..D]: cash entry,
+// holdings entries (row stride DS); in: [close[t] (D) | close[t+1] (D) | ind[t+1] (I*D)].
+__device__ __forceinline__ void store_state_rows(float* dst, int M, int S, int D, const float* env, int DS,
+                                                 const float* in, float price_scale, int lane) {
+  for (int f = lane; f < S; f += 64) {
+    const float* src;
+    int stride = 0;
+    float scale = 1.0f;
+    if (f == 0) {
+      src = env;
+      stride = DS;
+    } else if (f <= D) {
+      src = in + D + (f - 1);
+      scale = price_scale;
+    } else if (f <= 2 * D) {
+      src = env + (f - D);
+      stride = DS;
+    } else {
+      src = in + (f - 1);  // ind[t+1][f-1-2D]
+    }
+    float* o = dst + f;
+#pragma unroll 8
+    for (int m = 0; m < M; ++m) o[static_cast<size_t>(m) * S] = src[m * stride] * scale;
   }
 }
 

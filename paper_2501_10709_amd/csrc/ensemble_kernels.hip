@@ -42,6 +42,37 @@ __global__ void pack_matrix_kernel(const float* __restrict__ w, int kin, int nou
   }
 }
 
+// Rows 0 and A+1..2A of W1 [S][H] (cash, holdings) as bfloat16 MFMA fragments over ke_pad rows.
+__global__ void pack_env_rows_kernel(const float* __restrict__ w1, int A, int H, int ke_pad,
+                                     __bf16* __restrict__ out) {
+  const size_t total = static_cast<size_t>(ke_pad) * H;
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  // i = ((c * KK + kk) * 64 + lane) * 8 + j
+  const int j = static_cast<int>(i & 7);
+  const int lane = static_cast<int>((i >> 3) & 63);
+  const size_t rest = i >> 9;
+  const int KK = ke_pad / 32;
+  const int kk = static_cast<int>(rest % KK);
+  const int c = static_cast<int>(rest / KK);
+  const int k = 32 * kk + 8 * (lane >> 4) + j;
+  const int col = 16 * c + (lane & 15);
+  const int row = k == 0 ? 0 : (k <= A ? A + k : -1);
+  const float v = (row >= 0 && col < H) ? w1[static_cast<size_t>(row) * H + col] : 0.0f;
+  out[i] = static_cast<__bf16>(v);
+}
+
+// Rows 1..A and 2A+1..S-1 of W1 [S][H] (closes, indicators) as bfloat16 [S-1-A][H].
+__global__ void gather_market_rows_kernel(const float* __restrict__ w1, int S, int H, int A,
+                                          __bf16* __restrict__ out) {
+  const size_t total = static_cast<size_t>(S - 1 - A) * H;
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int f = static_cast<int>(i / H), col = static_cast<int>(i - static_cast<size_t>(f) * H);
+  const int row = f < A ? 1 + f : A + 1 + f;
+  out[i] = static_cast<__bf16>(w1[static_cast<size_t>(row) * H + col]);
+}
+
 __global__ void copy_pad_kernel(const float* __restrict__ src, int n, int n_pad,
                                 float* __restrict__ dst) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -168,6 +199,20 @@ hipError_t launch_pack_matrix(int dtype, const float* w, int kin, int nout, int 
   else
     hipLaunchKernelGGL(pack_matrix_kernel<kBF16>, grid, dim3(256), 0, stream, w, kin, nout, kin_pad,
                        nout_pad, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_env_rows(const float* w1, int A, int H, int ke_pad, void* out, hipStream_t stream) {
+  const size_t total = static_cast<size_t>(ke_pad) * H;
+  hipLaunchKernelGGL(pack_env_rows_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream,
+                     w1, A, H, ke_pad, static_cast<__bf16*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_market_rows(const float* w1, int S, int H, int A, __bf16* out, hipStream_t stream) {
+  const size_t total = static_cast<size_t>(S - 1 - A) * H;
+  hipLaunchKernelGGL(gather_market_rows_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
+                     stream, w1, S, H, A, out);
   return hipGetLastError();
 }
 

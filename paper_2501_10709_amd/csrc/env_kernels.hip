@@ -241,30 +241,7 @@ __global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvStat
             wave_store_row(A.act_out + row0 * D, MD, lane, [&](int i) { return in[n_mkt + i]; });
           if (A.qty) wave_store_row(A.qty + row0 * D, MD, lane, [&](int i) { return qty[i]; });
         }
-        // States s_{t+1} = [cash, new closes, holdings, new indicators]: lane f writes entry f
-        // (f, f+64, ...) of every row, so each store covers a contiguous run of the tile.
-        if (A.obs) {
-          for (int f = lane; f < S; f += kWave) {
-            const float* src;
-            int stride = 0;
-            float scale = 1.0f;
-            if (f == 0) {
-              src = env;
-              stride = DS;
-            } else if (f <= D) {
-              src = in + D + (f - 1);
-              scale = C.price_scale;
-            } else if (f <= 2 * D) {
-              src = env + (f - D);
-              stride = DS;
-            } else {
-              src = in + (f - 1);  // ind[tn][f-1-2D]
-            }
-            float* dst = A.obs + row0 * S + f;
-#pragma unroll 8
-            for (int m = 0; m < M; ++m) dst[static_cast<size_t>(m) * S] = src[m * stride] * scale;
-          }
-        }
+        if (A.obs) store_state_rows(A.obs + row0 * S, M, S, D, env, DS, in, C.price_scale, lane);
       }
     } else {
       if (it + 1 < n_iter) {

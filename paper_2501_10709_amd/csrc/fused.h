@@ -12,6 +12,13 @@
 
 namespace fm {
 
+// Steps per launch of the streamed schedule; its per-chunk scratch holds this many days.
+constexpr int kFusedChunk = 64;
+// Scratch floats of the streamed schedule for N environments and D stocks: the chunk's noise
+// [kFusedChunk][N][D] and market table [kFusedChunk][8][512] (any supported K, H).
+inline size_t fused_eps_floats(size_t N, size_t D) { return static_cast<size_t>(kFusedChunk) * N * D; }
+inline size_t fused_table_floats() { return static_cast<size_t>(kFusedChunk) * 8 * 512; }
+
 // Rows (environments) per workgroup of the fused kernel: 16 * row_tiles.
 struct FusedTuning {
   int row_tiles = 0;  // 0: choose from the problem size
@@ -25,7 +32,7 @@ bool fused_streamed_shape(const EnvConst& C, const EnsDev& E);
 hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0,
                                 int n_steps, float sigma, uint64_t key, int64_t env_offset,
                                 float* obs_traj, float* act_traj, double* rew_traj, int* qty_traj,
-                                hipStream_t stream, std::string* why,
+                                float* eps_chunk, float* mt_chunk, hipStream_t stream, std::string* why,
                                 FusedTuning tune = FusedTuning());
 
 }  // namespace fm

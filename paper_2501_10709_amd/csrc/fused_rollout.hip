@@ -34,6 +34,8 @@ struct FusedArgs {
   float* act_traj;
   double* rew_traj;
   int* qty_traj;
+  const float* eps;  // streamed schedule: the chunk's noise [n_steps][N][D]
+  const float* mt;   // streamed schedule: the chunk's layer-1 market shares [n_steps][K][H]
 };
 
 // Calls f(std::integral_constant<int, i>) for i = 0 .. N-1, fully unrolled.
@@ -203,7 +205,7 @@ struct EnvPhase {
   // Load the tile's state into the owner lanes (holdings into LDS).
   __device__ void load_state(bool owner, const EnvState& st, double& cash, double& asset, double& cumrew) {
     if (!owner) return;
-    const int D = C.D, N = C.N, DS = D + 1, n = n0 + lane;
+    const int D = C.D, N = C.N, n = n0 + lane;
     cash = st.cash[n];
     asset = st.asset[n];
     cumrew = st.cumrew[n];
@@ -211,7 +213,7 @@ struct EnvPhase {
   }
   __device__ void store_state(bool owner, const EnvState& st, double cash, double asset, double cumrew) {
     if (!owner) return;
-    const int D = C.D, N = C.N, DS = D + 1, n = n0 + lane;
+    const int D = C.D, N = C.N, n = n0 + lane;
     st.cash[n] = cash;
     st.asset[n] = asset;
     st.cumrew[n] = cumrew;
@@ -258,193 +260,500 @@ __device__ __forceinline__ void layer_bf16(const __bf16* sin, int ist, int kin_p
 }
 
 // ------------------------------------------------------------------------------------------
-// Streamed MLP schedule for K = 3, S_pad = 32*KK1, H = 256, A_pad = 32 with eight wavefronts.
-// Wavefront w owns layer-1/2 output tiles w and w+8 and, if w < 2, layer-3 tile w.  Its weight
-// fragments form a fixed sequence of NS k-steps per environment step; fragments for k-step
-// s+DEPTH are requested when k-step s is consumed.
+// Streamed MLP schedule for K = 3, H = 256, A_pad = 32 over the split first layer: layer 1 runs
+// on the per-environment entries only (KKE k-steps of 32 rows: cash, holdings, zero padding),
+// its market share comes from the day's table.  NWAVES wavefronts; wavefront w owns layer-1/2
+// output tiles w, w+NWAVES, ... and, if w < 2, layer-3 tile w.  Its weight fragments form a
+// fixed sequence of NS k-steps per environment step; fragments for k-step s+DEPTH are requested
+// when k-step s is consumed.
 // ------------------------------------------------------------------------------------------
-template <int KK1, int ROWT, int DEPTH, int NWAVES>
+template <int KKE, int ROWT, int DEPTH, int NWAVES>
 struct Streamed {
   static constexpr int K = 3, KK2 = 8, HT = 16, AT = 2, NW = NWAVES, TW = HT / NWAVES;
-  static constexpr int SPA = KK1 + 2 * KK2;  // k-steps per actor
+  static constexpr int SPA = KKE + 2 * KK2;  // k-steps per actor
   static constexpr int NS = K * SPA;         // k-steps per environment step
   // The schedule walks NSP >= NS positions per step, a multiple of DEPTH, so that k-step j always
   // uses ring slot j % DEPTH, also across the wrap into the next step; positions >= NS are idle.
   static constexpr int NSP = (NS + DEPTH - 1) / DEPTH * DEPTH;
 
-  // Packed-ensemble layout of this shape (bytes; checked against the workspace on the host).
-  static constexpr size_t kW1 = 0, kW2 = 32 * KK1 * 256 * 2, kW3 = kW2 + 256 * 256 * 2;
+  // Packed-ensemble layout of this shape (bytes; checked against the workspace on the host):
+  // per actor W1 (224 rows), W2, W3, b1, b2, b3; the env-row fragments of all actors elsewhere.
+  static constexpr size_t kW2 = 224 * 256 * 2, kW3 = kW2 + 256 * 256 * 2;
   static constexpr size_t kB1 = kW3 + 256 * 32 * 2, kB2 = kB1 + 1024, kB3 = kB2 + 1024;
   static constexpr size_t kActor = kB3 + 256;
+  static constexpr size_t kW1eActor = static_cast<size_t>(KKE) * HT * 1024;
 
   // Weight fragments of k-step S2 for wavefront wv (uniform); voff = lane * 16.
   template <int S2>
-  static __device__ __forceinline__ void load(bf16x8 (&b)[TW], const unsigned char* wb, int wv, int voff) {
+  static __device__ __forceinline__ void load(bf16x8 (&b)[TW], const unsigned char* wb, const unsigned char* w1e,
+                                              int wv, int voff) {
     if constexpr (S2 >= NS) return;  // idle position
     constexpr int actor = S2 / SPA, r = S2 % SPA;
-    const unsigned char* P = wb + kActor * actor;
-    if constexpr (r < KK1) {
+    if constexpr (r < KKE) {
+      const unsigned char* P = w1e + kW1eActor * actor;
 #pragma unroll
       for (int i = 0; i < TW; ++i)
-        b[i] = *reinterpret_cast<const bf16x8*>(P + kW1 + static_cast<size_t>((wv + NW * i) * KK1 + r) * 1024 + voff);
-    } else if constexpr (r < KK1 + KK2) {
-      constexpr int kk = r - KK1;
+        b[i] = *reinterpret_cast<const bf16x8*>(P + static_cast<size_t>((wv + NW * i) * KKE + r) * 1024 + voff);
+    } else if constexpr (r < KKE + KK2) {
+      constexpr int kk = r - KKE;
+      const unsigned char* P = wb + kActor * actor;
 #pragma unroll
       for (int i = 0; i < TW; ++i)
         b[i] = *reinterpret_cast<const bf16x8*>(P + kW2 + static_cast<size_t>((wv + NW * i) * KK2 + kk) * 1024 + voff);
     } else {
-      constexpr int kk = r - KK1 - KK2;
+      constexpr int kk = r - KKE - KK2;
+      const unsigned char* P = wb + kActor * actor;
       if (wv < AT) b[0] = *reinterpret_cast<const bf16x8*>(P + kW3 + static_cast<size_t>(wv * KK2 + kk) * 1024 + voff);
     }
   }
 };
 
-template <int ROWT, int KK1, int DEPTH, int NWAVES>
-__global__ __launch_bounds__(64 * NWAVES) void fused_streamed_kernel(EnvConst C, EnvState st, EnsDev E,
-                                                                     FusedArgs F) {
-  using SP = Streamed<KK1, ROWT, DEPTH, NWAVES>;
-  constexpr int NT = 64 * NWAVES, MR = 16 * ROWT, TW = SP::TW, NW = SP::NW;
+// ------------------------------------------------------------------------------------------
+// Per-chunk tables of the streamed kernel, made before it by two small kernels:
+//   mt[c][k][j]: actor k's layer-1 pre-activation share of the market entries of state s_t
+//     (t = t0 + c), b1_k[j] + sum_f bf16(x_f) * W1m_k[f][j] in float32 -- the same for every
+//     environment of day t, so it is computed once per day instead of once per environment;
+//   eps[c][n][d]: the noise of step t for environment n (Philox4x64-10 + Box-Muller).
+// ------------------------------------------------------------------------------------------
+__global__ void market_table_kernel(EnvConst C, EnsDev E, int t0, float* __restrict__ mt) {
+  extern __shared__ float xs[];  // the day's market entries, bfloat16-rounded
+  const int c = blockIdx.x, k = blockIdx.y, t = t0 + c;
+  const int D = C.D, I = C.I, Fm = (1 + I) * D, H = E.H;
+  for (int f = threadIdx.x; f < Fm; f += blockDim.x) {
+    const float v = f < D ? C.close[static_cast<size_t>(t) * D + f] * C.price_scale
+                          : C.ind[static_cast<size_t>(t) * I * D + (f - D)];
+    xs[f] = static_cast<float>(static_cast<__bf16>(v));
+  }
+  __syncthreads();
+  const __bf16* w = reinterpret_cast<const __bf16*>(E.base + E.off_w1m) + static_cast<size_t>(k) * Fm * H;
+  const float* b1 = reinterpret_cast<const float*>(E.base + k * E.actor_stride + E.off_b1);
+  for (int j = threadIdx.x; j < H; j += blockDim.x) {
+    float acc = 0.0f;
+    for (int f = 0; f < Fm; ++f) acc = acc + xs[f] * static_cast<float>(w[static_cast<size_t>(f) * H + j]);
+    mt[(static_cast<size_t>(c) * E.K + k) * H + j] = acc + b1[j];
+  }
+}
+
+__global__ void noise_chunk_kernel(uint64_t key, int64_t env_offset, int t0, int n_days, int N, int D,
+                                   float* __restrict__ eps) {
+  const int G = (D + 3) >> 2;
+  const size_t total = static_cast<size_t>(n_days) * N * G;
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int g = static_cast<int>(i % G);
+  const size_t rest = i / G;
+  const int n = static_cast<int>(rest % N);
+  const int c = static_cast<int>(rest / N);
+  float z[4];
+  noise_block(key, static_cast<uint64_t>(env_offset + n), static_cast<uint64_t>(t0 + c), static_cast<uint64_t>(g), z);
+  float* row = eps + (static_cast<size_t>(c) * N + n) * D;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (4 * g + r < D) row[4 * g + r] = z[r];
+}
+
+// ------------------------------------------------------------------------------------------
+// Streamed kernel.  Five wavefronts with two roles:
+//   wavefronts 0-3 (MLP): the three layers of the K actors for the tile's state rows, weight
+//     fragments streamed through a register ring; then the parallel chain phases (actions,
+//     orders and sells; buys applied, holdings entries of the next state rows);
+//   wavefront 4 (environment): while the MLP of step t runs, the stores of step t-1's results
+//     and the staging of step t+1's inputs (market rows, noise, market table) from registers
+//     into LDS, then the requests for step t+2's; after the MLP, the serial cash recurrence and
+//     the value and reward of each environment (lane m owns environment m and its cash, value
+//     and cumulative reward).
+// The two roles run separate loops that pass the same sequence of workgroup barriers per step.
+// State rows, actions, quantities, state entries, rewards, noise and table rows are
+// double-buffered by step parity; the market rows [close[t] | close[t+1] | ind[t+1]] are
+// triple-buffered by step (the results of step t read them during step t+1).
+// ------------------------------------------------------------------------------------------
+constexpr int kMlpWaves = 4;
+constexpr int kStreamThreads = 64 * (kMlpWaves + 1);
+constexpr int kStreamK = 3, kStreamH = 256;
+constexpr int kBiasStride = 2 * kStreamH;  // b2 | b3 (padded) per actor
+constexpr int kMktStage = 10;              // registers per lane: (2 + I) * D <= 640
+constexpr int kTabStage = kStreamK * kStreamH / 64;
+
+struct StreamLds {
+  // Double- and triple-buffered regions are a base and a buffer stride (in elements): buffer b
+  // starts at base + b * stride.
+  __bf16* x0_;    // [2][MR][ST0] state-row entries of the environments (cash, holdings)
+  __bf16* x1;     // [MR][STH]
+  __bf16* x2;     // [MR][STH]
+  float* bias;    // [K][kBiasStride]
+  float* mix;     // [K]
+  float* abar;    // [MR][DS] ensemble mean
+  float* eps_;    // [2][MR][D] noise
+  float* mt_;     // [2][K][H] layer-1 market share
+  float* act_;    // [2][MR][D]
+  int* qty_;      // [2][MR][D]
+  float* env_;    // [2][MR][DS] cash entry, holdings entries
+  double* rew_;   // [2][MR]
+  int* hold;      // [MR][D]
+  float* in_;     // [3][IN] market rows of a step
+  int x0s, epss, mts, acts, qtys, envs, rews, ins;
+  ChainLds chain;
+
+  __device__ __bf16* x0(int b) const { return x0_ + b * x0s; }
+  __device__ float* eps(int b) const { return eps_ + b * epss; }
+  __device__ float* mt(int b) const { return mt_ + b * mts; }
+  __device__ float* act(int b) const { return act_ + b * acts; }
+  __device__ int* qty(int b) const { return qty_ + b * qtys; }
+  __device__ float* env(int b) const { return env_ + b * envs; }
+  __device__ double* rew(int b) const { return rew_ + b * rews; }
+  __device__ float* in(int b) const { return in_ + b * ins; }
+
+  static __host__ __device__ size_t a16(size_t b) { return (b + 15) / 16 * 16; }
+  // Byte offsets of the regions and the total.
+  struct Offsets {
+    size_t sc, x0, x1, x2, bias, mix, abar, eps, mt, act, qty, env, rew, hold, in, total;
+    size_t x0b, epsb, mtb, actb, qtyb, envb, rewb, inb;  // bytes per buffer
+  };
+  __host__ __device__ static Offsets offsets(int MR, int st0, int sth, int D, int I) {
+    const ChainShape Z = ChainShape::of(D);
+    const size_t DS = D + 1;
+    Offsets o{};
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+      const size_t a = a16(p);
+      p = a + bytes;
+      return a;
+    };
+    o.x0b = a16(sizeof(__bf16) * MR * st0);
+    o.epsb = a16(sizeof(float) * MR * D);
+    o.mtb = a16(sizeof(float) * kStreamK * kStreamH);
+    o.actb = a16(sizeof(float) * MR * D);
+    o.qtyb = a16(sizeof(int) * MR * D);
+    o.envb = a16(sizeof(float) * MR * DS);
+    o.rewb = a16(sizeof(double) * MR);
+    const size_t nin = static_cast<size_t>(2 + I) * D;
+    o.inb = a16(sizeof(float) * (nin > static_cast<size_t>(Z.DP) ? nin : static_cast<size_t>(Z.DP)));
+    o.sc = take(Z.scratch_bytes(MR));
+    o.x0 = take(2 * o.x0b);
+    o.x1 = take(sizeof(__bf16) * MR * sth);
+    o.x2 = take(sizeof(__bf16) * MR * sth);
+    o.bias = take(sizeof(float) * kStreamK * kBiasStride);
+    o.mix = take(sizeof(float) * kStreamK);
+    o.abar = take(sizeof(float) * MR * DS);
+    o.eps = take(2 * o.epsb);
+    o.mt = take(2 * o.mtb);
+    o.act = take(2 * o.actb);
+    o.qty = take(2 * o.qtyb);
+    o.env = take(2 * o.envb);
+    o.rew = take(2 * o.rewb);
+    o.hold = take(sizeof(int) * MR * D);
+    o.in = take(3 * o.inb);
+    o.total = a16(p);
+    return o;
+  }
+  __device__ void carve(unsigned char* smem, int MR, int st0, int sth, int D, int I) {
+    const Offsets o = offsets(MR, st0, sth, D, I);
+    x0_ = reinterpret_cast<__bf16*>(smem + o.x0);
+    x1 = reinterpret_cast<__bf16*>(smem + o.x1);
+    x2 = reinterpret_cast<__bf16*>(smem + o.x2);
+    bias = reinterpret_cast<float*>(smem + o.bias);
+    mix = reinterpret_cast<float*>(smem + o.mix);
+    abar = reinterpret_cast<float*>(smem + o.abar);
+    eps_ = reinterpret_cast<float*>(smem + o.eps);
+    mt_ = reinterpret_cast<float*>(smem + o.mt);
+    act_ = reinterpret_cast<float*>(smem + o.act);
+    qty_ = reinterpret_cast<int*>(smem + o.qty);
+    env_ = reinterpret_cast<float*>(smem + o.env);
+    rew_ = reinterpret_cast<double*>(smem + o.rew);
+    hold = reinterpret_cast<int*>(smem + o.hold);
+    in_ = reinterpret_cast<float*>(smem + o.in);
+    x0s = static_cast<int>(o.x0b / sizeof(__bf16));
+    epss = static_cast<int>(o.epsb / sizeof(float));
+    mts = static_cast<int>(o.mtb / sizeof(float));
+    acts = static_cast<int>(o.actb / sizeof(float));
+    qtys = static_cast<int>(o.qtyb / sizeof(int));
+    envs = static_cast<int>(o.envb / sizeof(float));
+    rews = static_cast<int>(o.rewb / sizeof(double));
+    ins = static_cast<int>(o.inb / sizeof(float));
+    chain.carve_scratch(smem + o.sc, ChainShape::of(D), MR);
+    chain.hold = hold;
+  }
+};
+
+template <int ROWT, int KKE, int DEPTH>
+__global__ __launch_bounds__(kStreamThreads) void fused_streamed_kernel(EnvConst C, EnvState st, EnsDev E,
+                                                                        FusedArgs F) {
+  using SP = Streamed<KKE, ROWT, DEPTH, kMlpWaves>;
+  constexpr int MR = 16 * ROWT, TW = SP::TW, NW = SP::NW, NT = kStreamThreads;
   constexpr int KK2 = SP::KK2, SPA = SP::SPA, NS = SP::NS, NSP = SP::NSP;
-  constexpr int S_PAD = 32 * KK1, H = 256;
-  constexpr int ST0 = S_PAD + 8, STH = H + 8;
+  constexpr int H = kStreamH, K = kStreamK;
+  constexpr int ST0 = 32 * KKE + 8, STH = H + 8;
+  constexpr int NBAR = K * 3;                     // layer-end barriers per step
+  constexpr int EPS_STAGE = (MR * 32 + 63) / 64;  // registers per lane for a step's noise (D <= 32)
   extern __shared__ __align__(16) unsigned char smem[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int D = C.D, N = C.N, DS = D + 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int D = C.D, N = C.N, DS = D + 1, S = C.S, I = C.I;
   const int n0 = blockIdx.x * MR;
   const int M = min(MR, N - n0);
+  const ChainShape Z = ChainShape::of(D);
 
-  FusedLds L;
-  L.carve(smem, MR, ST0, STH, D);
-  EnvPhase<NT> P{C, F, L, tid, lane, wave, n0, M, S_PAD, ST0, 1.0f / static_cast<float>(D),
-                 1.0f / static_cast<float>((D + 3) >> 2), (D + 3) >> 2};
+  StreamLds L;
+  L.carve(smem, MR, ST0, STH, D, I);
 
-  for (int i = tid; i < MR * ST0; i += NT) L.x0[i] = static_cast<__bf16>(0.0f);
-
-  const bool owner = wave == 0 && lane < M;
-  const int n = n0 + lane;
-  double cash = 0.0, asset = 0.0, cumrew = 0.0;
-  P.load_state(owner, st, cash, asset, cumrew);
-
-  P.stage_market(F.t0, false);
-  P.env_entries(owner, cash);
+  // Zero both state-row buffers (padding columns and the rows of absent environments stay
+  // zero); layer-2/3 biases and mixing weights into LDS.
+  for (int b = 0; b < 2; ++b)
+    for (int i = tid; i < MR * ST0; i += NT) L.x0(b)[i] = static_cast<__bf16>(0.0f);
+  for (int i = tid; i < K * kBiasStride; i += NT) {
+    const int a = i / kBiasStride, c = i - a * kBiasStride;
+    const size_t off = c < H ? SP::kB2 + 4 * c : SP::kB3 + 4 * (c - H);
+    L.bias[i] = (c < H + 32) ? *reinterpret_cast<const float*>(E.base + SP::kActor * a + off) : 0.0f;
+  }
+  for (int i = tid; i < K; i += NT) L.mix[i] = E.mix[i];
   __syncthreads();
-  P.assemble(nullptr);
 
-  const int wv = __builtin_amdgcn_readfirstlane(wave);
-  const int voff = lane * 16;
-  bf16x8 ring[DEPTH][TW];
-  static_for<DEPTH>([&](auto sc) __attribute__((always_inline)) {
-    constexpr int s = decltype(sc)::value;
-    SP::template load<s>(ring[s], E.base, wv, voff);
-  });
-
-  const int row_q = 4 * (lane >> 4), col_l = lane & 15, row = lane & 15, grp = lane >> 4;
-  const float* mix = E.mix;
-
-  for (int it = 0; it < F.n_steps; ++it) {
-    const int t = F.t0 + it;
-    const size_t row_base = static_cast<size_t>(it) * N + n0;
-    __syncthreads();                       // x0 complete; LDS market rows free
-    P.stage_market(t + 1, true);
-    // The weight base is offset by an opaque zero every step, so that no fragment address is
-    // hoisted out of the step loop (there are hundreds of them).  Laundering an integer rather
-    // than the pointer keeps the loads in the global address space (flat loads would also count
-    // against the LDS wait counter and stall every LDS read behind the whole weight pipeline).
-    int opaque_zero = 0;
-    asm volatile("" : "+s"(opaque_zero));
-    const unsigned char* wb = E.base + opaque_zero;
-
-    floatx4 acc[ROWT][TW];
-    static_for<NSP>([&](auto sc) __attribute__((always_inline)) {
+  if (wave < NW) {
+    // ---------------------------------------------------------------- MLP wavefronts
+    const int wv = wave;
+    const int voff = lane * 16;
+    bf16x8 ring[DEPTH][TW];
+    static_for<DEPTH>([&](auto sc) __attribute__((always_inline)) {
       constexpr int s = decltype(sc)::value;
-      // Keep the k-steps in program order: the scheduler would otherwise hoist every load of a
-      // layer to its top and run out of registers.
-      __builtin_amdgcn_sched_barrier(0);
-      if constexpr (s >= NS) {
-        SP::template load<(s + DEPTH) % NSP>(ring[s % DEPTH], wb, wv, voff);
-        return;
-      }
-      constexpr int actor = s / SPA, r = s % SPA;
-      constexpr int layer = r < KK1 ? 1 : (r < KK1 + KK2 ? 2 : 3);
-      constexpr int kk = layer == 1 ? r : (layer == 2 ? r - KK1 : r - KK1 - KK2);
-      constexpr int first = layer == 1 ? 0 : (layer == 2 ? KK1 : KK1 + KK2);
-      constexpr int last = layer == 1 ? KK1 - 1 : (layer == 2 ? KK1 + KK2 - 1 : SPA - 1);
-      if constexpr (r == first) {
+      SP::template load<s>(ring[s], E.base, E.base + E.off_w1e, wv, voff);
+    });
+    const int row_q = 4 * (lane >> 4), col_l = lane & 15, row = lane & 15, grp = lane >> 4;
+    const float sigma = F.sigma;
+    __syncthreads();  // the first state rows and inputs are staged
+
+    for (int it = 0; it < F.n_steps; ++it) {
+      __syncthreads();  // T: state rows of step it complete
+      // The weight bases are offset by an opaque zero every step, so that no fragment address
+      // is hoisted out of the step loop (there are hundreds of them).  Laundering an integer
+      // rather than the pointer keeps the loads in the global address space (flat loads would
+      // also count against the LDS wait counter).
+      int opaque_zero = 0;
+      asm volatile("" : "+s"(opaque_zero));
+      const unsigned char* wb = E.base + opaque_zero;
+      const unsigned char* w1e = E.base + (E.off_w1e + opaque_zero);
+      const __bf16* xin = L.x0(it & 1);
+      const float* mtab = L.mt(it & 1);
+
+      floatx4 acc[ROWT][TW];
+      static_for<NSP>([&](auto sc) __attribute__((always_inline)) {
+        constexpr int s = decltype(sc)::value;
+        // Keep the k-steps in program order: the scheduler would otherwise hoist every load of
+        // a layer to its top and run out of registers.
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (s >= NS) {
+          SP::template load<(s + DEPTH) % NSP>(ring[s % DEPTH], wb, w1e, wv, voff);
+          return;
+        }
+        constexpr int actor = s / SPA, r = s % SPA;
+        constexpr int layer = r < KKE ? 1 : (r < KKE + KK2 ? 2 : 3);
+        constexpr int kk = layer == 1 ? r : (layer == 2 ? r - KKE : r - KKE - KK2);
+        constexpr int first = layer == 1 ? 0 : (layer == 2 ? KKE : KKE + KK2);
+        constexpr int last = layer == 1 ? KKE - 1 : (layer == 2 ? KKE + KK2 - 1 : SPA - 1);
+        if constexpr (r == first) {
+#pragma unroll
+          for (int rt = 0; rt < ROWT; ++rt)
+#pragma unroll
+            for (int i = 0; i < TW; ++i) acc[rt][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        bf16x8 cur[TW];
+#pragma unroll
+        for (int i = 0; i < TW; ++i) cur[i] = ring[s % DEPTH][i];
+        SP::template load<(s + DEPTH) % NSP>(ring[s % DEPTH], wb, w1e, wv, voff);
+
+        const __bf16* src = layer == 1 ? xin : (layer == 2 ? L.x1 : L.x2);
+        constexpr int ist = layer == 1 ? ST0 : STH;
+        bf16x8 a[ROWT];
 #pragma unroll
         for (int rt = 0; rt < ROWT; ++rt)
-#pragma unroll
-          for (int i = 0; i < TW; ++i) acc[rt][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-      }
-      bf16x8 cur[TW];
-#pragma unroll
-      for (int i = 0; i < TW; ++i) cur[i] = ring[s % DEPTH][i];
-      SP::template load<(s + DEPTH) % NSP>(ring[s % DEPTH], wb, wv, voff);
-
-      const __bf16* src = layer == 1 ? L.x0 : (layer == 2 ? L.x1 : L.x2);
-      constexpr int ist = layer == 1 ? ST0 : STH;
-      bf16x8 a[ROWT];
-#pragma unroll
-      for (int rt = 0; rt < ROWT; ++rt)
-        a[rt] = *reinterpret_cast<const bf16x8*>(src + (rt * 16 + row) * ist + 32 * kk + 8 * grp);
-      if constexpr (layer < 3) {
-#pragma unroll
-        for (int i = 0; i < TW; ++i)
-#pragma unroll
-          for (int rt = 0; rt < ROWT; ++rt) acc[rt][i] = mfma_bf16(a[rt], cur[i], acc[rt][i]);
-      } else {
-        if (wave < SP::AT) {
-#pragma unroll
-          for (int rt = 0; rt < ROWT; ++rt) acc[rt][0] = mfma_bf16(a[rt], cur[0], acc[rt][0]);
-        }
-      }
-
-      if constexpr (r == last) {
-        const unsigned char* PA = wb + SP::kActor * actor;
+          a[rt] = *reinterpret_cast<const bf16x8*>(src + (rt * 16 + row) * ist + 32 * kk + 8 * grp);
         if constexpr (layer < 3) {
-          const float* bias = reinterpret_cast<const float*>(PA + (layer == 1 ? SP::kB1 : SP::kB2));
-          __bf16* out = layer == 1 ? L.x1 : L.x2;
 #pragma unroll
-          for (int i = 0; i < TW; ++i) {
-            const int col = 16 * (wave + NW * i) + col_l;
-            const float b = bias[col];
+          for (int i = 0; i < TW; ++i)
 #pragma unroll
-            for (int rt = 0; rt < ROWT; ++rt)
-#pragma unroll
-              for (int q = 0; q < 4; ++q)
-                out[(rt * 16 + row_q + q) * STH + col] = static_cast<__bf16>(fast_tanh(acc[rt][i][q] + b));
-          }
+            for (int rt = 0; rt < ROWT; ++rt) acc[rt][i] = mfma_bf16(a[rt], cur[i], acc[rt][i]);
         } else {
-          if (wave < SP::AT) {
-            const float* b3 = reinterpret_cast<const float*>(PA + SP::kB3);
-            const int col = 16 * wave + col_l;
-            if (col < E.A) {
-              const float b = b3[col];
-              const float wk = mix[actor];
+          if (wv < SP::AT) {
+#pragma unroll
+            for (int rt = 0; rt < ROWT; ++rt) acc[rt][0] = mfma_bf16(a[rt], cur[0], acc[rt][0]);
+          }
+        }
+
+        if constexpr (r == last) {
+          if constexpr (layer < 3) {
+            // Layer 1 adds the day's market share (bias included); layer 2 its bias.
+            const float* b = layer == 1 ? mtab + actor * H : L.bias + actor * kBiasStride;
+            __bf16* out = layer == 1 ? L.x1 : L.x2;
+#pragma unroll
+            for (int i = 0; i < TW; ++i) {
+              const int col = 16 * (wv + NW * i) + col_l;
+              const float bc = b[col];
 #pragma unroll
               for (int rt = 0; rt < ROWT; ++rt)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                  float* dst = &L.abar[(rt * 16 + row_q + q) * DS + col];
-                  const float v = wk * fast_tanh(acc[rt][0][q] + b);
-                  *dst = (actor == 0) ? v : (*dst + v);
-                }
+                for (int q = 0; q < 4; ++q)
+                  out[(rt * 16 + row_q + q) * STH + col] = static_cast<__bf16>(fast_tanh(acc[rt][i][q] + bc));
+            }
+          } else {
+            if (wv < SP::AT) {
+              const int col = 16 * wv + col_l;
+              if (col < E.A) {
+                const float bc = L.bias[actor * kBiasStride + H + col];
+                const float wk = L.mix[actor];
+#pragma unroll
+                for (int rt = 0; rt < ROWT; ++rt)
+#pragma unroll
+                  for (int q = 0; q < 4; ++q) {
+                    float* dst = &L.abar[(rt * 16 + row_q + q) * DS + col];
+                    const float v = wk * fast_tanh(acc[rt][0][q] + bc);
+                    *dst = (actor == 0) ? v : (*dst + v);
+                  }
+              }
             }
           }
+          __syncthreads();  // layer end
         }
-        __syncthreads();
-      }
-    });
+      });
 
-    P.actions(t, row_base);
-    __syncthreads();
-    const double rwd = P.chain(owner, cash, asset, cumrew);
-    if (owner && F.rew_traj) F.rew_traj[static_cast<size_t>(it) * N + n] = rwd;
-    __syncthreads();
-    P.quantities(row_base);
-    P.assemble(F.obs_traj ? F.obs_traj + row_base * C.S : nullptr);
+      // Actions a = clip(a_bar + sigma * eps), orders, sells, debits.
+      const float* in = L.in(it % 3);
+      const float* eps = L.eps(it & 1);
+      ChainLds CL = L.chain;
+      CL.px = in;
+      CL.pn = in + D;
+      CL.qty = L.qty(it & 1);
+      CL.env = L.env(it & 1);
+      float* actb = L.act(it & 1);
+      chain_pairs_a(CL, Z, M, tid, 64 * NW, C.hmax_f, C.one_m, C.one_p, [&](int m, int d, int e) {
+        float a = L.abar[m * DS + d];
+        if (sigma != 0.0f) a = a + sigma * eps[e];
+        a = fminf(fmaxf(a, -1.0f), 1.0f);
+        actb[e] = a;
+        return a;
+      });
+      __syncthreads();  // A
+      __syncthreads();  // S: the cash recurrences (environment wavefront)
+      __bf16* xn = L.x0((it + 1) & 1);
+      chain_pairs_c(CL, Z, M, tid, 64 * NW, C.hold_scale,
+                    [&](int m, int d, float he) { xn[m * ST0 + 1 + d] = static_cast<__bf16>(he); });
+      __syncthreads();  // C
+    }
+    __syncthreads();  // end
+    return;
   }
 
-  P.store_state(owner, st, cash, asset, cumrew);
+  // ------------------------------------------------------------------ environment wavefront
+  const bool owner = lane < M;
+  const int n = n0 + lane;
+  double cash = 0.0, asset = 0.0, cumrew = 0.0;
+  if (owner) {
+    cash = st.cash[n];
+    asset = st.asset[n];
+    cumrew = st.cumrew[n];
+    for (int d = 0; d < D; ++d) L.hold[lane * D + d] = st.hold[static_cast<size_t>(d) * N + n];
+  }
+  const int n_mkt = (2 + I) * D, MD = M * D;
+  // Inputs of step j: market rows close[t] | close[t+1] | ind[t+1] (t = t0 + j), the tile's noise
+  // rows, the market table of day t.
+  float stg_m[kMktStage], stg_e[EPS_STAGE], stg_t[kTabStage];
+  auto issue = [&](int j) {
+    const int t = F.t0 + j;
+#pragma unroll
+    for (int r = 0; r < kMktStage; ++r) {
+      const int i = lane + 64 * r;
+      float v = 0.0f;
+      if (i < D) v = C.close[static_cast<size_t>(t) * D + i];
+      else if (i < 2 * D) v = C.close[static_cast<size_t>(t + 1) * D + (i - D)];
+      else if (i < n_mkt) v = C.ind[static_cast<size_t>(t + 1) * I * D + (i - 2 * D)];
+      stg_m[r] = v;
+    }
+    const float* e = F.eps + (static_cast<size_t>(j) * N + n0) * D;
+#pragma unroll
+    for (int r = 0; r < EPS_STAGE; ++r) {
+      const int i = lane + 64 * r;
+      stg_e[r] = i < MD ? e[i] : 0.0f;
+    }
+    const float* tb = F.mt + static_cast<size_t>(j) * K * H;
+#pragma unroll
+    for (int r = 0; r < kTabStage; ++r) stg_t[r] = tb[lane + 64 * r];
+  };
+  auto commit = [&](int j) {
+    float* in = L.in(j % 3);
+#pragma unroll
+    for (int r = 0; r < kMktStage; ++r) {
+      const int i = lane + 64 * r;
+      if (i < n_mkt) in[i] = stg_m[r];
+    }
+    float* e = L.eps(j & 1);
+#pragma unroll
+    for (int r = 0; r < EPS_STAGE; ++r) {
+      const int i = lane + 64 * r;
+      if (i < MD) e[i] = stg_e[r];
+    }
+    float* tb = L.mt(j & 1);
+#pragma unroll
+    for (int r = 0; r < kTabStage; ++r) tb[lane + 64 * r] = stg_t[r];
+  };
+  auto results = [&](int j) {
+    const size_t row0 = static_cast<size_t>(j) * N + n0;
+    if (F.rew_traj && owner) F.rew_traj[row0 + lane] = L.rew(j & 1)[lane];
+    if (F.act_traj) {
+      const float* a = L.act(j & 1);
+      wave_store_row(F.act_traj + row0 * D, MD, lane, [&](int i) { return a[i]; });
+    }
+    if (F.qty_traj) {
+      const int* q = L.qty(j & 1);
+      wave_store_row(F.qty_traj + row0 * D, MD, lane, [&](int i) { return q[i]; });
+    }
+    if (F.obs_traj) store_state_rows(F.obs_traj + row0 * S, M, S, D, L.env(j & 1), DS, L.in(j % 3), C.price_scale, lane);
+  };
+
+  // The first state rows: the cash and holdings entries.
+  if (owner) {
+    __bf16* x = L.x0(0) + lane * ST0;
+    x[0] = static_cast<__bf16>(static_cast<float>(cash * static_cast<double>(C.cash_scale)));
+    for (int d = 0; d < D; ++d) x[1 + d] = static_cast<__bf16>(static_cast<float>(L.hold[lane * D + d]) * C.hold_scale);
+  }
+  issue(0);
+  commit(0);
+  if (F.n_steps > 1) issue(1);
+  __syncthreads();  // the first state rows and inputs are staged
+
+  for (int it = 0; it < F.n_steps; ++it) {
+    __syncthreads();  // T
+    __syncthreads();  // end of layer 1 of the first actor: the longer layer-2 interval follows
+    if (it >= 1) results(it - 1);
+    if (it + 1 < F.n_steps) {
+      commit(it + 1);
+      if (it + 2 < F.n_steps) issue(it + 2);
+    }
+    for (int b = 1; b < NBAR; ++b) __syncthreads();  // the other layer ends
+    __syncthreads();  // A
+    const float* in = L.in(it % 3);
+    const ChainLds& CL = L.chain;
+    if (owner)
+      chain_serial(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.val + lane * Z.RD, CL.qd + lane * Z.RI,
+                   in, CL.kq + lane * Z.RI, Z.DP, C.one_p);
+    __syncthreads();  // S
+    __syncthreads();  // C
+    if (owner) {
+      const double v_new = chain_value(cash, CL.val + lane * Z.RD, Z.DP);
+      const double r = (v_new - asset) * C.reward_scale;
+      cumrew = cumrew + r;
+      asset = v_new;
+      const float ce = static_cast<float>(cash * static_cast<double>(C.cash_scale));
+      L.env(it & 1)[lane * DS] = ce;
+      L.x0((it + 1) & 1)[lane * ST0] = static_cast<__bf16>(ce);
+      L.rew(it & 1)[lane] = r;
+    }
+  }
+  __syncthreads();  // end
+  if (F.n_steps >= 1) results(F.n_steps - 1);
+  if (owner) {
+    st.cash[n] = cash;
+    st.asset[n] = asset;
+    st.cumrew[n] = cumrew;
+    for (int d = 0; d < D; ++d) st.hold[static_cast<size_t>(d) * N + n] = L.hold[lane * D + d];
+  }
 }
 
 template <int ROWT, int TMAX>
@@ -559,41 +868,92 @@ hipError_t launch_generic(const EnvConst& C, const EnvState& st, const EnsDev& E
   return go(fused_generic_kernel<1, 8>, grid, 256, lds, stream, C, st, E, F);
 }
 
-constexpr int kDepth = 6;
-constexpr int kWaves = 4;
-
+// Ring depth (k-steps of weight fragments in flight) by row tiles: the register budget of five
+// wavefronts per workgroup is 256 per lane.
 template <int ROWT>
-hipError_t launch_streamed(const EnvConst& C, const EnvState& st, const EnsDev& E, const FusedArgs& F,
-                           hipStream_t stream) {
-  const size_t lds = FusedLds::bytes(16 * ROWT, 224 + 8, 256 + 8, C.D, C.I);
+constexpr int streamed_depth() { return ROWT == 1 ? 6 : 5; }
+
+template <int ROWT, int KKE>
+size_t streamed_lds_bytes(const EnvConst& C) {
+  return StreamLds::offsets(16 * ROWT, 32 * KKE + 8, kStreamH + 8, C.D, C.I).total;
+}
+
+template <int ROWT, int KKE>
+hipError_t launch_streamed_kernel(const EnvConst& C, const EnvState& st, const EnsDev& E, const FusedArgs& F,
+                                  hipStream_t stream) {
+  const size_t lds = streamed_lds_bytes<ROWT, KKE>(C);
   const int grid = (C.N + 16 * ROWT - 1) / (16 * ROWT);
-  return go(fused_streamed_kernel<ROWT, 7, kDepth, kWaves>, grid, 64 * kWaves, lds, stream, C, st, E, F);
+  return go(fused_streamed_kernel<ROWT, KKE, streamed_depth<ROWT>()>, grid, kStreamThreads, lds, stream, C, st,
+            E, F);
+}
+
+// The streamed schedule over a rollout: per chunk of at most kFusedChunk steps, the chunk's
+// market table and noise, then the fused kernel for the chunk's steps.
+hipError_t launch_streamed(const EnvConst& C, const EnvState& st, const EnsDev& E, FusedArgs F, int rowt,
+                           float* eps_chunk, float* mt_chunk, hipStream_t stream) {
+  const int t_end = F.t0 + F.n_steps;
+  const size_t N = C.N, D = C.D, S = C.S;
+  const int Fm = (1 + C.I) * C.D;
+  for (int t = F.t0; t < t_end; t += kFusedChunk) {
+    const int n = t_end - t < kFusedChunk ? t_end - t : kFusedChunk;
+    const size_t i0 = static_cast<size_t>(t - F.t0);
+    hipLaunchKernelGGL(market_table_kernel, dim3(n, E.K), dim3(kStreamH), sizeof(float) * Fm, stream, C, E, t,
+                       mt_chunk);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (F.sigma != 0.0f) {
+      const size_t total = static_cast<size_t>(n) * N * ((D + 3) / 4);
+      hipLaunchKernelGGL(noise_chunk_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream,
+                         F.key, F.env_offset, t, n, C.N, C.D, eps_chunk);
+      err = hipGetLastError();
+      if (err != hipSuccess) return err;
+    }
+    FusedArgs Fc = F;
+    Fc.t0 = t;
+    Fc.n_steps = n;
+    Fc.eps = eps_chunk;
+    Fc.mt = mt_chunk;
+    Fc.obs_traj = F.obs_traj ? F.obs_traj + i0 * N * S : nullptr;
+    Fc.act_traj = F.act_traj ? F.act_traj + i0 * N * D : nullptr;
+    Fc.rew_traj = F.rew_traj ? F.rew_traj + i0 * N : nullptr;
+    Fc.qty_traj = F.qty_traj ? F.qty_traj + i0 * N * D : nullptr;
+    const int kke = E.ke_pad / 32;
+    if (rowt == 2)
+      err = kke == 1 ? launch_streamed_kernel<2, 1>(C, st, E, Fc, stream) : launch_streamed_kernel<2, 2>(C, st, E, Fc, stream);
+    else
+      err = kke == 1 ? launch_streamed_kernel<1, 1>(C, st, E, Fc, stream) : launch_streamed_kernel<1, 2>(C, st, E, Fc, stream);
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
 
 bool fused_streamed_shape(const EnvConst& C, const EnsDev& E) {
-  using SP = Streamed<7, 1, kDepth, kWaves>;
-  return E.K == 3 && E.H == 256 && E.S_pad == 224 && E.A_pad == 32 && C.D >= 1 && C.D <= 32 &&
-         E.off_w1 == SP::kW1 && E.off_w2 == SP::kW2 && E.off_w3 == SP::kW3 && E.off_b1 == SP::kB1 &&
+  using SP = Streamed<1, 1, streamed_depth<1>(), kMlpWaves>;
+  if (!(E.K == kStreamK && E.H == kStreamH && E.S_pad == 224 && E.A_pad == 32 && C.D >= 1 && C.D <= 32 &&
+        E.split_a == C.D && (E.ke_pad == 32 || E.ke_pad == 64) && (2 + C.I) * C.D <= 64 * kMktStage))
+    return false;
+  if (streamed_lds_bytes<2, 2>(C) > 160 * 1024) return false;
+  return E.off_w1 == 0 && E.off_w2 == SP::kW2 && E.off_w3 == SP::kW3 && E.off_b1 == SP::kB1 &&
          E.off_b2 == SP::kB2 && E.off_b3 == SP::kB3 && E.actor_stride == SP::kActor;
 }
 
 hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0, int n_steps,
                                 float sigma, uint64_t key, int64_t env_offset, float* obs_traj, float* act_traj,
-                                double* rew_traj, int* qty_traj, hipStream_t stream, std::string* why,
-                                FusedTuning tune) {
+                                double* rew_traj, int* qty_traj, float* eps_chunk, float* mt_chunk,
+                                hipStream_t stream, std::string* why, FusedTuning tune) {
   why->clear();
   if (E.A != C.D || E.S != C.S) {
     *why = "fused rollout: ensemble shape does not match the environment";
     return hipSuccess;
   }
-  FusedArgs F{t0, n_steps, sigma, key, env_offset, obs_traj, act_traj, rew_traj, qty_traj};
+  FusedArgs F{t0, n_steps, sigma, key, env_offset, obs_traj, act_traj, rew_traj, qty_traj, nullptr, nullptr};
   int rowt = tune.row_tiles;
   if (rowt <= 0) rowt = C.N >= 4096 ? 2 : 1;
   rowt = rowt >= 2 ? 2 : 1;
   if (tune.schedule != 2 && fused_streamed_shape(C, E))
-    return rowt == 2 ? launch_streamed<2>(C, st, E, F, stream) : launch_streamed<1>(C, st, E, F, stream);
+    return launch_streamed(C, st, E, F, rowt, eps_chunk, mt_chunk, stream);
   if (C.D > 128) {
     *why = "fused rollout: at most 128 stocks";
     return hipSuccess;

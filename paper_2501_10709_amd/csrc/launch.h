@@ -35,6 +35,10 @@ size_t mlp_lds_bytes(int dtype, int S_pad, int H);
 hipError_t launch_pack_matrix(int dtype, const float* w, int kin, int nout, int kin_pad,
                               int nout_pad, void* out, hipStream_t stream);
 hipError_t launch_copy_pad(const float* src, int n, int n_pad, float* dst, hipStream_t stream);
+// Split first layer: the per-environment rows of W1 [S][H] (row 0, rows A+1..2A) as bfloat16
+// MFMA fragments over ke_pad rows; the market rows (1..A, 2A+1..S-1) as bfloat16 [S-1-A][H].
+hipError_t launch_pack_env_rows(const float* w1, int A, int H, int ke_pad, void* out, hipStream_t stream);
+hipError_t launch_gather_market_rows(const float* w1, int S, int H, int A, __bf16* out, hipStream_t stream);
 hipError_t launch_mlp(int dtype, const EnsDev& E, const float* obs, int n, float* mu,
                       hipStream_t stream);
 hipError_t launch_combine(int K, int n, int A, const float* mu, const float* mix, float sigma,

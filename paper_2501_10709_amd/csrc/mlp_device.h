@@ -56,6 +56,14 @@ struct EnsDev {
   size_t actor_stride;
   size_t off_w1, off_w2, off_w3, off_b1, off_b2, off_b3;
   const float* mix;  // [K]
+  // Split first layer (bfloat16 ensembles whose input is a trading state [cash, closes(A),
+  // holdings(A), indicators]): W1 = W1e (rows of the per-environment entries: cash, holdings)
+  // + W1m (rows of the market entries shared by all environments of a day).  split_a = A when
+  // present, else 0.  Regions hold all actors back to back, from base.
+  int split_a;
+  int ke_pad;           // per-environment rows padded to a multiple of 32
+  size_t off_w1e;       // [K][H/16][ke_pad/32][64][8] bfloat16 MFMA fragments
+  size_t off_w1m;       // [K][S-1-A][H] bfloat16, row-major
 };
 
 // tanh from one exponential and one reciprocal: tanh|x| = (1 - e^{-2|x|}) / (1 + e^{-2|x|}).
