@@ -164,9 +164,10 @@ struct ChainShape {
     z.inv_dp = 1.0f / static_cast<float>(z.DP);
     return z;
   }
-  // LDS bytes of the scratch of M rows (16-byte multiple).
+  // LDS bytes of the scratch of M rows and the per-day terms (16-byte multiple).
   __host__ __device__ size_t scratch_bytes(int M) const {
-    return sizeof(double) * 3 * static_cast<size_t>(M) * RD + sizeof(int) * 2 * static_cast<size_t>(M) * RI;
+    return sizeof(double) * 3 * static_cast<size_t>(M) * RD + sizeof(int) * 2 * static_cast<size_t>(M) * RI +
+           sizeof(double) * 2 * DP;
   }
 };
 
@@ -182,6 +183,8 @@ struct ChainLds {
   double* val;
   int* qd;
   int* kq;
+  double* c1;   // [DP] per day: the one-share debit (p*1)*(1+c) of each stock
+  double* rc1;  // [DP] per day: its reciprocal (an estimate's input)
   // Carves the scratch (16-byte aligned base) of M rows; returns the first byte after it.
   __host__ __device__ unsigned char* carve_scratch(unsigned char* base, const ChainShape& Z, int M) {
     pro = reinterpret_cast<double*>(base);
@@ -189,14 +192,32 @@ struct ChainLds {
     val = deb + M * Z.RD;
     qd = reinterpret_cast<int*>(val + M * Z.RD);
     kq = qd + M * Z.RI;
-    return reinterpret_cast<unsigned char*>(kq + M * Z.RI);
+    c1 = reinterpret_cast<double*>(kq + M * Z.RI);
+    rc1 = c1 + Z.DP;
+    return reinterpret_cast<unsigned char*>(rc1 + Z.DP);
   }
 };
 
-// Phase A (all threads, pairs i = first, first + stride, ... over M*DP): orders, sells, the
-// whole-order debit and the reciprocal of the one-share debit c1 = (p*1)*(1+c) (refined by one
-// Newton step; only an estimate's input).  act(m, d, e)
-// yields the action of env m, stock d (e = m*D + d).
+// Per-day terms (threads first, first + stride, ... over DP): c1[d] = (p_d*1)*(1+c) and
+// rc1[d] ~ 1/c1[d], the hardware reciprocal refined by one Newton step -- only the input of an
+// estimate; zero beyond D.
+__device__ __forceinline__ void chain_day_terms(const ChainLds& L, const ChainShape& Z, int first, int stride,
+                                                double one_p) {
+#pragma clang fp contract(off)
+  for (int d = first; d < Z.DP; d += stride) {
+    double c = 0.0, r = 0.0;
+    if (d < Z.D) {
+      c = static_cast<double>(L.px[d]) * one_p;
+      r = __builtin_amdgcn_rcp(c);
+      r = fma(fma(-c, r, 1.0), r, r);
+    }
+    L.c1[d] = c;
+    L.rc1[d] = r;
+  }
+}
+
+// Phase A (all threads, pairs i = first, first + stride, ... over M*DP): orders, sells and the
+// whole-order debit.  act(m, d, e) yields the action of env m, stock d (e = m*D + d).
 template <class Act>
 __device__ __forceinline__ void chain_pairs_a(const ChainLds& L, const ChainShape& Z, int M, int first,
                                               int stride, float hmax_f, double one_m, double one_p, Act act) {
@@ -205,7 +226,7 @@ __device__ __forceinline__ void chain_pairs_a(const ChainLds& L, const ChainShap
   for (int i = first; i < M * Z.DP; i += stride) {
     const int m = div_small(i, Z.inv_dp);
     const int d = i - m * Z.DP;
-    double pro = 0.0, deb = 0.0, rc1 = 0.0;
+    double pro = 0.0, deb = 0.0;
     int qd = 0;
     if (d < Z.D) {
       const int e = m * Z.D + d;
@@ -218,13 +239,9 @@ __device__ __forceinline__ void chain_pairs_a(const ChainLds& L, const ChainShap
       pro = (p * static_cast<double>(s)) * one_m;
       qd = q > 0 ? q : 0;
       deb = (p * static_cast<double>(qd)) * one_p;
-      const double c1 = p * one_p;
-      rc1 = __builtin_amdgcn_rcp(c1);
-      rc1 = fma(fma(-c1, rc1, 1.0), rc1, rc1);  // one Newton step
     }
     L.pro[m * Z.RD + d] = pro;
     L.deb[m * Z.RD + d] = deb;
-    L.val[m * Z.RD + d] = rc1;  // the slot is reused for the position values in phase C
     L.qd[m * Z.RI + d] = qd;
   }
 }
@@ -255,18 +272,20 @@ __device__ __forceinline__ int partial_fill(double cash, double p, double rc1, i
   return k;
 }
 
-// Eight float64 / int / float entries from a 16-byte-aligned LDS address.
-__device__ __forceinline__ void lds8(double (&v)[kChunk], const double* src) {
+// CH (a multiple of 4) float64 / int / float entries from a 16-byte-aligned LDS address.
+template <int CH>
+__device__ __forceinline__ void lds_vec(double (&v)[CH], const double* src) {
 #pragma unroll
-  for (int j = 0; j < kChunk / 2; ++j) {
+  for (int j = 0; j < CH / 2; ++j) {
     const double2 t = reinterpret_cast<const double2*>(src)[j];
     v[2 * j] = t.x;
     v[2 * j + 1] = t.y;
   }
 }
-__device__ __forceinline__ void lds8(int (&v)[kChunk], const int* src) {
+template <int CH>
+__device__ __forceinline__ void lds_vec(int (&v)[CH], const int* src) {
 #pragma unroll
-  for (int j = 0; j < kChunk / 4; ++j) {
+  for (int j = 0; j < CH / 4; ++j) {
     const int4 t = reinterpret_cast<const int4*>(src)[j];
     v[4 * j] = t.x;
     v[4 * j + 1] = t.y;
@@ -274,9 +293,10 @@ __device__ __forceinline__ void lds8(int (&v)[kChunk], const int* src) {
     v[4 * j + 3] = t.w;
   }
 }
-__device__ __forceinline__ void lds8(float (&v)[kChunk], const float* src) {
+template <int CH>
+__device__ __forceinline__ void lds_vec(float (&v)[CH], const float* src) {
 #pragma unroll
-  for (int j = 0; j < kChunk / 4; ++j) {
+  for (int j = 0; j < CH / 4; ++j) {
     const float4 t = reinterpret_cast<const float4*>(src)[j];
     v[4 * j] = t.x;
     v[4 * j + 1] = t.y;
@@ -285,61 +305,71 @@ __device__ __forceinline__ void lds8(float (&v)[kChunk], const float* src) {
   }
 }
 
-// acc + v[0] + ... + v[DP-1] in index order, the terms read chunk by chunk one chunk ahead.
+// acc + v[0] + ... + v[DP-1] in index order, the terms read CH at a time one chunk ahead.
+template <int CH = kChunk>
 __device__ __forceinline__ double chain_sum(double acc, const double* __restrict__ v, int DP) {
 #pragma clang fp contract(off)
-  double cur[kChunk];
-  lds8(cur, v);
-  for (int d0 = 0; d0 < DP; d0 += kChunk) {
-    double nxt[kChunk];
-    lds8(nxt, v + (d0 + kChunk < DP ? d0 + kChunk : d0));
+  double cur[CH];
+  lds_vec<CH>(cur, v);
+  for (int d0 = 0; d0 < DP; d0 += CH) {
+    double nxt[CH];
+    lds_vec<CH>(nxt, v + (d0 + CH < DP ? d0 + CH : d0));
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) acc = acc + cur[j];
+    for (int j = 0; j < CH; ++j) acc = acc + cur[j];
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) cur[j] = nxt[j];
+    for (int j = 0; j < CH; ++j) cur[j] = nxt[j];
   }
   return acc;
 }
 
+template <int CH>
 struct BuyChunk {
-  double deb[kChunk], c1[kChunk];
-  int q[kChunk];
-  float p[kChunk];
-  __device__ __forceinline__ void load(const double* deb_, const double* c1_, const int* q_, const float* p_) {
-    lds8(deb, deb_);
-    lds8(c1, c1_);
-    lds8(q, q_);
-    lds8(p, p_);
+  double deb[CH], c1[CH], rc1[CH];
+  int q[CH];
+  float p[CH];
+  __device__ __forceinline__ void load(const double* deb_, const double* c1_, const double* rc1_, const int* q_,
+                                       const float* p_) {
+    lds_vec<CH>(deb, deb_);
+    lds_vec<CH>(c1, c1_);
+    lds_vec<CH>(rc1, rc1_);
+    lds_vec<CH>(q, q_);
+    lds_vec<CH>(p, p_);
   }
 };
 
 // Phase B (lane m of the owner group): the cash recurrence of environment m -- all sells, then
-// all buys, in ascending stock order.  A buy fills whole when its debit fits the cash (a select);
-// otherwise the partial fill decides (the one divergent branch).  c1s: the reciprocals rc1.
+// all buys, in ascending stock order.  A buy fills whole when its debit fits the cash and not at
+// all when one share does not (selects); otherwise the partial fill decides (the one divergent
+// branch).  c1s, rc1s: the day's one-share debits and their reciprocals (shared by all
+// environments).  CH stocks per register chunk (DP is a multiple of CH).
+template <int CH = kChunk>
 __device__ __forceinline__ void chain_serial(double& cash, const double* __restrict__ pro,
                                              const double* __restrict__ deb, const double* __restrict__ c1s,
-                                             const int* __restrict__ qd, const float* __restrict__ px,
-                                             int* __restrict__ kq, int DP, double one_p) {
+                                             const double* __restrict__ rc1s, const int* __restrict__ qd,
+                                             const float* __restrict__ px, int* __restrict__ kq, int DP,
+                                             double one_p) {
 #pragma clang fp contract(off)
-  cash = chain_sum(cash, pro, DP);
-  BuyChunk cur;
-  cur.load(deb, c1s, qd, px);
-  for (int d0 = 0; d0 < DP; d0 += kChunk) {
-    BuyChunk nxt;
-    const int dn = d0 + kChunk < DP ? d0 + kChunk : d0;
-    nxt.load(deb + dn, c1s + dn, qd + dn, px + dn);
-    int k[kChunk];
+  static_assert(CH % 4 == 0 && kChunk % CH == 0, "chunks of 4 or 8 stocks");
+  cash = chain_sum<CH>(cash, pro, DP);
+  BuyChunk<CH> cur;
+  cur.load(deb, c1s, rc1s, qd, px);
+  for (int d0 = 0; d0 < DP; d0 += CH) {
+    BuyChunk<CH> nxt;
+    const int dn = d0 + CH < DP ? d0 + CH : d0;
+    nxt.load(deb + dn, c1s + dn, rc1s + dn, qd + dn, px + dn);
+    int k[CH];
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
+    for (int j = 0; j < CH; ++j) {
       const bool fits = cur.deb[j] <= cash;
       int kj = fits ? cur.q[j] : 0;
       double debit = fits ? cur.deb[j] : 0.0;
-      if (!fits) kj = partial_fill(cash, static_cast<double>(cur.p[j]), cur.c1[j], cur.q[j], one_p, debit);
+      if (!fits && cur.c1[j] <= cash)
+        kj = partial_fill(cash, static_cast<double>(cur.p[j]), cur.rc1[j], cur.q[j], one_p, debit);
       cash = cash - debit;
       k[j] = kj;
     }
 #pragma unroll
-    for (int j = 0; j < kChunk / 4; ++j)
+    for (int j = 0; j < CH / 4; ++j)
       reinterpret_cast<int4*>(kq + d0)[j] = int4{k[4 * j], k[4 * j + 1], k[4 * j + 2], k[4 * j + 3]};
     cur = nxt;
   }
@@ -377,8 +407,9 @@ __device__ __forceinline__ void chain_pairs_c(const ChainLds& L, const ChainShap
 }
 
 // Phase D (lane m): v = cash + sum_d p'_d h_d in ascending stock order.
+template <int CH = kChunk>
 __device__ __forceinline__ double chain_value(double cash, const double* __restrict__ val, int DP) {
-  return chain_sum(cash, val, DP);
+  return chain_sum<CH>(cash, val, DP);
 }
 
 // Holdings entries and position values without trading (reset / observe): all threads.

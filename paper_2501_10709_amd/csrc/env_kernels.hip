@@ -204,11 +204,12 @@ __global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvStat
         // The chain: parallel pre-terms, serial cash recurrence per env, parallel post-terms.
         wave_lds_sync();
         if (trades(MODE)) {
+          chain_day_terms(CL, Z, lane, kWave, C.one_p);
           chain_pairs_a(CL, Z, M, lane, kWave, C.hmax_f, C.one_m, C.one_p);
           wave_lds_sync();
           if (active)
-            chain_serial(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.val + lane * Z.RD,
-                         CL.qd + lane * Z.RI, CL.px, CL.kq + lane * Z.RI, Z.DP, C.one_p);
+            chain_serial(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.c1, CL.rc1, CL.qd + lane * Z.RI, CL.px,
+                         CL.kq + lane * Z.RI, Z.DP, C.one_p);
           wave_lds_sync();
           chain_pairs_c(CL, Z, M, lane, kWave, C.hold_scale);
         } else {

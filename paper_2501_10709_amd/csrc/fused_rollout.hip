@@ -159,11 +159,12 @@ struct EnvPhase {
   __device__ double chain(bool owner, double& cash, double& asset, double& cumrew) {
     const ChainShape Z = ChainShape::of(C.D);
     const ChainLds& CL = L.chain;
+    chain_day_terms(CL, Z, tid, NT, C.one_p);
     chain_pairs_a(CL, Z, M, tid, NT, C.hmax_f, C.one_m, C.one_p);
     __syncthreads();
     if (owner)
-      chain_serial(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.val + lane * Z.RD, CL.qd + lane * Z.RI,
-                   CL.px, CL.kq + lane * Z.RI, Z.DP, C.one_p);
+      chain_serial(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.c1, CL.rc1, CL.qd + lane * Z.RI, CL.px,
+                   CL.kq + lane * Z.RI, Z.DP, C.one_p);
     __syncthreads();
     chain_pairs_c(CL, Z, M, tid, NT, C.hold_scale);
     __syncthreads();
@@ -262,16 +263,21 @@ __device__ __forceinline__ void layer_bf16(const __bf16* sin, int ist, int kin_p
 // ------------------------------------------------------------------------------------------
 // Streamed MLP schedule for K = 3, H = 256, A_pad = 32 over the split first layer: layer 1 runs
 // on the per-environment entries only (KKE k-steps of 32 rows: cash, holdings, zero padding),
-// its market share comes from the day's table.  NWAVES wavefronts; wavefront w owns layer-1/2
-// output tiles w, w+NWAVES, ... and, if w < 2, layer-3 tile w.  Its weight fragments form a
+// its market share comes from the day's table.  NWAVES wavefronts; in layers 1 and 2 wavefront w
+// owns output tiles w, w+NWAVES, ...; layer 3 (two output tiles) is split over the K dimension:
+// wavefront w takes k-blocks w*L3 .. w*L3+L3-1 of both tiles and leaves partial sums, which the
+// action phase adds up.  Every wavefront requests the same number of fragments at every
+// position, so the wait counts of the register ring are exact.  Its weight fragments form a
 // fixed sequence of NS k-steps per environment step; fragments for k-step s+DEPTH are requested
 // when k-step s is consumed.
 // ------------------------------------------------------------------------------------------
 template <int KKE, int ROWT, int DEPTH, int NWAVES>
 struct Streamed {
   static constexpr int K = 3, KK2 = 8, HT = 16, AT = 2, NW = NWAVES, TW = HT / NWAVES;
-  static constexpr int SPA = KKE + 2 * KK2;  // k-steps per actor
-  static constexpr int NS = K * SPA;         // k-steps per environment step
+  static constexpr int L3 = KK2 / NWAVES;          // layer-3 k-steps per wavefront
+  static constexpr int SPA = KKE + KK2 + L3;       // k-steps per actor
+  static constexpr int NS = K * SPA;               // k-steps per environment step
+  static_assert(TW >= AT, "a ring slot holds the layer-3 fragments of both tiles");
   // The schedule walks NSP >= NS positions per step, a multiple of DEPTH, so that k-step j always
   // uses ring slot j % DEPTH, also across the wrap into the next step; positions >= NS are idle.
   static constexpr int NSP = (NS + DEPTH - 1) / DEPTH * DEPTH;
@@ -301,9 +307,12 @@ struct Streamed {
       for (int i = 0; i < TW; ++i)
         b[i] = *reinterpret_cast<const bf16x8*>(P + kW2 + static_cast<size_t>((wv + NW * i) * KK2 + kk) * 1024 + voff);
     } else {
-      constexpr int kk = r - KKE - KK2;
+      constexpr int j = r - KKE - KK2;
+      const int kk = wv * L3 + j;
       const unsigned char* P = wb + kActor * actor;
-      if (wv < AT) b[0] = *reinterpret_cast<const bf16x8*>(P + kW3 + static_cast<size_t>(wv * KK2 + kk) * 1024 + voff);
+#pragma unroll
+      for (int c = 0; c < AT; ++c)
+        b[c] = *reinterpret_cast<const bf16x8*>(P + kW3 + static_cast<size_t>(c * KK2 + kk) * 1024 + voff);
     }
   }
 };
@@ -355,14 +364,16 @@ __global__ void noise_chunk_kernel(uint64_t key, int64_t env_offset, int t0, int
 // ------------------------------------------------------------------------------------------
 // Streamed kernel.  Five wavefronts with two roles:
 //   wavefronts 0-3 (MLP): the three layers of the K actors for the tile's state rows, weight
-//     fragments streamed through a register ring; then the parallel chain phases (actions,
-//     orders and sells; buys applied, holdings entries of the next state rows);
-//   wavefront 4 (environment): while the MLP of step t runs, the stores of step t-1's results
-//     and the staging of step t+1's inputs (market rows, noise, market table) from registers
-//     into LDS, then the requests for step t+2's; after the MLP, the serial cash recurrence and
-//     the value and reward of each environment (lane m owns environment m and its cash, value
-//     and cumulative reward).
+//     fragments streamed through a register ring; then the trading chain: the parallel phases
+//     over (env, stock) pairs (actions, orders and sells; buys applied, holdings entries of the
+//     next state rows) and the serial ones, where lane l of wavefront w runs environment
+//     w*MR/4 + l (the cash recurrence, then the value and reward);
+//   wavefront 4 (memory): while the chain runs and no weights stream, the stores of step t-1's
+//     results, the staging of step t+1's inputs (market rows, noise, market table) from
+//     registers into LDS, and the requests for step t+2's.  Its vector-memory traffic never
+//     delays the MLP wavefronts' weight waits, which count only their own requests.
 // The two roles run separate loops that pass the same sequence of workgroup barriers per step.
+// The trading state (cash, value, cumulative reward, holdings) stays in LDS for the launch.
 // State rows, actions, quantities, state entries, rewards, noise and table rows are
 // double-buffered by step parity; the market rows [close[t] | close[t+1] | ind[t+1]] are
 // triple-buffered by step (the results of step t read them during step t+1).
@@ -382,7 +393,7 @@ struct StreamLds {
   __bf16* x2;     // [MR][STH]
   float* bias;    // [K][kBiasStride]
   float* mix;     // [K]
-  float* abar;    // [MR][DS] ensemble mean
+  float* part;    // [K][NW][MR][32] layer-3 partial sums by actor and wavefront
   float* eps_;    // [2][MR][D] noise
   float* mt_;     // [2][K][H] layer-1 market share
   float* act_;    // [2][MR][D]
@@ -390,6 +401,9 @@ struct StreamLds {
   float* env_;    // [2][MR][DS] cash entry, holdings entries
   double* rew_;   // [2][MR]
   int* hold;      // [MR][D]
+  double* cash;   // [MR] the trading state: cash, pre-trade value, cumulative reward
+  double* asset;  // [MR]
+  double* cumrew; // [MR]
   float* in_;     // [3][IN] market rows of a step
   int x0s, epss, mts, acts, qtys, envs, rews, ins;
   ChainLds chain;
@@ -406,7 +420,7 @@ struct StreamLds {
   static __host__ __device__ size_t a16(size_t b) { return (b + 15) / 16 * 16; }
   // Byte offsets of the regions and the total.
   struct Offsets {
-    size_t sc, x0, x1, x2, bias, mix, abar, eps, mt, act, qty, env, rew, hold, in, total;
+    size_t sc, x0, x1, x2, bias, mix, part, eps, mt, act, qty, env, rew, hold, state, in, total;
     size_t x0b, epsb, mtb, actb, qtyb, envb, rewb, inb;  // bytes per buffer
   };
   __host__ __device__ static Offsets offsets(int MR, int st0, int sth, int D, int I) {
@@ -428,13 +442,17 @@ struct StreamLds {
     o.rewb = a16(sizeof(double) * MR);
     const size_t nin = static_cast<size_t>(2 + I) * D;
     o.inb = a16(sizeof(float) * (nin > static_cast<size_t>(Z.DP) ? nin : static_cast<size_t>(Z.DP)));
-    o.sc = take(Z.scratch_bytes(MR));
+    // The chain's scratch (used after the MLP) shares its region with the layer-1/2 outputs
+    // (used during the MLP only).
+    const size_t xb = a16(sizeof(__bf16) * MR * sth);
+    const size_t region = Z.scratch_bytes(MR) > 2 * xb ? Z.scratch_bytes(MR) : 2 * xb;
+    o.sc = take(region);
+    o.x1 = o.sc;
+    o.x2 = o.sc + xb;
     o.x0 = take(2 * o.x0b);
-    o.x1 = take(sizeof(__bf16) * MR * sth);
-    o.x2 = take(sizeof(__bf16) * MR * sth);
     o.bias = take(sizeof(float) * kStreamK * kBiasStride);
     o.mix = take(sizeof(float) * kStreamK);
-    o.abar = take(sizeof(float) * MR * DS);
+    o.part = take(sizeof(float) * kStreamK * kMlpWaves * MR * 32);
     o.eps = take(2 * o.epsb);
     o.mt = take(2 * o.mtb);
     o.act = take(2 * o.actb);
@@ -442,6 +460,7 @@ struct StreamLds {
     o.env = take(2 * o.envb);
     o.rew = take(2 * o.rewb);
     o.hold = take(sizeof(int) * MR * D);
+    o.state = take(sizeof(double) * 3 * MR);
     o.in = take(3 * o.inb);
     o.total = a16(p);
     return o;
@@ -453,7 +472,7 @@ struct StreamLds {
     x2 = reinterpret_cast<__bf16*>(smem + o.x2);
     bias = reinterpret_cast<float*>(smem + o.bias);
     mix = reinterpret_cast<float*>(smem + o.mix);
-    abar = reinterpret_cast<float*>(smem + o.abar);
+    part = reinterpret_cast<float*>(smem + o.part);
     eps_ = reinterpret_cast<float*>(smem + o.eps);
     mt_ = reinterpret_cast<float*>(smem + o.mt);
     act_ = reinterpret_cast<float*>(smem + o.act);
@@ -461,6 +480,9 @@ struct StreamLds {
     env_ = reinterpret_cast<float*>(smem + o.env);
     rew_ = reinterpret_cast<double*>(smem + o.rew);
     hold = reinterpret_cast<int*>(smem + o.hold);
+    cash = reinterpret_cast<double*>(smem + o.state);
+    asset = cash + MR;
+    cumrew = asset + MR;
     in_ = reinterpret_cast<float*>(smem + o.in);
     x0s = static_cast<int>(o.x0b / sizeof(__bf16));
     epss = static_cast<int>(o.epsb / sizeof(float));
@@ -483,8 +505,9 @@ __global__ __launch_bounds__(kStreamThreads) void fused_streamed_kernel(EnvConst
   constexpr int KK2 = SP::KK2, SPA = SP::SPA, NS = SP::NS, NSP = SP::NSP;
   constexpr int H = kStreamH, K = kStreamK;
   constexpr int ST0 = 32 * KKE + 8, STH = H + 8;
-  constexpr int NBAR = K * 3;                     // layer-end barriers per step
+  constexpr int NBAR = 2 * K + 1;                 // layer-end barriers per step
   constexpr int EPS_STAGE = (MR * 32 + 63) / 64;  // registers per lane for a step's noise (D <= 32)
+  constexpr int SPW = MR / kMlpWaves;             // environments per MLP wavefront in the serial phases
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -562,20 +585,21 @@ __global__ __launch_bounds__(kStreamThreads) void fused_streamed_kernel(EnvConst
 
         const __bf16* src = layer == 1 ? xin : (layer == 2 ? L.x1 : L.x2);
         constexpr int ist = layer == 1 ? ST0 : STH;
+        const int kcol = layer == 3 ? 32 * (wv * SP::L3 + kk) : 32 * kk;
         bf16x8 a[ROWT];
 #pragma unroll
         for (int rt = 0; rt < ROWT; ++rt)
-          a[rt] = *reinterpret_cast<const bf16x8*>(src + (rt * 16 + row) * ist + 32 * kk + 8 * grp);
+          a[rt] = *reinterpret_cast<const bf16x8*>(src + (rt * 16 + row) * ist + kcol + 8 * grp);
         if constexpr (layer < 3) {
 #pragma unroll
           for (int i = 0; i < TW; ++i)
 #pragma unroll
             for (int rt = 0; rt < ROWT; ++rt) acc[rt][i] = mfma_bf16(a[rt], cur[i], acc[rt][i]);
         } else {
-          if (wv < SP::AT) {
 #pragma unroll
-            for (int rt = 0; rt < ROWT; ++rt) acc[rt][0] = mfma_bf16(a[rt], cur[0], acc[rt][0]);
-          }
+          for (int c = 0; c < SP::AT; ++c)
+#pragma unroll
+            for (int rt = 0; rt < ROWT; ++rt) acc[rt][c] = mfma_bf16(a[rt], cur[c], acc[rt][c]);
         }
 
         if constexpr (r == last) {
@@ -593,28 +617,22 @@ __global__ __launch_bounds__(kStreamThreads) void fused_streamed_kernel(EnvConst
                 for (int q = 0; q < 4; ++q)
                   out[(rt * 16 + row_q + q) * STH + col] = static_cast<__bf16>(fast_tanh(acc[rt][i][q] + bc));
             }
+            __syncthreads();  // layer end
           } else {
-            if (wv < SP::AT) {
-              const int col = 16 * wv + col_l;
-              if (col < E.A) {
-                const float bc = L.bias[actor * kBiasStride + H + col];
-                const float wk = L.mix[actor];
+            // This wavefront's share of the layer-3 sums of this actor.
+            float* pp = L.part + (actor * NW + wv) * MR * 32;
 #pragma unroll
-                for (int rt = 0; rt < ROWT; ++rt)
+            for (int c = 0; c < SP::AT; ++c)
 #pragma unroll
-                  for (int q = 0; q < 4; ++q) {
-                    float* dst = &L.abar[(rt * 16 + row_q + q) * DS + col];
-                    const float v = wk * fast_tanh(acc[rt][0][q] + bc);
-                    *dst = (actor == 0) ? v : (*dst + v);
-                  }
-              }
-            }
+              for (int rt = 0; rt < ROWT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pp[(rt * 16 + row_q + q) * 32 + 16 * c + col_l] = acc[rt][c][q];
+            if constexpr (actor == K - 1) __syncthreads();  // all partial sums written
           }
-          __syncthreads();  // layer end
         }
       });
 
-      // Actions a = clip(a_bar + sigma * eps), orders, sells, debits.
+      // Actions a = clip(a_bar + sigma * eps), orders, sells, debits; the day's reciprocals.
       const float* in = L.in(it % 3);
       const float* eps = L.eps(it & 1);
       ChainLds CL = L.chain;
@@ -623,32 +641,62 @@ __global__ __launch_bounds__(kStreamThreads) void fused_streamed_kernel(EnvConst
       CL.qty = L.qty(it & 1);
       CL.env = L.env(it & 1);
       float* actb = L.act(it & 1);
+      chain_day_terms(CL, Z, tid, 64 * NW, C.one_p);
       chain_pairs_a(CL, Z, M, tid, 64 * NW, C.hmax_f, C.one_m, C.one_p, [&](int m, int d, int e) {
-        float a = L.abar[m * DS + d];
+        // a_bar = sum_k w_k tanh(z_k + b3_k), z_k the sum of the wavefronts' partial sums.
+        float a = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float* pk = L.part + k * NW * MR * 32 + m * 32 + d;
+          float z = pk[0];
+#pragma unroll
+          for (int w = 1; w < NW; ++w) z = z + pk[w * MR * 32];
+          const float v = L.mix[k] * fast_tanh(z + L.bias[k * kBiasStride + H + d]);
+          a = k == 0 ? v : a + v;
+        }
         if (sigma != 0.0f) a = a + sigma * eps[e];
         a = fminf(fmaxf(a, -1.0f), 1.0f);
         actb[e] = a;
         return a;
       });
       __syncthreads();  // A
-      __syncthreads();  // S: the cash recurrences (environment wavefront)
+      // The cash recurrences: lane l of wavefront w runs environment w*SPW + l.
+      const int me = wv * SPW + lane;
+      const bool mine = lane < SPW && me < M;
+      if (mine) {
+        double cash = L.cash[me];
+        chain_serial<4>(cash, CL.pro + me * Z.RD, CL.deb + me * Z.RD, CL.c1, CL.rc1, CL.qd + me * Z.RI, in,
+                        CL.kq + me * Z.RI, Z.DP, C.one_p);
+        L.cash[me] = cash;
+      }
+      __syncthreads();  // S
       __bf16* xn = L.x0((it + 1) & 1);
       chain_pairs_c(CL, Z, M, tid, 64 * NW, C.hold_scale,
                     [&](int m, int d, float he) { xn[m * ST0 + 1 + d] = static_cast<__bf16>(he); });
       __syncthreads();  // C
+      if (mine) {
+        const double cash = L.cash[me];
+        const double v_new = chain_value<4>(cash, CL.val + me * Z.RD, Z.DP);
+        const double r = (v_new - L.asset[me]) * C.reward_scale;
+        L.cumrew[me] = L.cumrew[me] + r;
+        L.asset[me] = v_new;
+        const float ce = static_cast<float>(cash * static_cast<double>(C.cash_scale));
+        CL.env[me * DS] = ce;
+        xn[me * ST0] = static_cast<__bf16>(ce);
+        L.rew(it & 1)[me] = r;
+      }
     }
     __syncthreads();  // end
     return;
   }
 
-  // ------------------------------------------------------------------ environment wavefront
+  // ------------------------------------------------------------------ memory wavefront
   const bool owner = lane < M;
   const int n = n0 + lane;
-  double cash = 0.0, asset = 0.0, cumrew = 0.0;
   if (owner) {
-    cash = st.cash[n];
-    asset = st.asset[n];
-    cumrew = st.cumrew[n];
+    L.cash[lane] = st.cash[n];
+    L.asset[lane] = st.asset[n];
+    L.cumrew[lane] = st.cumrew[n];
     for (int d = 0; d < D; ++d) L.hold[lane * D + d] = st.hold[static_cast<size_t>(d) * N + n];
   }
   const int n_mkt = (2 + I) * D, MD = M * D;
@@ -710,7 +758,7 @@ __global__ __launch_bounds__(kStreamThreads) void fused_streamed_kernel(EnvConst
   // The first state rows: the cash and holdings entries.
   if (owner) {
     __bf16* x = L.x0(0) + lane * ST0;
-    x[0] = static_cast<__bf16>(static_cast<float>(cash * static_cast<double>(C.cash_scale)));
+    x[0] = static_cast<__bf16>(static_cast<float>(L.cash[lane] * static_cast<double>(C.cash_scale)));
     for (int d = 0; d < D; ++d) x[1 + d] = static_cast<__bf16>(static_cast<float>(L.hold[lane * D + d]) * C.hold_scale);
   }
   issue(0);
@@ -719,39 +767,23 @@ __global__ __launch_bounds__(kStreamThreads) void fused_streamed_kernel(EnvConst
   __syncthreads();  // the first state rows and inputs are staged
 
   for (int it = 0; it < F.n_steps; ++it) {
-    __syncthreads();  // T
-    __syncthreads();  // end of layer 1 of the first actor: the longer layer-2 interval follows
-    if (it >= 1) results(it - 1);
-    if (it + 1 < F.n_steps) {
+    __syncthreads();                                 // T
+    for (int b = 0; b < NBAR; ++b) __syncthreads();  // layer ends
+    if (it >= 1) results(it - 1);                    // while the orders are made
+    __syncthreads();                                 // A
+    if (it + 1 < F.n_steps) {                        // while the cash recurrences run
       commit(it + 1);
       if (it + 2 < F.n_steps) issue(it + 2);
     }
-    for (int b = 1; b < NBAR; ++b) __syncthreads();  // the other layer ends
-    __syncthreads();  // A
-    const float* in = L.in(it % 3);
-    const ChainLds& CL = L.chain;
-    if (owner)
-      chain_serial(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.val + lane * Z.RD, CL.qd + lane * Z.RI,
-                   in, CL.kq + lane * Z.RI, Z.DP, C.one_p);
     __syncthreads();  // S
     __syncthreads();  // C
-    if (owner) {
-      const double v_new = chain_value(cash, CL.val + lane * Z.RD, Z.DP);
-      const double r = (v_new - asset) * C.reward_scale;
-      cumrew = cumrew + r;
-      asset = v_new;
-      const float ce = static_cast<float>(cash * static_cast<double>(C.cash_scale));
-      L.env(it & 1)[lane * DS] = ce;
-      L.x0((it + 1) & 1)[lane * ST0] = static_cast<__bf16>(ce);
-      L.rew(it & 1)[lane] = r;
-    }
   }
   __syncthreads();  // end
   if (F.n_steps >= 1) results(F.n_steps - 1);
   if (owner) {
-    st.cash[n] = cash;
-    st.asset[n] = asset;
-    st.cumrew[n] = cumrew;
+    st.cash[n] = L.cash[lane];
+    st.asset[n] = L.asset[lane];
+    st.cumrew[n] = L.cumrew[lane];
     for (int d = 0; d < D; ++d) st.hold[static_cast<size_t>(d) * N + n] = L.hold[lane * D + d];
   }
 }
