@@ -129,6 +129,12 @@ fm_status env_write_state(fm_env* env, const double* d_cash, const int32_t* d_ho
 
 /* The environment's current day (host-side bookkeeping; -1 for NULL). */
 int32_t env_day(const fm_env* env);
+
+/* Tuning (no effect on results): environments per workgroup of the environment kernels, 1..64;
+ * 0 restores the size-based default.  A value whose LDS footprint does not fit is lowered at
+ * launch.  Returns FM_ERR_INVALID for NULL or out-of-range values.  *h_tile (may be NULL) gets
+ * the value in effect. */
+fm_status env_set_tile(fm_env* env, int32_t envs_per_group, int32_t* h_tile);
 void env_destroy(fm_env* env);
 
 /* ---------------------------------------------------------------------------------------------

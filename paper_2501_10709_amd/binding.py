@@ -20,7 +20,7 @@ FM_PATH_PLAIN, FM_PATH_FUSED = 0, 1
 # Symbols declared in include/finrl_mi.h.
 EXPORTS = (
     "env_workspace_bytes", "env_create", "env_reset", "env_step", "env_rollout", "env_read_state",
-    "env_write_state", "env_day", "env_destroy", "ensemble_workspace_bytes", "ensemble_create",
+    "env_write_state", "env_day", "env_set_tile", "env_destroy", "ensemble_workspace_bytes", "ensemble_create",
     "ensemble_act", "ensemble_destroy", "fm_last_error", "fm_noise", "fm_version", "fm_backtest_metrics",
     "fm_sharpe_weights",
 )
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH):
         "env_read_state": (I32, [P, P, P, P, P, ctypes.POINTER(I32)]),
         "env_write_state": (I32, [P, P, P, P, P, I32]),
         "env_day": (I32, [P]),
+        "env_set_tile": (I32, [P, I32, ctypes.POINTER(I32)]),
         "env_destroy": (None, [P]),
         "ensemble_workspace_bytes": (SZ, [I32, I32, I32, I32, I32, I32]),
         "ensemble_create": (I32, [I32, I32, I32, I32, I32, P, P, I32, P, SZ, P, ctypes.POINTER(P)]),
@@ -192,6 +193,12 @@ def env_write_state(env, d_cash, d_hold, d_asset, d_cumrew, day: int):
 
 def env_day(env) -> int:
     return int(load().env_day(env))
+
+
+def env_set_tile(env, envs_per_group: int) -> int:
+    out = ctypes.c_int32(0)
+    _check(load().env_set_tile(env, int(envs_per_group), ctypes.byref(out)))
+    return out.value
 
 
 def env_destroy(env):

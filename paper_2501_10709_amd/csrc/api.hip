@@ -31,9 +31,12 @@ bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % kAlign) =
 
 // Environments per 64-lane workgroup of the environment kernels: small tiles spread the serial
 // trading chains over more compute units; the tile is capped by the kernels' LDS budget.
+// Environments per workgroup of the environment kernels by problem size (measured on MI355X,
+// D = 30, driven rollouts): small tiles while the grid does not fill the GPU, large tiles once it
+// does (the per-step cost of a workgroup grows much slower than its tile).
 int env_tile(int N) {
-  if (N >= 16384) return 32;
-  if (N >= 4096) return 16;
+  if (N >= 16384) return 64;
+  if (N >= 8192) return 32;
   return 8;
 }
 
@@ -360,6 +363,14 @@ fm_status env_write_state(fm_env* env, const double* d_cash, const int32_t* d_ho
 }
 
 int32_t env_day(const fm_env* env) { return env ? env->day : -1; }
+
+fm_status env_set_tile(fm_env* env, int32_t envs_per_group, int32_t* h_tile) {
+  if (!env) return fail(FM_ERR_INVALID, "env is NULL");
+  if (envs_per_group < 0 || envs_per_group > 64) return fail(FM_ERR_INVALID, "envs_per_group must be in 0..64");
+  env->tile = envs_per_group == 0 ? env_tile(env->C.N) : envs_per_group;
+  if (h_tile) *h_tile = env->tile;
+  return FM_OK;
+}
 
 void env_destroy(fm_env* env) { delete env; }
 

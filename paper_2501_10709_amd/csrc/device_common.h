@@ -252,9 +252,11 @@ __device__ __forceinline__ void chain_pairs_a(const ChainLds& L, const ChainShap
 
 // The buy of one stock that does not fit whole: (p*q)*one_p > cash.  The answer is the largest k
 // in [0, q-1] with (p*k)*one_p <= cash (a zero-share buy debits nothing; q <= 0 gives 0).  The
-// debit is monotone in k.  The estimate k = floor(cash * rc1), rc1 ~ 1/((p*1)*one_p), clamped to
-// [0, max(q-1, 0)], is kept when the debits of k and k+1 bracket cash; otherwise unit steps from
-// it reach the answer, whatever the estimate's error.  k stays in float64 (an exact small integer) on the common path.
+// debit is monotone in k.  The estimate k = floor(cash * rc1), rc1 ~ 1/((p*1)*one_p) (relative
+// error below 2^-44), clamped to [0, max(q-1, 0)], is kept when the debits of k and k+1 bracket
+// cash; otherwise unit steps from it reach the answer, whatever the estimate's error (for orders
+// below 2^20 shares the estimate is at most one share off, so at most one step is taken).  k stays
+// in float64 (an exact small integer) on the common path.
 __device__ __forceinline__ int partial_fill(double cash, double p, double rc1, int q, double one_p,
                                            double& debit) {
 #pragma clang fp contract(off)
@@ -432,9 +434,12 @@ __device__ __forceinline__ void chain_pairs_hold(const ChainLds& L, const ChainS
 // The state rows s_{t+1} = [cash, new closes, holdings, new indicators] of M environments from
 // LDS into dst[m][0..S) (row stride S), with one wavefront: lane f writes entry f (f, f+64, ...) of
 // every row, so each store instruction covers 64 consecutive entries.  env[m][0..D]: cash entry,
-// holdings entries (row stride DS); in: [close[t] (D) | close[t+1] (D) | ind[t+1] (I*D)].
+// holdings entries (row stride DS); in: [close[t] (D) | close[t+1] (D) | ind[t+1] (I*D)].  Rows go
+// in batches of 8: all eight LDS reads are issued before the first store, so the LDS latency is
+// paid once per batch rather than once per entry.
 __device__ __forceinline__ void store_state_rows(float* dst, int M, int S, int D, const float* env, int DS,
                                                  const float* in, float price_scale, int lane) {
+  constexpr int B = 8;
   for (int f = lane; f < S; f += 64) {
     const float* src;
     int stride = 0;
@@ -452,8 +457,15 @@ __device__ __forceinline__ void store_state_rows(float* dst, int M, int S, int D
       src = in + (f - 1);  // ind[t+1][f-1-2D]
     }
     float* o = dst + f;
-#pragma unroll 8
-    for (int m = 0; m < M; ++m) o[static_cast<size_t>(m) * S] = src[m * stride] * scale;
+    for (int m0 = 0; m0 < M; m0 += B) {
+      float v[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) v[j] = src[min(m0 + j, M - 1) * stride];  // rows past M: row M-1
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < B; ++j)
+        if (m0 + j < M) o[static_cast<size_t>(m0 + j) * S] = v[j] * scale;
+    }
   }
 }
 

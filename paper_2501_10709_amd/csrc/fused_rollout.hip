@@ -368,10 +368,11 @@ __global__ void noise_chunk_kernel(uint64_t key, int64_t env_offset, int t0, int
 //     over (env, stock) pairs (actions, orders and sells; buys applied, holdings entries of the
 //     next state rows) and the serial ones, where lane l of wavefront w runs environment
 //     w*MR/4 + l (the cash recurrence, then the value and reward);
-//   wavefront 4 (memory): while the chain runs and no weights stream, the stores of step t-1's
-//     results, the staging of step t+1's inputs (market rows, noise, market table) from
-//     registers into LDS, and the requests for step t+2's.  Its vector-memory traffic never
-//     delays the MLP wavefronts' weight waits, which count only their own requests.
+//   wavefront 4 (memory): during the MLP of step t, the staging of step t+1's inputs (market
+//     rows, noise, market table) from registers into LDS and the requests for step t+2's; while
+//     the cash recurrences of step t run, the stores of step t-1's results.  Its vector-memory
+//     traffic never delays the MLP wavefronts' weight waits, which count only their own
+//     requests.
 // The two roles run separate loops that pass the same sequence of workgroup barriers per step.
 // The trading state (cash, value, cumulative reward, holdings) stays in LDS for the launch.
 // State rows, actions, quantities, state entries, rewards, noise and table rows are
@@ -767,14 +768,15 @@ __global__ __launch_bounds__(kStreamThreads) void fused_streamed_kernel(EnvConst
   __syncthreads();  // the first state rows and inputs are staged
 
   for (int it = 0; it < F.n_steps; ++it) {
-    __syncthreads();                                 // T
-    for (int b = 0; b < NBAR; ++b) __syncthreads();  // layer ends
-    if (it >= 1) results(it - 1);                    // while the orders are made
+    __syncthreads();  // T
+    // During layer 1 of the first actor: step it+1's inputs into LDS (no HBM traffic).
+    if (it + 1 < F.n_steps) commit(it + 1);
+    __syncthreads();  // end of layer 1 of the first actor
+    // During layer 2: the requests for step it+2's inputs.
+    if (it + 2 < F.n_steps) issue(it + 2);
+    for (int b = 1; b < NBAR; ++b) __syncthreads();  // the other layer ends
     __syncthreads();                                 // A
-    if (it + 1 < F.n_steps) {                        // while the cash recurrences run
-      commit(it + 1);
-      if (it + 2 < F.n_steps) issue(it + 2);
-    }
+    if (it >= 1) results(it - 1);                    // while the cash recurrences run
     __syncthreads();  // S
     __syncthreads();  // C
   }

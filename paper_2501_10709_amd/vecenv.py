@@ -79,6 +79,10 @@ class VecEnv:
     def day(self) -> int:
         return B.env_day(self.handle)
 
+    def set_tile(self, envs_per_group: int) -> int:
+        """Environments per workgroup of the environment kernels (0: size-based default)."""
+        return B.env_set_tile(self.handle, envs_per_group)
+
     def reset(self, return_obs=True):
         obs = torch.empty((self.N, self.S), dtype=torch.float32, device=self.device) if return_obs else None
         B.env_reset(self.handle, obs)

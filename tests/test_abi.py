@@ -103,3 +103,8 @@ def test_sharpe_weights_match_oracle():
         assert np.allclose(got, want, rtol=1e-6, atol=1e-7), (s, got, want)
     with pytest.raises(B.FmError):
         B.fm_sharpe_weights([float("nan"), 1.0])
+
+
+def test_env_set_tile_validation(lib):
+    assert lib.env_set_tile(None, 8, None) == B.FM_ERR_INVALID
+    assert "NULL" in B.fm_last_error()
