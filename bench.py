@@ -10,9 +10,16 @@ Reported:
   value        env-steps/s (N*T / median rollout time) of the fused bfloat16 path
   fp32_plain   the same for the plain float32 path (per-step MLP and environment launches)
   latency_ms   p50 / p99 rollout latency of both paths
-  roofline     the fused kernel against the bfloat16 MFMA peak (763,392 flop per env-step)
-  env_roofline the driven-mode environment kernel against HBM peak (1,092 B per env-step)
-  cpu_baseline the CPU oracle (float64 numpy) on the same workload
+  roofline     the fused kernel against the bfloat16 MFMA peak: algorithmic flops per launch
+               (763,392 per env-step x envs x steps of the launch) over the average launch time,
+               timed with HIP events on the stream the kernels run on (the rollout launches one
+               fused kernel per chunk of up to 64 steps)
+  env_roofline the driven-mode environment kernel against HBM peak (1,092 B per env-step), at the
+               headline size and at a size that fills the GPU (N = 65536, T = 64)
+  cpu_baseline the CPU oracle (float64 numpy) on a bounded sample of the same workload
+`traffic` comes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in profiles/traffic.json,
+scaled by the counters' reading for a copy kernel of known size; it is null when the kernel
+sources have changed since those runs (a hash of the sources is stored with the numbers).
 Inputs are generated on the host and uploaded before timing.
 """
 from __future__ import annotations
@@ -44,6 +51,34 @@ def env_bytes_per_env_step(D, S):
     return 4 * D + 4 * S + 8 + 4 * D
 
 
+CHUNK = 64  # steps per fused-kernel launch (the library's chunk)
+
+
+def source_hash():
+    """Hash of the HIP sources: counter readings are only valid for the code they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2501_10709_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel_key, per_launch_units):
+    """HBM bytes per launch from the committed counter summary, or None if stale or absent."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash() or kernel_key not in t.get("kernels", {}):
+        return None
+    k = t["kernels"][kernel_key]
+    return k["bytes_per_unit"] * per_launch_units
+
+
 def _pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
@@ -73,6 +108,26 @@ def time_rollouts(env, n_steps, reps, warmup, stream, **kw):
         totals.append(a.elapsed_time(c))
         kernels.append(b.elapsed_time(c))
     return totals, kernels, wall, out
+
+
+def time_launches(env, n_steps, reps, stream, **kw):
+    """Per-launch durations of a rollout issued chunk by chunk (one fused launch per call).
+    Returns a list of (steps, ms) over reps rollouts."""
+    import torch
+    out, res = None, []
+    for _ in range(reps):
+        env.reset(return_obs=False)
+        evs = []
+        for c0 in range(0, n_steps, CHUNK):
+            n = min(CHUNK, n_steps - c0)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            out = env.rollout(n, out=None, **kw)
+            b.record(stream)
+            evs.append((n, a, b))
+        torch.cuda.synchronize()
+        res += [(n, a.elapsed_time(b)) for n, a, b in evs]
+    return res
 
 
 def cpu_baseline(w, seconds_hint=True):
@@ -139,7 +194,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper", choices=["paper", "precision"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "precision", "envlarge"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=None, help="timed rollouts of the plain float32 path")
     ap.add_argument("--kernel", choices=["fused", "driven", "plain", "copy"], default=None,
@@ -171,6 +226,8 @@ def main():
     ens_bf16 = Ensemble(packed, K, S, H, D, dtype="bf16", max_batch=N, device=dev)
     bf_tot, bf_ker, bf_wall, _ = time_rollouts(env, T, args.steps, args.warmup, stream, ens=ens_bf16,
                                                sigma=w.sigma, noise_key=w.noise_key, path="fused", store=store)
+    launches = time_launches(env, T, max(3, args.steps // 5), stream, ens=ens_bf16, sigma=w.sigma,
+                             noise_key=w.noise_key, path="fused", store=store)
     ens_f32 = Ensemble(packed, K, S, H, D, dtype="f32", max_batch=N, device=dev)
     f32_reps = args.fp32_steps if args.fp32_steps is not None else max(5, args.steps // 3)
     f_tot, f_ker, f_wall, _ = time_rollouts(env, T, f32_reps, max(1, args.warmup // 2), stream, ens=ens_f32,
@@ -181,16 +238,34 @@ def main():
     acts = torch.from_numpy(make_actions(5, T, N, D)).to(dev)
     d_tot, d_ker, _, _ = time_rollouts(env, T, args.steps, args.warmup, stream, actions=acts,
                                        store=("obs", "rew", "qty"))
+    del acts
+    # The same kernel on a problem that fills the GPU.
+    wl = WORKLOADS["envlarge"]
+    NL, TL = wl.env.n_envs, wl.env.n_days
+    ml = make_market(wl.market_seed, D, TL)
+    env_l = VecEnv(wl.env, ml.close, ml.ind, device=dev)
+    acts_l = torch.rand((TL, NL, D), device=dev, dtype=torch.float32) * 2 - 1
+    l_tot, l_ker, _, out_l = time_rollouts(env_l, TL, max(3, args.steps // 5), 1, stream, actions=acts_l,
+                                           store=("obs", "rew", "qty"))
+    del out_l, acts_l, env_l
+    torch.cuda.empty_cache()
 
     env_steps = N * T
     bf_ms = float(np.median(bf_tot))
     f_ms = float(np.median(f_tot))
     flop = mlp_flops_per_env_step(S, H, D, K) * env_steps
     ker_s = float(np.mean(bf_ker)) / 1e3
-    achieved_tf = flop / ker_s / 1e12
+    flop_env_step = mlp_flops_per_env_step(S, H, D, K)
+    launch_steps = sum(n for n, _ in launches)
+    launch_ms = sum(ms for _, ms in launches)
+    achieved_tf = flop_env_step * N * launch_steps / (launch_ms / 1e3) / 1e12
+    mean_launch_ms = launch_ms / len(launches)
+    steps_per_launch = launch_steps / len(launches)
     env_b = env_bytes_per_env_step(D, S) * env_steps
     d_s = float(np.mean(d_ker)) / 1e3
     achieved_gbs = env_b / d_s / 1e9
+    l_s = float(np.mean(l_ker)) / 1e3
+    large_gbs = env_bytes_per_env_step(D, S) * NL * TL / l_s / 1e9
     rec = {
         "metric": METRIC,
         "value": env_steps / (bf_ms / 1e3),
@@ -213,13 +288,18 @@ def main():
                        "steps": f32_reps, "dtype": "f32"},
         "bf16_over_fp32": f_ms / bf_ms,
         "roofline": {"bound": "mfma", "achieved": achieved_tf, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / PEAK_BF16_TFLOPS, "traffic": None,
-                     "kernel": "fused_rollout_kernel", "kernel_ms": ker_s * 1e3,
-                     "flop_per_env_step": mlp_flops_per_env_step(S, H, D, K)},
+                     "frac": achieved_tf / PEAK_BF16_TFLOPS,
+                     "traffic": traffic_for("fused_streamed_kernel", N * steps_per_launch),
+                     "kernel": "fused_streamed_kernel", "launch_ms": mean_launch_ms,
+                     "steps_per_launch": steps_per_launch, "flop_per_env_step": flop_env_step},
         "env_roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": None, "kernel": "env_tile_kernel (driven)",
-                         "kernel_ms": d_s * 1e3, "bytes_per_env_step": env_bytes_per_env_step(D, S),
-                         "env_steps_per_s": env_steps / d_s},
+                         "frac": achieved_gbs / PEAK_HBM_GBS,
+                         "traffic": traffic_for("env_tile_kernel<1>@2048", N * T),
+                         "kernel": "env_tile_kernel<1> (driven)", "kernel_ms": d_s * 1e3,
+                         "bytes_per_env_step": env_bytes_per_env_step(D, S), "env_steps_per_s": env_steps / d_s,
+                         "large": {"workload": wl.name, "achieved": large_gbs, "frac": large_gbs / PEAK_HBM_GBS,
+                                   "kernel_ms": l_s * 1e3, "env_steps_per_s": NL * TL / l_s,
+                                   "traffic": traffic_for("env_tile_kernel<1>@65536", NL * TL)}},
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)

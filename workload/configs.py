@@ -75,4 +75,9 @@ PAPER_SCALE = Workload("paper-scale N=2048 D=30 T=252 H=256", EnvConfig(n_envs=2
 PRECISION = Workload("precision N=8192 D=30 T=252 H=256 bf16", EnvConfig(n_envs=8192, n_days=252),
                      ActorConfig(in_dim=_S, hidden=256, out_dim=30), sigma=0.1, dtype="bf16")
 
-WORKLOADS = {"tiny": TINY, "paper": PAPER_SCALE, "precision": PRECISION}
+# Environment-kernel throughput: enough environments to fill the GPU many times over, fewer days
+# (the driven trajectories of 65536 x 64 steps are 3.5 GB of states).
+ENV_LARGE = Workload("env-throughput N=65536 D=30 T=64", EnvConfig(n_envs=65536, n_days=64),
+                     ActorConfig(in_dim=_S, hidden=256, out_dim=30), sigma=0.1, dtype="f32")
+
+WORKLOADS = {"tiny": TINY, "paper": PAPER_SCALE, "precision": PRECISION, "envlarge": ENV_LARGE}
