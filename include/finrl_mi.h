@@ -193,6 +193,53 @@ fm_status fm_backtest_metrics(const double* d_rew, int32_t n_steps, int32_t n_en
 fm_status fm_sharpe_weights(const double* h_sharpe, int32_t n_actors, double min_sharpe, float* h_mix);
 
 /* ---------------------------------------------------------------------------------------------
+ * Uneven batch (Section 4.2: the vectorised environment is a set of independent sub-environments
+ * with their own market and horizon; here G groups of them, each with its own stock count D_g,
+ * environment count N_g, horizon and bfloat16 ensemble, run together).  One persistent kernel
+ * launch per chunk of 64 days steps every group: workgroups take (group, tile) work items in
+ * decreasing order of cost from a device counter until none is left.  The chunk launches can be
+ * captured once in a hipGraph and replayed.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct fm_batch fm_batch; /* opaque host handle */
+
+typedef struct fm_batch_group {
+  fm_env* env;               /* the group's environments (their stream is not used) */
+  const fm_ensemble* ens;    /* bfloat16 ensemble with in_dim = the env's state width,
+                                out_dim = its stock count, hidden <= 256 */
+  int32_t n_steps;           /* days to advance, env day + n_steps <= T */
+  float sigma;               /* exploration noise scale, finite, >= 0 */
+  uint64_t noise_key;
+  int64_t env_offset;        /* global index of the group's first environment (noise counter) */
+  float* d_obs_traj;         /* optional [n_steps][N][S] */
+  float* d_act_traj;         /* optional [n_steps][N][D] */
+  double* d_rew_traj;        /* optional [n_steps][N] */
+  int32_t* d_qty_traj;       /* optional [n_steps][N][D] */
+} fm_batch_group;
+
+/* Device workspace bytes for a batch of these groups (0 if the groups are invalid). */
+size_t fm_batch_workspace_bytes(const fm_batch_group* h_groups, int32_t n_groups);
+
+/* Validates the groups (1 <= n_groups <= 4096; every env and ensemble on the current device;
+ * shapes as above), lays out the per-chunk group descriptors and work lists in d_workspace
+ * (caller-owned, 256-byte aligned, >= fm_batch_workspace_bytes) and records each group's current
+ * day: fm_batch_run requires the environments to be at those days again.  Synchronous. */
+fm_status fm_batch_create(const fm_batch_group* h_groups, int32_t n_groups, void* d_workspace,
+                          size_t workspace_bytes, hipStream_t stream, fm_batch** out);
+
+/* Autotuner: times the first chunk under each candidate tile shape (16 or 32 environments per
+ * work item) and persistent grid size, restores every group's state after each trial, and keeps
+ * the fastest.  *h_rows and *h_blocks (may be NULL) get the choice.  Invalidates a captured
+ * graph.  Trajectory buffers are overwritten by the trials. */
+fm_status fm_batch_tune(fm_batch* batch, int32_t* h_rows, int32_t* h_blocks);
+
+/* Runs every group's n_steps on the batch's stream and advances each environment's day.
+ * use_graph != 0 captures the chunk launches into a hipGraph on first use and replays it.
+ * Returns FM_ERR_STATE if an environment is not at the day recorded by fm_batch_create. */
+fm_status fm_batch_run(fm_batch* batch, int32_t use_graph);
+
+void fm_batch_destroy(fm_batch* batch);
+
+/* ---------------------------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------------------------- */
 

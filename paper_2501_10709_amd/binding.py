@@ -22,7 +22,8 @@ EXPORTS = (
     "env_workspace_bytes", "env_create", "env_reset", "env_step", "env_rollout", "env_read_state",
     "env_write_state", "env_day", "env_set_tile", "env_destroy", "ensemble_workspace_bytes", "ensemble_create",
     "ensemble_act", "ensemble_destroy", "fm_last_error", "fm_noise", "fm_version", "fm_backtest_metrics",
-    "fm_sharpe_weights",
+    "fm_sharpe_weights", "fm_batch_workspace_bytes", "fm_batch_create", "fm_batch_tune", "fm_batch_run",
+    "fm_batch_destroy",
 )
 
 
@@ -49,6 +50,13 @@ class FmRolloutOpts(ctypes.Structure):
         ("d_obs_traj", ctypes.c_void_p), ("d_act_traj", ctypes.c_void_p),
         ("d_rew_traj", ctypes.c_void_p), ("d_qty_traj", ctypes.c_void_p),
     ]
+
+
+class FmBatchGroup(ctypes.Structure):
+    _fields_ = [("env", ctypes.c_void_p), ("ens", ctypes.c_void_p), ("n_steps", ctypes.c_int32),
+                ("sigma", ctypes.c_float), ("noise_key", ctypes.c_uint64), ("env_offset", ctypes.c_int64),
+                ("d_obs_traj", ctypes.c_void_p), ("d_act_traj", ctypes.c_void_p), ("d_rew_traj", ctypes.c_void_p),
+                ("d_qty_traj", ctypes.c_void_p)]
 
 
 _lib = None
@@ -89,6 +97,11 @@ def load(path: str = LIB_PATH):
         "fm_backtest_metrics": (I32, [P, I32, I32, ctypes.c_double, P, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, P, P]),
         "fm_sharpe_weights": (I32, [P, I32, ctypes.c_double, P]),
+        "fm_batch_workspace_bytes": (SZ, [ctypes.POINTER(FmBatchGroup), I32]),
+        "fm_batch_create": (I32, [ctypes.POINTER(FmBatchGroup), I32, P, SZ, P, ctypes.POINTER(P)]),
+        "fm_batch_tune": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "fm_batch_run": (I32, [P, I32]),
+        "fm_batch_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -273,3 +286,46 @@ def fm_last_error() -> str:
 
 def fm_version() -> str:
     return load().fm_version().decode()
+
+
+def make_batch_groups(groups):
+    """Array of FmBatchGroup from dicts with keys env (handle), ens (handle), n_steps, sigma,
+    noise_key, env_offset and optional obs/act/rew/qty trajectory tensors."""
+    import torch
+    arr = (FmBatchGroup * len(groups))()
+    for i, g in enumerate(groups):
+        arr[i] = FmBatchGroup(g["env"], g["ens"], int(g["n_steps"]), float(g.get("sigma", 0.0)),
+                              int(g.get("noise_key", 0)), int(g.get("env_offset", 0)),
+                              _ptr(g.get("obs"), torch.float32, name="obs_traj"),
+                              _ptr(g.get("act"), torch.float32, name="act_traj"),
+                              _ptr(g.get("rew"), torch.float64, name="rew_traj"),
+                              _ptr(g.get("qty"), torch.int32, name="qty_traj"))
+    return arr
+
+
+def fm_batch_workspace_bytes(groups) -> int:
+    arr = groups if isinstance(groups, ctypes.Array) else make_batch_groups(groups)
+    return int(load().fm_batch_workspace_bytes(arr, len(arr)))
+
+
+def fm_batch_create(groups, d_workspace, stream=None):
+    arr = groups if isinstance(groups, ctypes.Array) else make_batch_groups(groups)
+    h = ctypes.c_void_p()
+    _check(load().fm_batch_create(arr, len(arr), _ptr(d_workspace, name="workspace"),
+                                  d_workspace.numel() * d_workspace.element_size(), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def fm_batch_tune(batch):
+    rows, blocks = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load().fm_batch_tune(batch, ctypes.byref(rows), ctypes.byref(blocks)))
+    return rows.value, blocks.value
+
+
+def fm_batch_run(batch, use_graph=False):
+    _check(load().fm_batch_run(batch, 1 if use_graph else 0))
+
+
+def fm_batch_destroy(batch):
+    load().fm_batch_destroy(batch)
+

@@ -6,6 +6,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "../../include/finrl_mi.h"
 #include "fused.h"
@@ -184,6 +186,324 @@ std::string validate_ensemble(int K, int S, int H, int A, int dtype, int max_bat
 extern "C" {
 
 const char* fm_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------------------------------
+// Uneven batch
+// ------------------------------------------------------------------------------------------
+}  // extern "C"
+
+struct fm_batch {
+  int n_groups = 0, device = 0, n_chunks = 0, rows = 16, blocks = 0;
+  hipStream_t stream = nullptr;
+  std::vector<fm_batch_group> groups;
+  std::vector<int> start_day;
+  size_t desc_bytes = 0, lds = 0, items_cap = 0;
+  unsigned char* d_desc = nullptr;  // [n_chunks][n_groups] descriptors
+  int* d_items = nullptr;           // [n_chunks][items_cap] int2
+  int* d_counter = nullptr;
+  unsigned char* d_save = nullptr;  // state copies for the autotuner
+  std::vector<int> n_items;         // per chunk, for the current rows
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;  // private stream the chunk launches are captured on
+};
+
+namespace {
+
+constexpr int kBatchChunk = 64;
+
+struct BatchLayout {
+  size_t desc, items, counter, save, total, items_cap;
+  int n_chunks;
+};
+
+std::string validate_batch(const fm_batch_group* g, int n, int device) {
+  if (!g) return "groups is NULL";
+  if (n < 1 || n > 4096) return "n_groups must be in 1..4096";
+  for (int i = 0; i < n; ++i) {
+    const fm_batch_group& b = g[i];
+    const std::string at = " (group " + std::to_string(i) + ")";
+    if (!b.env || !b.ens) return "env and ensemble are required" + at;
+    if (b.ens->dtype != FM_BF16) return "the batch runs bfloat16 ensembles" + at;
+    if (b.ens->S != b.env->C.S || b.ens->A != b.env->C.D) return "ensemble in_dim/out_dim do not match" + at;
+    if (b.ens->H > 256) return "hidden must be <= 256" + at;
+    if (b.env->device != device || b.ens->device != device) return "all groups must be on the current device" + at;
+    if (b.n_steps < 0 || b.env->day + b.n_steps > b.env->C.T) return "n_steps out of range" + at;
+    if (!(b.sigma >= 0.0f) || !std::isfinite(b.sigma)) return "sigma must be finite and >= 0" + at;
+    if (fm::batched_lds_bytes(16, b.env->C, b.ens->E) > fm::batched_max_lds()) return "state too wide for the LDS budget" + at;
+  }
+  return "";
+}
+
+BatchLayout batch_layout(const fm_batch_group* g, int n) {
+  BatchLayout L{};
+  int max_steps = 0;
+  size_t items = 0, save = 0;
+  for (int i = 0; i < n; ++i) {
+    max_steps = std::max(max_steps, g[i].n_steps);
+    items += static_cast<size_t>((g[i].env->C.N + 15) / 16);
+    save += align_up(sizeof(double) * 3 * g[i].env->C.N) +
+            align_up(sizeof(int32_t) * static_cast<size_t>(g[i].env->C.D) * g[i].env->C.N);
+  }
+  L.n_chunks = std::max(1, (max_steps + kBatchChunk - 1) / kBatchChunk);
+  L.items_cap = items;
+  size_t off = 0;
+  L.desc = off;
+  off = align_up(off + fm::batched_group_desc_bytes() * n * L.n_chunks);
+  L.items = off;
+  off = align_up(off + sizeof(int) * 2 * items * L.n_chunks);
+  L.counter = off;
+  off = align_up(off + 256);
+  L.save = off;
+  off = align_up(off + save);
+  L.total = off;
+  return L;
+}
+
+// Work lists of every chunk for the given tile rows: (group, tile), most expensive first.
+fm_status batch_items(fm_batch* b, int rows) {
+  std::vector<int> host;
+  b->n_items.assign(b->n_chunks, 0);
+  for (int c = 0; c < b->n_chunks; ++c) {
+    struct It { double cost; int g, tile; };
+    std::vector<It> list;
+    for (int g = 0; g < b->n_groups; ++g) {
+      const fm_batch_group& G = b->groups[g];
+      const int n = std::min(kBatchChunk, G.n_steps - c * kBatchChunk);
+      if (n <= 0) continue;
+      const fm::EnsDev& E = G.ens->E;
+      const double per_step = static_cast<double>(E.K) *
+                              (static_cast<double>(E.S_pad) * E.H + static_cast<double>(E.H) * E.H +
+                               static_cast<double>(E.H) * E.A_pad) + 64.0 * G.env->C.D;
+      const int tiles = (G.env->C.N + rows - 1) / rows;
+      for (int t = 0; t < tiles; ++t) list.push_back({per_step * n, g, t});
+    }
+    std::stable_sort(list.begin(), list.end(), [](const It& x, const It& y) { return x.cost > y.cost; });
+    b->n_items[c] = static_cast<int>(list.size());
+    host.resize(2 * b->items_cap);
+    for (size_t i = 0; i < list.size(); ++i) {
+      host[2 * i] = list[i].g;
+      host[2 * i + 1] = list[i].tile;
+    }
+    hipError_t e = hipMemcpyAsync(b->d_items + 2 * b->items_cap * c, host.data(), sizeof(int) * 2 * list.size(),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return device_status(e, "fm_batch (work lists)");
+    e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return device_status(e, "fm_batch (work lists)");
+  }
+  b->rows = rows;
+  size_t lds = 0;
+  for (const fm_batch_group& G : b->groups) lds = std::max(lds, fm::batched_lds_bytes(rows, G.env->C, G.ens->E));
+  b->lds = lds;
+  return device_status(fm::prepare_batched(lds), "fm_batch (LDS limit)");
+}
+
+void batch_drop_graph(fm_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+hipError_t batch_enqueue(fm_batch* b, int n_chunks, hipStream_t stream) {
+  for (int c = 0; c < n_chunks; ++c) {
+    if (b->n_items[c] == 0) continue;
+    const hipError_t e = fm::launch_batched(b->rows, b->blocks, b->lds, b->d_desc + b->desc_bytes * b->n_groups * c,
+                                            b->d_items + 2 * b->items_cap * c, b->n_items[c], b->d_counter,
+                                            stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Copies every group's trading state to (save) or from (restore) the batch's save area.
+hipError_t batch_state_copy(fm_batch* b, bool save) {
+  unsigned char* p = b->d_save;
+  for (const fm_batch_group& G : b->groups) {
+    const size_t N = G.env->C.N, D = G.env->C.D;
+    const size_t nd = align_up(sizeof(double) * 3 * N), nh = sizeof(int32_t) * D * N;
+    const fm::EnvState& st = G.env->st;
+    void* src[4] = {st.cash, st.asset, st.cumrew, st.hold};
+    const size_t sz[4] = {sizeof(double) * N, sizeof(double) * N, sizeof(double) * N, nh};
+    size_t off[4] = {0, sizeof(double) * N, 2 * sizeof(double) * N, nd};
+    for (int k = 0; k < 4; ++k) {
+      const hipError_t e = save ? hipMemcpyAsync(p + off[k], src[k], sz[k], hipMemcpyDeviceToDevice, b->stream)
+                                : hipMemcpyAsync(src[k], p + off[k], sz[k], hipMemcpyDeviceToDevice, b->stream);
+      if (e != hipSuccess) return e;
+    }
+    p += nd + align_up(nh);
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fm_batch_workspace_bytes(const fm_batch_group* h_groups, int32_t n_groups) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  if (!validate_batch(h_groups, n_groups, dev).empty()) return 0;
+  return batch_layout(h_groups, n_groups).total;
+}
+
+fm_status fm_batch_create(const fm_batch_group* h_groups, int32_t n_groups, void* d_workspace,
+                          size_t workspace_bytes, hipStream_t stream, fm_batch** out) {
+  if (!out) return fail(FM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const std::string why = validate_batch(h_groups, n_groups, dev);
+  if (!why.empty()) return fail(FM_ERR_INVALID, why);
+  if (!d_workspace) return fail(FM_ERR_INVALID, "d_workspace is NULL");
+  if (!aligned(d_workspace)) return fail(FM_ERR_INVALID, "d_workspace must be 256-byte aligned");
+  const BatchLayout L = batch_layout(h_groups, n_groups);
+  if (workspace_bytes < L.total) return fail(FM_ERR_INVALID, "workspace too small");
+  fm_batch* b = new (std::nothrow) fm_batch();
+  if (!b) return fail(FM_ERR_DEVICE, "host allocation failed");
+  unsigned char* base = static_cast<unsigned char*>(d_workspace);
+  b->n_groups = n_groups;
+  b->device = dev;
+  b->stream = stream;
+  b->groups.assign(h_groups, h_groups + n_groups);
+  b->n_chunks = L.n_chunks;
+  b->items_cap = L.items_cap;
+  b->desc_bytes = fm::batched_group_desc_bytes();
+  b->d_desc = base + L.desc;
+  b->d_items = reinterpret_cast<int*>(base + L.items);
+  b->d_counter = reinterpret_cast<int*>(base + L.counter);
+  b->d_save = base + L.save;
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+  b->blocks = cus;
+  // Descriptors of every (chunk, group): the chunk's first day, its steps and trajectory rows.
+  std::vector<unsigned char> host(b->desc_bytes * n_groups * L.n_chunks);
+  for (int c = 0; c < L.n_chunks; ++c)
+    for (int g = 0; g < n_groups; ++g) {
+      const fm_batch_group& G = h_groups[g];
+      const fm::EnvConst& C = G.env->C;
+      const int n = std::max(0, std::min(kBatchChunk, G.n_steps - c * kBatchChunk));
+      const size_t r0 = static_cast<size_t>(c) * kBatchChunk;
+      const size_t N = C.N, D = C.D, S = C.S;
+      fm::batched_group_desc(C, G.env->st, G.ens->E, G.env->day + c * kBatchChunk, n, G.sigma, G.noise_key,
+                             G.env_offset, G.d_obs_traj && n ? G.d_obs_traj + r0 * N * S : nullptr,
+                             G.d_act_traj && n ? G.d_act_traj + r0 * N * D : nullptr,
+                             G.d_rew_traj && n ? G.d_rew_traj + r0 * N : nullptr,
+                             G.d_qty_traj && n ? G.d_qty_traj + r0 * N * D : nullptr,
+                             host.data() + b->desc_bytes * (static_cast<size_t>(c) * n_groups + g));
+    }
+  for (int g = 0; g < n_groups; ++g) b->start_day.push_back(h_groups[g].env->day);
+  DeviceGuard guard(dev);
+  hipError_t e = hipMemcpyAsync(b->d_desc, host.data(), host.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    delete b;
+    return device_status(e, "fm_batch_create");
+  }
+  const fm_status s = batch_items(b, 16);
+  if (s != FM_OK) {
+    delete b;
+    return s;
+  }
+  *out = b;
+  return FM_OK;
+}
+
+fm_status fm_batch_tune(fm_batch* b, int32_t* h_rows, int32_t* h_blocks) {
+  if (!b) return fail(FM_ERR_INVALID, "batch is NULL");
+  DeviceGuard guard(b->device);
+  batch_drop_graph(b);
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) cus = 256;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(FM_ERR_DEVICE, "fm_batch_tune: event creation failed");
+  int best_rows = b->rows, best_blocks = b->blocks;
+  float best_ms = -1.0f;
+  fm_status status = FM_OK;
+  for (int rows : {16, 32}) {
+    bool fits = true;
+    for (const fm_batch_group& G : b->groups)
+      fits = fits && fm::batched_lds_bytes(rows, G.env->C, G.ens->E) <= fm::batched_max_lds();
+    if (!fits) continue;
+    status = batch_items(b, rows);
+    if (status != FM_OK) break;
+    for (int blocks : {cus / 2, cus, 2 * cus}) {
+      b->blocks = blocks;
+      hipError_t e = batch_state_copy(b, true);
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first run warms up
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        if (e == hipSuccess) e = batch_enqueue(b, 1, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = batch_state_copy(b, false);
+      }
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+      if (e != hipSuccess) {
+        status = device_status(e, "fm_batch_tune");
+        break;
+      }
+      if (best_ms < 0.0f || ms < best_ms) {
+        best_ms = ms;
+        best_rows = rows;
+        best_blocks = blocks;
+      }
+    }
+    if (status != FM_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status != FM_OK) return status;
+  b->blocks = best_blocks;
+  status = batch_items(b, best_rows);
+  if (status != FM_OK) return status;
+  if (h_rows) *h_rows = b->rows;
+  if (h_blocks) *h_blocks = b->blocks;
+  return FM_OK;
+}
+
+fm_status fm_batch_run(fm_batch* b, int32_t use_graph) {
+  if (!b) return fail(FM_ERR_INVALID, "batch is NULL");
+  for (int g = 0; g < b->n_groups; ++g)
+    if (b->groups[g].env->day != b->start_day[g])
+      return fail(FM_ERR_STATE, "an environment is not at the day the batch was created for (group " +
+                                    std::to_string(g) + ")");
+  DeviceGuard guard(b->device);
+  hipError_t e = hipSuccess;
+  if (use_graph) {
+    if (!b->exec) {
+      // Captured on a private stream (the caller's may be the legacy default stream, which cannot
+      // capture) and launched on the caller's.
+      if (!b->capture) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        const hipError_t le = batch_enqueue(b, b->n_chunks, b->capture);
+        e = hipStreamEndCapture(b->capture, &b->graph);
+        if (le != hipSuccess) e = le;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        batch_drop_graph(b);
+        return device_status(e, "fm_batch_run (graph capture)");
+      }
+    }
+    e = hipGraphLaunch(b->exec, b->stream);
+  } else {
+    e = batch_enqueue(b, b->n_chunks, b->stream);
+  }
+  if (e != hipSuccess) return device_status(e, "fm_batch_run");
+  for (fm_batch_group& G : b->groups) G.env->day += G.n_steps;
+  return FM_OK;
+}
+
+void fm_batch_destroy(fm_batch* b) {
+  if (!b) return;
+  batch_drop_graph(b);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  delete b;
+}
 
 const char* fm_version(void) { return "finrl_mi 0.1 gfx950"; }
 

@@ -35,4 +35,20 @@ hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const Ens
                                 float* eps_chunk, float* mt_chunk, hipStream_t stream, std::string* why,
                                 FusedTuning tune = FusedTuning());
 
+// Batched persistent rollout of uneven groups (generic schedule, hidden size 256, K <= 8).
+// rows: environments per work item (16 or 32).  A group descriptor is an opaque block of
+// batched_group_desc_bytes() bytes, filled on the host and copied to the device.
+size_t batched_lds_bytes(int rows, const EnvConst& C, const EnsDev& E);
+size_t batched_group_desc_bytes();
+void batched_group_desc(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0, int n_steps, float sigma,
+                        uint64_t key, int64_t env_offset, float* obs_traj, float* act_traj, double* rew_traj,
+                        int* qty_traj, void* out);
+// The batched kernels' dynamic LDS limit: raised to lds (<= batched_max_lds()) outside any
+// stream capture.
+size_t batched_max_lds();
+hipError_t prepare_batched(size_t lds);
+// items: int2 (group, tile) pairs; counter: one int of device scratch.
+hipError_t launch_batched(int rows, int blocks, size_t lds, const void* groups, const int* items, int n_items,
+                          int* counter, hipStream_t stream);
+
 }  // namespace fm

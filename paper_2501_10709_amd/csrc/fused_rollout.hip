@@ -15,6 +15,7 @@
 //     of all actors), keeping DEPTH k-steps of fragments in flight in registers.  The sequence
 //     wraps around, so the first fragments of the next step load while the trading chain runs.
 //   * generic (any supported shape): four wavefronts, runtime loops, one fragment at a time.
+#include <cstring>
 #include <utility>
 
 #include "device_common.h"
@@ -790,14 +791,15 @@ __global__ __launch_bounds__(kStreamThreads) void fused_streamed_kernel(EnvConst
   }
 }
 
+// One tile (16*ROWT environments starting at tile*16*ROWT) through the steps of F, generic
+// schedule: the body of the generic kernel and of the batched persistent kernel.
 template <int ROWT, int TMAX>
-__global__ __launch_bounds__(256) void fused_generic_kernel(EnvConst C, EnvState st, EnsDev E,
-                                                            FusedArgs F) {
+__device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& st, const EnsDev& E,
+                                             const FusedArgs& F, int tile, unsigned char* smem) {
   constexpr int NT = 256, MR = 16 * ROWT;
-  extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int D = C.D, N = C.N, DS = D + 1;
-  const int n0 = blockIdx.x * MR;
+  const int n0 = tile * MR;
   const int M = min(MR, N - n0);
   const int st0 = E.S_pad + 8, sth = E.H + 8;
 
@@ -876,6 +878,48 @@ __global__ __launch_bounds__(256) void fused_generic_kernel(EnvConst C, EnvState
   }
 
   P.store_state(owner, st, cash, asset, cumrew);
+}
+
+template <int ROWT, int TMAX>
+__global__ __launch_bounds__(256) void fused_generic_kernel(EnvConst C, EnvState st, EnsDev E,
+                                                            FusedArgs F) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  generic_tile<ROWT, TMAX>(C, st, E, F, blockIdx.x, smem);
+}
+
+// Batched persistent kernel (uneven groups): every workgroup takes work items -- (group, tile)
+// pairs, ordered by decreasing cost -- from a counter until none is left, and runs each item's
+// steps with the generic schedule.  The item counter is reset by zero_counter_kernel before each
+// launch (a kernel, not a memset, so that the pair can be captured in a graph).
+constexpr size_t kBatchedMaxLds = 160 * 1024 - 256;  // the kernel's own item slot takes a little
+
+struct GroupDesc {
+  EnvConst C;
+  EnvState st;
+  EnsDev E;
+  FusedArgs F;
+};
+
+template <int ROWT, int TMAX>
+__global__ __launch_bounds__(256) void fused_batched_kernel(const GroupDesc* __restrict__ groups,
+                                                            const int2* __restrict__ items, int n_items,
+                                                            int* __restrict__ counter) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= n_items) break;
+    const int2 gt = items[item];
+    const GroupDesc G = groups[gt.x];
+    if (G.F.n_steps > 0) generic_tile<ROWT, TMAX>(G.C, G.st, G.E, G.F, gt.y, smem);
+  }
+}
+
+__global__ void zero_counter_kernel(int* counter) {
+  if (threadIdx.x == 0) counter[0] = 0;
 }
 
 template <class Kern>
@@ -971,6 +1015,46 @@ bool fused_streamed_shape(const EnvConst& C, const EnsDev& E) {
   if (streamed_lds_bytes<2, 2>(C) > 160 * 1024) return false;
   return E.off_w1 == 0 && E.off_w2 == SP::kW2 && E.off_w3 == SP::kW3 && E.off_b1 == SP::kB1 &&
          E.off_b2 == SP::kB2 && E.off_b3 == SP::kB3 && E.actor_stride == SP::kActor;
+}
+
+size_t batched_lds_bytes(int rows, const EnvConst& C, const EnsDev& E) {
+  return FusedLds::bytes(rows, E.S_pad + 8, E.H + 8, C.D, C.I);
+}
+
+size_t batched_max_lds() { return kBatchedMaxLds; }
+
+size_t batched_group_desc_bytes() { return sizeof(GroupDesc); }
+
+void batched_group_desc(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0, int n_steps, float sigma,
+                        uint64_t key, int64_t env_offset, float* obs_traj, float* act_traj, double* rew_traj,
+                        int* qty_traj, void* out) {
+  GroupDesc G{C, st, E, FusedArgs{t0, n_steps, sigma, key, env_offset, obs_traj, act_traj, rew_traj, qty_traj,
+                                  nullptr, nullptr}};
+  std::memcpy(out, &G, sizeof(GroupDesc));
+}
+
+hipError_t prepare_batched(size_t lds) {
+  for (const void* k : {reinterpret_cast<const void*>(fused_batched_kernel<1, 4>),
+                        reinterpret_cast<const void*>(fused_batched_kernel<2, 4>)}) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_batched(int rows, int blocks, size_t lds, const void* groups, const int* items, int n_items,
+                          int* counter, hipStream_t stream) {
+  if (lds > kBatchedMaxLds) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, stream, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const GroupDesc* g = static_cast<const GroupDesc*>(groups);
+  const int2* it = reinterpret_cast<const int2*>(items);
+  if (rows == 32)
+    hipLaunchKernelGGL((fused_batched_kernel<2, 4>), dim3(blocks), dim3(256), lds, stream, g, it, n_items, counter);
+  else
+    hipLaunchKernelGGL((fused_batched_kernel<1, 4>), dim3(blocks), dim3(256), lds, stream, g, it, n_items, counter);
+  return hipGetLastError();
 }
 
 hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0, int n_steps,

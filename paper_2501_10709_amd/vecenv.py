@@ -150,3 +150,52 @@ class VecEnv:
             self.close_env()
         except Exception:
             pass
+
+
+class Batch:
+    """Uneven groups of environments stepped together by the batched persistent kernel.
+
+    groups: list of dicts with env (VecEnv), ens (bfloat16 Ensemble), n_steps, and optional
+    sigma, noise_key, env_offset, store (names among obs, act, rew, qty; default ("rew",)).
+    The trajectories are allocated here: self.out[g][name] is [n_steps][N][...].
+    """
+
+    def __init__(self, groups, stream=None):
+        dev = groups[0]["env"].device
+        self.groups = groups
+        self.out = []
+        spec = []
+        for g in groups:
+            env, T = g["env"], int(g["n_steps"])
+            shapes = {"obs": ((T, env.N, env.S), torch.float32), "act": ((T, env.N, env.D), torch.float32),
+                      "rew": ((T, env.N), torch.float64), "qty": ((T, env.N, env.D), torch.int32)}
+            res = {k: torch.empty(shapes[k][0], dtype=shapes[k][1], device=dev) for k in g.get("store", ("rew",))}
+            self.out.append(res)
+            spec.append(dict(env=env.handle, ens=g["ens"].handle, n_steps=T, sigma=g.get("sigma", 0.0),
+                             noise_key=g.get("noise_key", 0), env_offset=g.get("env_offset", 0), **res))
+        self._arr = B.make_batch_groups(spec)
+        nbytes = B.fm_batch_workspace_bytes(self._arr)
+        if nbytes == 0:
+            raise ValueError("invalid batch groups")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.handle = B.fm_batch_create(self._arr, self.workspace, stream)
+
+    def tune(self):
+        """Autotune the tile rows and persistent grid; returns (rows, blocks)."""
+        return B.fm_batch_tune(self.handle)
+
+    def run(self, use_graph=False):
+        B.fm_batch_run(self.handle, use_graph)
+        return self.out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            B.fm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -108,3 +108,14 @@ def test_sharpe_weights_match_oracle():
 def test_env_set_tile_validation(lib):
     assert lib.env_set_tile(None, 8, None) == B.FM_ERR_INVALID
     assert "NULL" in B.fm_last_error()
+
+
+def test_batch_argument_validation(lib):
+    assert lib.fm_batch_workspace_bytes(None, 0) == 0
+    h = ctypes.c_void_p()
+    assert lib.fm_batch_create(None, 1, ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(h)) == B.FM_ERR_INVALID
+    assert "NULL" in B.fm_last_error()
+    groups = (B.FmBatchGroup * 1)()
+    assert lib.fm_batch_workspace_bytes(groups, 1) == 0  # NULL env / ensemble
+    assert lib.fm_batch_run(None, 0) == B.FM_ERR_INVALID
+    assert lib.fm_batch_tune(None, None, None) == B.FM_ERR_INVALID

@@ -63,3 +63,18 @@ def test_actions_cover_special_values():
     assert np.all(np.abs(a) <= 1)
     assert (a == 0).any() and (a == 1).any() and (a == -1).any()
     assert ((np.abs(a) < 0.01) & (a != 0)).any()
+
+
+def test_uneven_groups_follow_their_recipe():
+    import math
+    from workload.uneven import uneven_groups
+    gs = uneven_groups(seed=4, n_groups=64)
+    assert len(gs) == 64
+    assert {g.env.n_stocks for g in gs} <= {5, 10, 30, 50, 100}
+    assert all(32 <= g.env.n_envs <= 4096 and 20 <= g.env.n_days <= 1000 for g in gs)
+    assert all(0.01 <= g.vol <= 0.04 for g in gs)
+    assert all(g.actors.in_dim == 7 * g.env.n_stocks + 1 and g.actors.out_dim == g.env.n_stocks for g in gs)
+    # log-uniform env counts: the median of log N sits near the middle of [log 32, log 4096]
+    med = float(np.median([math.log(g.env.n_envs) for g in gs]))
+    assert abs(med - 0.5 * (math.log(32) + math.log(4096))) < 0.9
+    assert uneven_groups(seed=4, n_groups=64) == gs  # seeded
