@@ -54,12 +54,17 @@ def env_bytes_per_env_step(D, S):
 CHUNK = 64  # steps per fused-kernel launch (the library's chunk)
 
 
+# Sources the stock-environment and fused-rollout kernels (and their launch choices) are built from.
+PROFILED_SOURCES = ("api.hip", "device_common.h", "ensemble_kernels.hip", "env_kernels.hip", "fused.h",
+                    "fused_rollout.hip", "launch.h", "mlp_device.h")
+
+
 def source_hash():
-    """Hash of the HIP sources: counter readings are only valid for the code they were taken on."""
+    """Hash of the profiled HIP sources: counter readings are only valid for the code they were taken on."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2501_10709_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in PROFILED_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
@@ -208,6 +213,9 @@ def profile_kernel(args):
         torch.cuda.synchronize()
         print(json.dumps({"kernel": "copy", "bytes_read": nbytes, "bytes_written": nbytes}), flush=True)
         return
+    if args.kernel == "batched":
+        print(json.dumps(bench_batched(dev, reps=max(1, args.steps))), flush=True)
+        return
     w = WORKLOADS[args.workload]
     cfg, acfg = w.env, w.actors
     N, D, T, S, H, K = cfg.n_envs, cfg.n_stocks, cfg.n_days, cfg.state_dim, acfg.hidden, acfg.n_actors
@@ -236,7 +244,7 @@ def main():
     ap.add_argument("--workload", default="paper", choices=["paper", "precision", "envlarge"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=None, help="timed rollouts of the plain float32 path")
-    ap.add_argument("--kernel", choices=["fused", "driven", "plain", "copy"], default=None,
+    ap.add_argument("--kernel", choices=["fused", "driven", "plain", "copy", "batched"], default=None,
                     help="profiling mode: one warm-up and --steps launches of one kernel, nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
