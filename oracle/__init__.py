@@ -14,6 +14,12 @@ Plain, slow, float64 numpy code written from the paper:
                   Section 5.2.1 (weighted average of the agents' actions).
   * rollout.py -- T-step trajectories (Section 4.3, the T x N x D sample
                   tensors and R(tau) = sum_t gamma^t r_t).
+  * metrics.py -- backtest metrics (Section 6.1), softmax-of-Sharpe weights and
+                  the majority vote (Section 5.2).
+  * crypto.py  -- the single-asset crypto task: discrete target positions with a
+                  proportional fee, the agents' Q-networks, the averaged-softmax
+                  and majority-vote ensemble rules, exploration draws and the
+                  running backtest statistics (Sections 3.1, 5.2.2, 6.1).
 
 Each function is vectorised over environments only; loops over stocks run in
 ascending order so every environment's floating-point operation order is the
