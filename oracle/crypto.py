@@ -144,11 +144,13 @@ def env_ticks(start_tick: int, stride: int, n_envs: int, t: int) -> np.ndarray:
 
 
 def rollout(market, actors, n_envs: int, horizon: int, start_tick: int, stride: int, key: int, eps: float,
-            fee: float = 2e-4, cash0: float = 1e5, mode: int = AVG_SOFTMAX, mix=None, actions=None):
+            fee: float = 2e-4, cash0: float = 1e5, mode: int = AVG_SOFTMAX, mix=None, actions=None,
+            obs_out=None):
     """A request's trajectories.  Closed loop unless actions [horizon][n] is given, in which case
     the environment is driven by those actions and the policy is still evaluated on the states the
     environment reaches.  Returns (final state dict, probs [T][n][3] (average mode), chosen
-    actions [T][n], per-step decided-by-policy actions [T][n], explore mask [T][n], rewards [T][n])."""
+    actions [T][n], per-step decided-by-policy actions [T][n], explore mask [T][n], rewards [T][n]).
+    obs_out, if given, is a list that receives each step's state rows."""
     st = CryptoState(n_envs, cash0)
     T = horizon
     probs = np.zeros((T, n_envs, 3))
@@ -160,6 +162,8 @@ def rollout(market, actors, n_envs: int, horizon: int, start_tick: int, stride: 
     for t in range(T):
         ticks = env_ticks(start_tick, stride, n_envs, t)
         x = state_rows(st.cash, st.pos, market.mid[ticks], market.feat[ticks])
+        if obs_out is not None:
+            obs_out.append(x)
         if mode == AVG_SOFTMAX:
             probs[t] = ensemble_probs(actors, x, mix)
             greedy[t] = first_argmax(probs[t])

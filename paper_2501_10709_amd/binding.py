@@ -23,8 +23,10 @@ EXPORTS = (
     "env_write_state", "env_day", "env_set_tile", "env_destroy", "ensemble_workspace_bytes", "ensemble_create",
     "ensemble_act", "ensemble_destroy", "fm_last_error", "fm_noise", "fm_version", "fm_backtest_metrics",
     "fm_sharpe_weights", "fm_batch_workspace_bytes", "fm_batch_create", "fm_batch_tune", "fm_batch_run",
-    "fm_batch_destroy",
+    "fm_batch_destroy", "fm_serve_request_bytes", "fm_serve_workspace_bytes", "fm_serve_create", "fm_serve_submit",
+    "fm_serve_step", "fm_serve_poll", "fm_serve_destroy",
 )
+FM_RULE_AVG_SOFTMAX, FM_RULE_MAJORITY_VOTE = 0, 1
 
 
 class FmError(RuntimeError):
@@ -50,6 +52,29 @@ class FmRolloutOpts(ctypes.Structure):
         ("d_obs_traj", ctypes.c_void_p), ("d_act_traj", ctypes.c_void_p),
         ("d_rew_traj", ctypes.c_void_p), ("d_qty_traj", ctypes.c_void_p),
     ]
+
+
+class FmCryptoResult(ctypes.Structure):
+    _fields_ = [("cash", ctypes.c_double), ("value", ctypes.c_double), ("sum_r", ctypes.c_double),
+                ("sum_r2", ctypes.c_double), ("peak", ctypes.c_double), ("max_drawdown", ctypes.c_double),
+                ("position", ctypes.c_int32), ("trades", ctypes.c_int32), ("ticks", ctypes.c_int64)]
+
+
+class FmServeConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("d_mid", ctypes.c_void_p), ("d_feat", ctypes.c_void_p),
+                ("n_ticks", ctypes.c_int64), ("n_agents", ctypes.c_int32), ("h_weights", ctypes.c_void_p),
+                ("h_mix", ctypes.c_void_p), ("rule", ctypes.c_int32), ("eps", ctypes.c_float),
+                ("fee", ctypes.c_double), ("cash0", ctypes.c_double), ("tile_rows", ctypes.c_int32),
+                ("chunk_ticks", ctypes.c_int32), ("max_requests", ctypes.c_int32),
+                ("max_active_envs", ctypes.c_int64), ("grid", ctypes.c_int32), ("d_pool", ctypes.c_void_p),
+                ("pool_bytes", ctypes.c_size_t), ("d_workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class FmServeRequest(ctypes.Structure):
+    _fields_ = [("n_envs", ctypes.c_int32), ("stride", ctypes.c_int32), ("horizon", ctypes.c_int64),
+                ("start_tick", ctypes.c_int64), ("key", ctypes.c_uint64), ("d_result", ctypes.c_void_p),
+                ("d_act", ctypes.c_void_p), ("d_prob", ctypes.c_void_p)]
 
 
 class FmBatchGroup(ctypes.Structure):
@@ -102,6 +127,13 @@ def load(path: str = LIB_PATH):
         "fm_batch_tune": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "fm_batch_run": (I32, [P, I32]),
         "fm_batch_destroy": (None, [P]),
+        "fm_serve_request_bytes": (SZ, [I32]),
+        "fm_serve_workspace_bytes": (SZ, [ctypes.POINTER(FmServeConfig)]),
+        "fm_serve_create": (I32, [ctypes.POINTER(FmServeConfig), P, ctypes.POINTER(P)]),
+        "fm_serve_submit": (I32, [P, ctypes.POINTER(FmServeRequest), ctypes.POINTER(I64)]),
+        "fm_serve_step": (I32, [P, P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "fm_serve_poll": (I32, [P, I32, ctypes.POINTER(I64), I32, ctypes.POINTER(I32)]),
+        "fm_serve_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -329,3 +361,45 @@ def fm_batch_run(batch, use_graph=False):
 def fm_batch_destroy(batch):
     load().fm_batch_destroy(batch)
 
+
+
+# ------------------------------------------------------------------------------------------------
+# Crypto serving (include/crypto_serve.h)
+# ------------------------------------------------------------------------------------------------
+
+def fm_serve_request_bytes(n_envs: int) -> int:
+    return int(load().fm_serve_request_bytes(int(n_envs)))
+
+
+def fm_serve_workspace_bytes(cfg: FmServeConfig) -> int:
+    return int(load().fm_serve_workspace_bytes(ctypes.byref(cfg)))
+
+
+def fm_serve_create(cfg: FmServeConfig, stream=None):
+    out = ctypes.c_void_p()
+    _check(load().fm_serve_create(ctypes.byref(cfg), _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def fm_serve_submit(server, req: FmServeRequest) -> int:
+    rid = ctypes.c_int64()
+    _check(load().fm_serve_submit(server, ctypes.byref(req), ctypes.byref(rid)))
+    return rid.value
+
+
+def fm_serve_step(server, stream=None):
+    """(active requests, queued requests) after the step."""
+    a, q = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().fm_serve_step(server, _stream(stream), ctypes.byref(a), ctypes.byref(q)))
+    return a.value, q.value
+
+
+def fm_serve_poll(server, wait=False, cap=4096):
+    ids = (ctypes.c_int64 * cap)()
+    n = ctypes.c_int32()
+    _check(load().fm_serve_poll(server, 1 if wait else 0, ids, cap, ctypes.byref(n)))
+    return [ids[i] for i in range(n.value)]
+
+
+def fm_serve_destroy(server):
+    load().fm_serve_destroy(server)

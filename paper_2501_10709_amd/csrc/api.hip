@@ -12,6 +12,7 @@
 #include "../../include/finrl_mi.h"
 #include "fused.h"
 #include "launch.h"
+#include "status.h"
 
 namespace {
 
@@ -90,18 +91,14 @@ std::string validate_config(const fm_env_config* c) {
   return "";
 }
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-    else prev = -1;
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
+using fm::DeviceGuard;
 
 }  // namespace
+
+namespace fm {
+fm_status set_error(fm_status s, const std::string& msg) { return fail(s, msg); }
+fm_status device_error(hipError_t e, const char* what) { return device_status(e, what); }
+}  // namespace fm
 
 struct fm_env {
   fm_env_config cfg;

@@ -12,13 +12,17 @@ from paper_2501_10709_amd import binding as B
 from workload import PAPER_SCALE, TINY
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "finrl_mi.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def _declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    names = []
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text,
+                            flags=re.M)
     return sorted(set(names))
 
 
@@ -119,3 +123,25 @@ def test_batch_argument_validation(lib):
     assert lib.fm_batch_workspace_bytes(groups, 1) == 0  # NULL env / ensemble
     assert lib.fm_batch_run(None, 0) == B.FM_ERR_INVALID
     assert lib.fm_batch_tune(None, None, None) == B.FM_ERR_INVALID
+
+
+def test_serve_config_validation(lib):
+    cfg = B.FmServeConfig()
+    assert B.fm_serve_workspace_bytes(cfg) == 0          # NULL tick table
+    w = np.zeros(5 * (16 * 128 + 128 + 128 * 128 + 128 + 128 * 3 + 3), np.float32)
+    cfg.d_mid, cfg.d_feat, cfg.n_ticks = 256, 256, 1000
+    cfg.n_agents, cfg.h_weights, cfg.rule, cfg.eps, cfg.fee, cfg.cash0 = 5, w.ctypes.data, 0, 0.0, 2e-4, 1e5
+    cfg.tile_rows, cfg.chunk_ticks, cfg.max_requests, cfg.max_active_envs = 64, 256, 16, 4096
+    cfg.d_pool, cfg.pool_bytes = 256, 1 << 20
+    n = B.fm_serve_workspace_bytes(cfg)
+    assert n > 5 * 32 * 1024
+    for field, bad in [("tile_rows", 32), ("n_agents", 4), ("eps", 1.5), ("chunk_ticks", 0), ("rule", 7)]:
+        old = getattr(cfg, field)
+        setattr(cfg, field, bad)
+        assert B.fm_serve_workspace_bytes(cfg) == 0, field
+        out = ctypes.c_void_p()
+        assert lib.fm_serve_create(ctypes.byref(cfg), None, ctypes.byref(out)) == B.FM_ERR_INVALID
+        assert not out.value and B.fm_last_error()
+        setattr(cfg, field, old)
+    assert B.fm_serve_request_bytes(0) == 0 and B.fm_serve_request_bytes(1) == 256
+    assert B.fm_serve_request_bytes(100) == 6400

@@ -73,6 +73,16 @@ def crypto_actors(n_actors: int = 5, hidden: int = 128, seed_base: int = 7000, b
                        bias_std=bias_std)
 
 
+def make_crypto_agents(cfg: ActorConfig, q_gain: float = 4.0):
+    """Seeded agents (Xavier initialisation) with the output layer scaled by q_gain, so that the
+    three action values differ by O(1) and the ensemble's decisions are not all near-ties."""
+    from .actors import make_actor_weights
+    agents = make_actor_weights(cfg)
+    for a in agents:
+        a["W3"] = (a["W3"] * np.float32(q_gain)).astype(np.float32)
+    return agents
+
+
 @dataclass(frozen=True)
 class CryptoRequest:
     arrival_s: float     # arrival time from the start of the run
