@@ -1,19 +1,20 @@
 // The single-asset crypto task served with continuous batching (include/crypto_serve.h):
 // the per-chunk policy + environment kernel and the request scheduler.
 //
-// Kernel.  A workgroup of four wavefronts runs a work item = ROWS environments of one request
-// for up to chunk_ticks ticks.  The agents' weights stay on chip for the whole launch: wavefront
-// w owns hidden units 32w..32w+31 of every agent, with its slice of W2 in registers and W1, W3
-// and the biases in LDS.  All three layers run transposed on MFMA (outputs x environments), so
+// Kernel.  A workgroup of five wavefronts runs a work item = ROWS environments of one request
+// for up to chunk_ticks ticks.  The agents' weights stay on chip for the whole launch: MLP
+// wavefront w (0..3) owns hidden units 32w..32w+31 of every agent, with its slice of W2 in
+// registers and W1, W3 and the biases in LDS; wavefront 4 holds the environments.  All three layers run transposed on MFMA (outputs x environments), so
 // a wavefront's layer-1 and layer-2 accumulators are directly the B operands of the next layer
 // once its k-slots are read in the order the weights were packed:
 //   k-slot 8g + j of wavefront w  <->  hidden unit 32w + 16 (j / 4) + 4g + (j % 4).
 // Per tick: layer 1 (16 -> 128, v_mfma_f32_16x16x16_bf16) and an LDS exchange of the hidden
 // units; layer 2 (v_mfma_f32_16x16x32_bf16, W2 from registers) and the wavefront's share of
-// layer 3 (its 32 units) into LDS partial sums; then one lane per environment adds the four
-// partial sums in a fixed order, applies the ensemble rule, draws the exploration, trades in
-// float64, updates the running statistics and writes the next state row.  Three workgroup
-// barriers per tick.  The environment's state stays in that lane's registers for the item.
+// layer 3 (its 32 units) into LDS partial sums; then one lane of the environment wavefront per
+// environment adds the four partial sums in a fixed order, applies the ensemble rule and the
+// exploration draw (computed while the MLP ran), trades in float64, updates the running
+// statistics and writes the next state row.  Three workgroup barriers per tick.  The
+// environment's state stays in that lane's registers for the item.
 //
 // Scheduler.  Host-side: a FIFO queue, a first-fit allocator over the caller's device pool, the
 // active set, and per-chunk lists of (request, tile) items copied from pinned staging.
@@ -38,8 +39,8 @@ namespace cx {
 constexpr int kF = 16;    // agent input width
 constexpr int kH = 128;   // hidden units
 constexpr int kA = 3;     // actions
-constexpr int kNW = 4;    // wavefronts per workgroup
-constexpr int kNT = 64 * kNW;
+constexpr int kNW = 4;    // MLP wavefronts per workgroup
+constexpr int kNT = 64 * (kNW + 1);   // plus the environment wavefront
 
 typedef __attribute__((ext_vector_type(4))) short s16x4;
 
@@ -94,19 +95,23 @@ struct Lds {
   static constexpr size_t total = part + size_t(kNW) * K * R * 16 * 16;
 };
 
-__device__ __forceinline__ float relu(float v) { return v > 0.0f ? v : 0.0f; }
+typedef __attribute__((ext_vector_type(8))) short s16x8;
 
+// relu(x) rounded to bfloat16 for eight accumulators.  Rounding keeps the sign, so the ReLU is
+// applied after it as a signed 16-bit max with zero on the bfloat16 bit patterns (negative
+// values, -0 included, have the sign bit set).
 __device__ __forceinline__ bf16x8 pack_relu(floatx4 a, floatx4 b) {
   bf16x8 r;
-  r[0] = static_cast<__bf16>(relu(a[0]));
-  r[1] = static_cast<__bf16>(relu(a[1]));
-  r[2] = static_cast<__bf16>(relu(a[2]));
-  r[3] = static_cast<__bf16>(relu(a[3]));
-  r[4] = static_cast<__bf16>(relu(b[0]));
-  r[5] = static_cast<__bf16>(relu(b[1]));
-  r[6] = static_cast<__bf16>(relu(b[2]));
-  r[7] = static_cast<__bf16>(relu(b[3]));
-  return r;
+  r[0] = static_cast<__bf16>(a[0]);
+  r[1] = static_cast<__bf16>(a[1]);
+  r[2] = static_cast<__bf16>(a[2]);
+  r[3] = static_cast<__bf16>(a[3]);
+  r[4] = static_cast<__bf16>(b[0]);
+  r[5] = static_cast<__bf16>(b[1]);
+  r[6] = static_cast<__bf16>(b[2]);
+  r[7] = static_cast<__bf16>(b[3]);
+  const s16x8 m = __builtin_elementwise_max(__builtin_bit_cast(s16x8, r), s16x8{0, 0, 0, 0, 0, 0, 0, 0});
+  return __builtin_bit_cast(bf16x8, m);
 }
 
 __device__ __forceinline__ floatx4 mfma16(s16x4 a, s16x4 b, floatx4 c) {
@@ -145,25 +150,34 @@ __device__ __forceinline__ void load_feat(const float* feat, int64_t tick, float
 #pragma clang fp contract(off)
 template <int R, int K>
 __global__ __launch_bounds__(kNT, 1) void crypto_chunk_kernel(ChunkArgs a) {
-  using L = Lds<R, K>;
   constexpr int ROWS = 16 * R;
-  extern __shared__ __align__(16) unsigned char smem[];
+  // Separate LDS objects, so that the compiler can see that the layer phases' loads and stores
+  // never alias and keep several blocks' MFMA chains in flight.
+  __shared__ s16x4 w1s[K * kNW * 2 * 64];
+  __shared__ bf16x8 w3s[K * kNW * 12];   // lanes (g, r < 3) of the layer-3 A fragments
+  __shared__ __align__(16) float b1s[K * kH];
+  __shared__ __align__(16) float b2s[K * kH];
+  __shared__ float b3s[K * 4];
+  __shared__ float mixs[K];
+  __shared__ __align__(16) __bf16 xs[R * 16 * kF];
+  __shared__ bf16x8 hs[K * kNW * R * 64];
+  __shared__ floatx4 ps[kNW * K * R * 16];
+  __shared__ floatx4 pk[K * ROWS];   // per-agent weighted probabilities or votes
+  // The environments' state between ticks (kept out of registers that the MLP wavefronts need).
+  __shared__ double s_cash[ROWS], s_value[ROWS], s_sum[ROWS], s_sum2[ROWS], s_peak[ROWS], s_mdd[ROWS];
+  __shared__ int s_pos[ROWS], s_trades[ROWS];
+  __shared__ double sp[ROWS], sp1[ROWS];
+  __shared__ float4 sf[ROWS * 4];
   __shared__ int s_item;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, e16 = lane & 15;
+  const bool mlp_wave = wave < kNW;
 
-  s16x4* w1s = reinterpret_cast<s16x4*>(smem + L::w1);
-  bf16x8* w3s = reinterpret_cast<bf16x8*>(smem + L::w3);
-  float* b1s = reinterpret_cast<float*>(smem + L::b1);
-  float* b2s = reinterpret_cast<float*>(smem + L::b2);
-  float* b3s = reinterpret_cast<float*>(smem + L::b3);
-  float* mixs = reinterpret_cast<float*>(smem + L::mix);
-  __bf16* xs = reinterpret_cast<__bf16*>(smem + L::x);
-  bf16x8* hs = reinterpret_cast<bf16x8*>(smem + L::h);
-  floatx4* ps = reinterpret_cast<floatx4*>(smem + L::part);
-
-  // Agents into LDS (W1, W3, biases) and registers (this wavefront's W2 slice).
+  // Agents into LDS (W1, W3, biases) and registers (each MLP wavefront's W2 slice).
   for (int i = tid; i < K * kNW * 2 * 64; i += kNT) w1s[i] = a.P.w1[i];
-  for (int i = tid; i < K * kNW * 64; i += kNT) w3s[i] = a.P.w3[i];
+  for (int i = tid; i < K * kNW * 12; i += kNT) {
+    const int kw = i / 12, gr = i % 12;   // fragment rows 3..15 are zero and not stored
+    w3s[i] = a.P.w3[kw * 64 + (gr / 3) * 16 + gr % 3];
+  }
   for (int i = tid; i < K * kH; i += kNT) {
     b1s[i] = a.P.b1[i];
     b2s[i] = a.P.b2[i];
@@ -171,16 +185,19 @@ __global__ __launch_bounds__(kNT, 1) void crypto_chunk_kernel(ChunkArgs a) {
   for (int i = tid; i < K * 4; i += kNT) b3s[i] = a.P.b3[i];
   for (int i = tid; i < K; i += kNT) mixs[i] = a.P.mix[i];
   bf16x8 w2[K][2][4];
+  {
+    const int wl = mlp_wave ? wave : 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
+      for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) w2[k][tt][kk] = a.P.w2[(((k * kNW + wave) * 2 + tt) * 4 + kk) * 64 + lane];
+        for (int kk = 0; kk < 4; ++kk) w2[k][tt][kk] = a.P.w2[(((k * kNW + wl) * 2 + tt) * 4 + kk) * 64 + lane];
+  }
 
-  // Environment lanes: lanes 0..15 of wavefronts 0..R-1, one environment each.
-  const bool env_lane = wave < R && lane < 16;
-  const int ce = 16 * wave + e16;
+  // The environment wavefront: lane ce < ROWS owns environment ce of the work item.
+  const bool env_lane = wave == kNW && lane < ROWS;
+  const int ce = lane;
 
   for (;;) {
     __syncthreads();
@@ -197,137 +214,167 @@ __global__ __launch_bounds__(kNT, 1) void crypto_chunk_kernel(ChunkArgs a) {
     const bool valid = env_lane && ce < nvalid;
     const int64_t n = n0 + ce;
 
-    fm_crypto_result st{};
-    int64_t tick = 0;
-    double p = 0.0;
-    float4 f[4];
+    const int64_t tick0 = d.start_tick + n * d.stride + t0;   // this environment's tick at t0
     if (valid) {
-      if (t0 == 0) {
-        st.cash = a.cash0;
-        st.value = a.cash0;
-        st.peak = a.cash0;
-      } else {
-        st = d.state[n];
+      double cash = a.cash0, value = a.cash0, sum = 0.0, sum2 = 0.0, peak = a.cash0, mdd = 0.0;
+      int pos = 0, trades = 0;
+      if (t0 != 0) {
+        const fm_crypto_result* r = d.state + n;
+        cash = r->cash;
+        value = r->value;
+        sum = r->sum_r;
+        sum2 = r->sum_r2;
+        peak = r->peak;
+        mdd = r->max_drawdown;
+        pos = r->position;
+        trades = r->trades;
       }
-      tick = d.start_tick + n * d.stride + t0;
-      p = a.mid[tick];
-      load_feat(a.feat, tick, f);
-      write_state_row(xs + ce * kF, st.cash, p, st.position, f);
+      s_cash[ce] = cash;
+      s_value[ce] = value;
+      s_sum[ce] = sum;
+      s_sum2[ce] = sum2;
+      s_peak[ce] = peak;
+      s_mdd[ce] = mdd;
+      s_pos[ce] = pos;
+      s_trades[ce] = trades;
+      const double p = a.mid[tick0];
+      sp[ce] = p;
+      float4 f[4];
+      load_feat(a.feat, tick0, f);
+      write_state_row(xs + ce * kF, cash, p, pos, f);
     } else if (env_lane) {
       const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      f[0] = f[1] = f[2] = f[3] = z;
+      float4 f[4] = {z, z, z, z};
       write_state_row(xs + ce * kF, 0.0, 0.0, 0, f);
     }
     __syncthreads();
 
     for (int s = 0; s < nt; ++s) {
       const int64_t t = t0 + s;
-      // Next tick's market row, in flight during the MLP.
-      double p1 = 0.0;
-      if (valid) {
-        p1 = a.mid[tick + 1];
-        load_feat(a.feat, tick + 1, f);
-      }
-      // Layer 1: hidden units 32w.. of every agent for every block of 16 environments.
+      if (mlp_wave) {
+        // Layer 1: hidden units 32w.. of every agent for every block of 16 environments.
+        s16x4 xb[R];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const s16x4 wa0 = w1s[((k * kNW + wave) * 2 + 0) * 64 + lane];
-        const s16x4 wa1 = w1s[((k * kNW + wave) * 2 + 1) * 64 + lane];
-        const floatx4 c0 = *reinterpret_cast<const floatx4*>(b1s + k * kH + 32 * wave + 4 * g);
-        const floatx4 c1 = *reinterpret_cast<const floatx4*>(b1s + k * kH + 32 * wave + 16 + 4 * g);
+        for (int b = 0; b < R; ++b) xb[b] = *reinterpret_cast<const s16x4*>(xs + (b * 16 + e16) * kF + 4 * g);
 #pragma unroll
-        for (int b = 0; b < R; ++b) {
-          const s16x4 xb = *reinterpret_cast<const s16x4*>(xs + (b * 16 + e16) * kF + 4 * g);
-          const floatx4 h0 = mfma16(wa0, xb, c0);
-          const floatx4 h1 = mfma16(wa1, xb, c1);
-          hs[((k * kNW + wave) * R + b) * 64 + lane] = pack_relu(h0, h1);
+        for (int k = 0; k < K; ++k) {
+          const s16x4 wa0 = w1s[((k * kNW + wave) * 2 + 0) * 64 + lane];
+          const s16x4 wa1 = w1s[((k * kNW + wave) * 2 + 1) * 64 + lane];
+          const floatx4 c0 = *reinterpret_cast<const floatx4*>(b1s + k * kH + 32 * wave + 4 * g);
+          const floatx4 c1 = *reinterpret_cast<const floatx4*>(b1s + k * kH + 32 * wave + 16 + 4 * g);
+#pragma unroll
+          for (int b = 0; b < R; ++b)
+            hs[((k * kNW + wave) * R + b) * 64 + lane] = pack_relu(mfma16(wa0, xb[b], c0), mfma16(wa1, xb[b], c1));
         }
+      } else if (valid) {
+        // Next tick's market row, staged in LDS while the MLP runs.
+        const int64_t tick = tick0 + s;
+        sp1[ce] = a.mid[tick + 1];
+        float4 f[4];
+        load_feat(a.feat, tick + 1, f);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sf[ce * 4 + i] = f[i];
       }
       __syncthreads();
-      // Layer 2 (this wavefront's 32 units) and its share of layer 3.
+      int explore_act = -1;
+      if (mlp_wave) {
+        // Layer 2 (this wavefront's 32 units) and its share of layer 3.
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const floatx4 c0 = *reinterpret_cast<const floatx4*>(b2s + k * kH + 32 * wave + 4 * g);
-        const floatx4 c1 = *reinterpret_cast<const floatx4*>(b2s + k * kH + 32 * wave + 16 + 4 * g);
-        const bf16x8 w3 = w3s[(k * kNW + wave) * 64 + lane];
+        for (int k = 0; k < K; ++k) {
+          const floatx4 c0 = *reinterpret_cast<const floatx4*>(b2s + k * kH + 32 * wave + 4 * g);
+          const floatx4 c1 = *reinterpret_cast<const floatx4*>(b2s + k * kH + 32 * wave + 16 + 4 * g);
+          bf16x8 w3 = {};
+          if (e16 < kA) w3 = w3s[(k * kNW + wave) * 12 + g * 3 + e16];
 #pragma unroll
-        for (int b = 0; b < R; ++b) {
-          floatx4 acc0 = c0, acc1 = c1;
+          for (int b = 0; b < R; ++b) {
+            bf16x8 hc[4];
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const bf16x8 hb = hs[((k * kNW + kk) * R + b) * 64 + lane];
-            acc0 = mfma_bf16(w2[k][0][kk], hb, acc0);
-            acc1 = mfma_bf16(w2[k][1][kk], hb, acc1);
+            for (int kk = 0; kk < 4; ++kk) hc[kk] = hs[((k * kNW + kk) * R + b) * 64 + lane];
+            floatx4 acc0 = c0, acc1 = c1;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+              acc0 = mfma_bf16(w2[k][0][kk], hc[kk], acc0);
+              acc1 = mfma_bf16(w2[k][1][kk], hc[kk], acc1);
+            }
+            const floatx4 q = mfma_bf16(w3, pack_relu(acc0, acc1), floatx4{0.0f, 0.0f, 0.0f, 0.0f});
+            if (lane < 16) ps[((wave * K + k) * R + b) * 16 + lane] = q;
           }
-          const floatx4 q = mfma_bf16(w3, pack_relu(acc0, acc1), floatx4{0.0f, 0.0f, 0.0f, 0.0f});
-          if (lane < 16) ps[((wave * K + k) * R + b) * 16 + lane] = q;
         }
+      } else if (valid && a.eps > 0.0f) {
+        // Exploration draw for this tick, while the MLP runs.
+        uint64_t c0 = static_cast<uint64_t>(n), c1 = static_cast<uint64_t>(t), c2 = 0, c3 = 0;
+        philox4x64_10(c0, c1, c2, c3, d.key, 1);
+        if (uniform_from_word(c0) < a.eps) explore_act = static_cast<int>(static_cast<uint32_t>(c1 >> 32) % 3u);
+      }
+      __syncthreads();
+      // One thread per (agent, environment): the agent's action values from the four partial
+      // sums (fixed order) and its weighted softmax, or its vote.
+      if (tid < K * ROWS) {
+        const int k = tid / ROWS, c = tid % ROWS, b = c >> 4, e = c & 15;
+        floatx4 q = ps[((0 * K + k) * R + b) * 16 + e];
+#pragma unroll
+        for (int w = 1; w < kNW; ++w) {
+          const floatx4 pw = ps[((w * K + k) * R + b) * 16 + e];
+          q[0] = q[0] + pw[0];
+          q[1] = q[1] + pw[1];
+          q[2] = q[2] + pw[2];
+        }
+        const float q0 = q[0] + b3s[4 * k], q1 = q[1] + b3s[4 * k + 1], q2 = q[2] + b3s[4 * k + 2];
+        floatx4 out;
+        if (a.rule == FM_RULE_AVG_SOFTMAX) {
+          const float m = fmaxf(q0, fmaxf(q1, q2));
+          const float e0 = __expf(q0 - m), e1 = __expf(q1 - m), e2 = __expf(q2 - m);
+          const float inv = __builtin_amdgcn_rcpf((e0 + e1) + e2);
+          const float wk = mixs[k];
+          out = floatx4{wk * (e0 * inv), wk * (e1 * inv), wk * (e2 * inv), 0.0f};
+        } else {
+          const int j = (q0 >= q1 && q0 >= q2) ? 0 : (q1 >= q2 ? 1 : 2);
+          out = floatx4{j == 0 ? 1.0f : 0.0f, j == 1 ? 1.0f : 0.0f, j == 2 ? 1.0f : 0.0f, 0.0f};
+        }
+        pk[k * ROWS + c] = out;
       }
       __syncthreads();
       // One lane per environment: ensemble rule, exploration, trade, statistics, next state row.
       if (valid) {
-        const int b = wave;
         float avg[kA] = {0.0f, 0.0f, 0.0f};
-        int votes[kA] = {0, 0, 0};
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          floatx4 q = ps[((0 * K + k) * R + b) * 16 + e16];
-#pragma unroll
-          for (int w = 1; w < kNW; ++w) {
-            const floatx4 pw = ps[((w * K + k) * R + b) * 16 + e16];
-            q[0] = q[0] + pw[0];
-            q[1] = q[1] + pw[1];
-            q[2] = q[2] + pw[2];
-          }
-          const float q0 = q[0] + b3s[4 * k], q1 = q[1] + b3s[4 * k + 1], q2 = q[2] + b3s[4 * k + 2];
-          if (a.rule == FM_RULE_AVG_SOFTMAX) {
-            const float m = fmaxf(q0, fmaxf(q1, q2));
-            const float e0 = __expf(q0 - m), e1 = __expf(q1 - m), e2 = __expf(q2 - m);
-            const float inv = 1.0f / ((e0 + e1) + e2);
-            const float wk = mixs[k];
-            avg[0] = avg[0] + wk * (e0 * inv);
-            avg[1] = avg[1] + wk * (e1 * inv);
-            avg[2] = avg[2] + wk * (e2 * inv);
-          } else {
-            const int j = (q0 >= q1 && q0 >= q2) ? 0 : (q1 >= q2 ? 1 : 2);
-            votes[0] += j == 0;
-            votes[1] += j == 1;
-            votes[2] += j == 2;
-          }
+          const floatx4 v = pk[k * ROWS + ce];
+          avg[0] = avg[0] + v[0];
+          avg[1] = avg[1] + v[1];
+          avg[2] = avg[2] + v[2];
         }
-        int act;
+        // Averaged probabilities, or vote counts (exact small integers).
+        int act = (avg[0] >= avg[1] && avg[0] >= avg[2]) ? 0 : (avg[1] >= avg[2] ? 1 : 2);
         float out[kA];
         if (a.rule == FM_RULE_AVG_SOFTMAX) {
-          act = (avg[0] >= avg[1] && avg[0] >= avg[2]) ? 0 : (avg[1] >= avg[2] ? 1 : 2);
           out[0] = avg[0];
           out[1] = avg[1];
           out[2] = avg[2];
         } else {
-          act = (votes[0] >= votes[1] && votes[0] >= votes[2]) ? 0 : (votes[1] >= votes[2] ? 1 : 2);
-          out[0] = static_cast<float>(votes[0]) / K;
-          out[1] = static_cast<float>(votes[1]) / K;
-          out[2] = static_cast<float>(votes[2]) / K;
+          out[0] = avg[0] / K;
+          out[1] = avg[1] / K;
+          out[2] = avg[2] / K;
         }
-        if (a.eps > 0.0f) {
-          uint64_t c0 = static_cast<uint64_t>(n), c1 = static_cast<uint64_t>(t), c2 = 0, c3 = 0;
-          philox4x64_10(c0, c1, c2, c3, d.key, 1);
-          if (uniform_from_word(c0) < a.eps) act = static_cast<int>(static_cast<uint32_t>(c1 >> 32) % 3u);
-        }
+        if (explore_act >= 0) act = explore_act;
         // Trade at p, mark at p1 (float64, one rounding per operation).
+        const double p = sp[ce], p1 = sp1[ce];
         const int pos1 = act - 1;
-        const int delta = pos1 - st.position;
-        const double cash1 = (st.cash - static_cast<double>(delta) * p) -
+        const int delta = pos1 - s_pos[ce];
+        const double cash1 = (s_cash[ce] - static_cast<double>(delta) * p) -
                              (static_cast<double>(delta < 0 ? -delta : delta) * p) * a.fee;
         const double v1 = cash1 + static_cast<double>(pos1) * p1;
-        const double r = v1 - st.value;
-        st.sum_r = st.sum_r + r;
-        st.sum_r2 = st.sum_r2 + r * r;
-        st.peak = fmax(st.peak, v1);
-        st.max_drawdown = fmax(st.max_drawdown, st.peak - v1);
-        st.trades += delta != 0;
-        st.cash = cash1;
-        st.position = pos1;
-        st.value = v1;
+        const double r = v1 - s_value[ce];
+        s_sum[ce] = s_sum[ce] + r;
+        s_sum2[ce] = s_sum2[ce] + r * r;
+        const double peak = fmax(s_peak[ce], v1);
+        s_peak[ce] = peak;
+        s_mdd[ce] = fmax(s_mdd[ce], peak - v1);
+        s_trades[ce] += delta != 0;
+        s_cash[ce] = cash1;
+        s_pos[ce] = pos1;
+        s_value[ce] = v1;
+        sp[ce] = p1;
         const int64_t o = t * d.n_envs + n;
         if (d.act) d.act[o] = static_cast<int8_t>(act);
         if (d.prob) {
@@ -335,16 +382,27 @@ __global__ __launch_bounds__(kNT, 1) void crypto_chunk_kernel(ChunkArgs a) {
           d.prob[3 * o + 1] = out[1];
           d.prob[3 * o + 2] = out[2];
         }
-        p = p1;
-        ++tick;
-        write_state_row(xs + ce * kF, st.cash, p, st.position, f);
+        float4 f[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f[i] = sf[ce * 4 + i];
+        write_state_row(xs + ce * kF, cash1, p1, pos1, f);
       }
       __syncthreads();
     }
     if (valid) {
-      st.ticks = t0 + nt;
-      d.state[n] = st;
-      if (t0 + nt == d.horizon) d.result[n] = st;
+      const bool last = t0 + nt == d.horizon;
+      for (int o = 0; o < (last ? 2 : 1); ++o) {
+        fm_crypto_result* r = o == 0 ? d.state + n : d.result + n;
+        r->cash = s_cash[ce];
+        r->value = s_value[ce];
+        r->sum_r = s_sum[ce];
+        r->sum_r2 = s_sum2[ce];
+        r->peak = s_peak[ce];
+        r->max_drawdown = s_mdd[ce];
+        r->position = s_pos[ce];
+        r->trades = s_trades[ce];
+        r->ticks = t0 + nt;
+      }
     }
   }
 }
@@ -355,13 +413,9 @@ __global__ void zero_counter(int* c) {
 
 template <int R, int K>
 hipError_t launch(const ChunkArgs& a, int grid, hipStream_t stream) {
-  using L = Lds<R, K>;
-  static_assert(L::total <= 160 * 1024 - 256, "LDS budget");
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&crypto_chunk_kernel<R, K>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(L::total));
-  if (e != hipSuccess) return e;
+  static_assert(Lds<R, K>::total <= 160 * 1024 - 256, "LDS budget");
   zero_counter<<<1, 64, 0, stream>>>(a.counter);
-  crypto_chunk_kernel<R, K><<<grid, kNT, L::total, stream>>>(a);
+  crypto_chunk_kernel<R, K><<<grid, kNT, 0, stream>>>(a);
   return hipGetLastError();
 }
 
