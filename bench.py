@@ -174,6 +174,69 @@ def bench_batched(dev, n_groups=64, reps=3):
             "schedule": "generic (runtime shapes)"}
 
 
+CRYPTO_FLOP_PER_ENV_STEP = 2 * 5 * (16 * 128 + 128 * 128 + 128 * 3)   # K=5 agents 16-128-128-3: 188,160
+
+
+def crypto_server(dev, tick_seed=11, n_ticks=1_000_000, chunk=256, rows=64):
+    from paper_2501_10709_amd.serve import CryptoServer
+    from workload import pack_actor_weights
+    from workload.crypto import crypto_actors, make_crypto_agents, make_ticks
+    m = make_ticks(seed=tick_seed, n_ticks=n_ticks)
+    W = pack_actor_weights(make_crypto_agents(crypto_actors()))
+    return m, CryptoServer(m.mid, m.feat, W, 5, eps=0.005, fee=2e-4, tile_rows=rows, chunk_ticks=chunk,
+                           device=dev)
+
+
+def serving_capacity(srv, n_req=64, n_envs=4096, horizon=1024):
+    """Saturated chunk launches: n_req requests of n_envs environments x horizon ticks admitted at
+    once; every launch is timed with HIP events on the stream it runs on."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for i in range(n_req):
+        srv.submit(n_envs, horizon, 1000 + 97 * i, 200, i)
+    times, done = [], []
+    while True:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        active, queued = srv.step()
+        b.record(stream)
+        times.append((a, b))
+        done += srv.poll()
+        if active == 0 and queued == 0:
+            done += srv.poll(wait=True)
+            break
+    torch.cuda.synchronize()
+    for rid in done:
+        srv.requests.pop(rid, None)
+    ms = [x.elapsed_time(y) for x, y in times]
+    steps = n_req * n_envs * horizon
+    tf = CRYPTO_FLOP_PER_ENV_STEP * steps / (sum(ms) / 1e3) / 1e12
+    return {"workload": f"{n_req} requests x {n_envs} envs x {horizon} ticks admitted together",
+            "env_steps_per_s": steps / (sum(ms) / 1e3), "launches": len(ms), "launch_ms": float(np.mean(ms)),
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / PEAK_BF16_TFLOPS, "traffic": None, "kernel": "crypto_chunk_kernel<4,5>",
+                         "flop_per_env_step": CRYPTO_FLOP_PER_ENV_STEP}}
+
+
+def bench_serving(dev, rate=200.0, n_requests=400):
+    """Continuous-batching serving of the crypto task (Poisson arrivals, FIFO admission by pool
+    bytes); p50/p99 request latency and throughput, and the saturated capacity."""
+    from paper_2501_10709_amd.serve import serve_poisson
+    from workload.crypto import poisson_requests
+    m, srv = crypto_server(dev)
+    cap = serving_capacity(srv)
+    reqs = poisson_requests(5, n_requests, rate, m.n_ticks)
+    offered = sum(q.n_envs * q.horizon for q in reqs)
+    lat, makespan, steps = serve_poisson(srv, reqs)
+    srv.close()
+    return {"workload": f"crypto serving: {m.n_ticks} ticks, K=5 bf16 agents 16-128-128-3 (averaged softmax), "
+                        f"eps 0.005, Poisson {rate:g} req/s, {n_requests} requests, N log-uniform 1-4096, "
+                        "horizon log-uniform 1k-100k ticks, 64-env tiles, 256-tick chunks",
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "throughput": steps / makespan, "unit": "env-steps/s", "offered": offered / reqs[-1].arrival_s,
+            "makespan_s": makespan, "capacity": cap}
+
+
 def cpu_baseline(w, seconds_hint=True):
     """The oracle (float64 numpy) on the same workload, timed on the host."""
     from oracle.rollout import rollout_closed_loop
@@ -216,6 +279,11 @@ def profile_kernel(args):
     if args.kernel == "batched":
         print(json.dumps(bench_batched(dev, reps=max(1, args.steps))), flush=True)
         return
+    if args.kernel == "serve":
+        _, srv = crypto_server(dev)
+        print(json.dumps(serving_capacity(srv, n_req=max(1, args.steps) * 16)), flush=True)
+        srv.close()
+        return
     w = WORKLOADS[args.workload]
     cfg, acfg = w.env, w.actors
     N, D, T, S, H, K = cfg.n_envs, cfg.n_stocks, cfg.n_days, cfg.state_dim, acfg.hidden, acfg.n_actors
@@ -244,7 +312,7 @@ def main():
     ap.add_argument("--workload", default="paper", choices=["paper", "precision", "envlarge"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=None, help="timed rollouts of the plain float32 path")
-    ap.add_argument("--kernel", choices=["fused", "driven", "plain", "copy", "batched"], default=None,
+    ap.add_argument("--kernel", choices=["fused", "driven", "plain", "copy", "batched", "serve"], default=None,
                     help="profiling mode: one warm-up and --steps launches of one kernel, nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -349,6 +417,7 @@ def main():
                                    "traffic": traffic_for("env_tile_kernel<1>@65536", NL * TL)}},
     }
     rec["batched_uneven"] = bench_batched(dev)
+    rec["serving"] = bench_serving(dev)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)
