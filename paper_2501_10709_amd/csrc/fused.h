@@ -23,6 +23,7 @@ inline size_t fused_table_floats() { return static_cast<size_t>(kFusedChunk) * 8
 struct FusedTuning {
   int row_tiles = 0;  // 0: choose from the problem size
   int schedule = 0;   // 0: streamed when the shape allows, 2: always the generic schedule
+  int tile_envs = 0;  // streamed: environments per workgroup, 0: fill the compute units
 };
 
 // True when the streamed MLP schedule handles this ensemble and environment.

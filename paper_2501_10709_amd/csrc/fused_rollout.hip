@@ -15,6 +15,7 @@
 //     of all actors), keeping DEPTH k-steps of fragments in flight in registers.  The sequence
 //     wraps around, so the first fragments of the next step load while the trading chain runs.
 //   * generic (any supported shape): four wavefronts, runtime loops, one fragment at a time.
+#include <algorithm>
 #include <cstring>
 #include <utility>
 
@@ -37,6 +38,7 @@ struct FusedArgs {
   int* qty_traj;
   const float* eps;  // streamed schedule: the chunk's noise [n_steps][N][D]
   const float* mt;   // streamed schedule: the chunk's layer-1 market shares [n_steps][K][H]
+  int tile_envs = 0; // streamed schedule: environments per workgroup (<= its 16 * ROWT rows)
 };
 
 // Calls f(std::integral_constant<int, i>) for i = 0 .. N-1, fully unrolled.
@@ -514,8 +516,10 @@ __global__ __launch_bounds__(kStreamThreads) void fused_streamed_kernel(EnvConst
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int D = C.D, N = C.N, DS = D + 1, S = C.S, I = C.I;
-  const int n0 = blockIdx.x * MR;
-  const int M = min(MR, N - n0);
+  // A workgroup owns tile_envs <= MR environments; the MFMA rows beyond them stay zero, as in a
+  // ragged last tile.  Smaller tiles spread a small N over every compute unit.
+  const int n0 = blockIdx.x * F.tile_envs;
+  const int M = min(F.tile_envs, N - n0);
   const ChainShape Z = ChainShape::of(D);
 
   StreamLds L;
@@ -960,7 +964,8 @@ template <int ROWT, int KKE>
 hipError_t launch_streamed_kernel(const EnvConst& C, const EnvState& st, const EnsDev& E, const FusedArgs& F,
                                   hipStream_t stream) {
   const size_t lds = streamed_lds_bytes<ROWT, KKE>(C);
-  const int grid = (C.N + 16 * ROWT - 1) / (16 * ROWT);
+  if (F.tile_envs < 1 || F.tile_envs > 16 * ROWT) return hipErrorInvalidValue;
+  const int grid = (C.N + F.tile_envs - 1) / F.tile_envs;
   return go(fused_streamed_kernel<ROWT, KKE, streamed_depth<ROWT>()>, grid, kStreamThreads, lds, stream, C, st,
             E, F);
 }
@@ -1070,6 +1075,19 @@ hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const Ens
   int rowt = tune.row_tiles;
   if (rowt <= 0) rowt = C.N >= 4096 ? 2 : 1;
   rowt = rowt >= 2 ? 2 : 1;
+  // Environments per workgroup: a full 16 * rowt rows, or fewer when that leaves compute units
+  // idle (one workgroup fits a compute unit).
+  F.tile_envs = 16 * rowt;
+  if (tune.tile_envs > 0) {
+    F.tile_envs = std::min(tune.tile_envs, 16 * rowt);
+  } else {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+      const int per_cu = (C.N + cus - 1) / cus;
+      if (per_cu < F.tile_envs) F.tile_envs = std::max(per_cu, 1);
+    }
+  }
   if (tune.schedule != 2 && fused_streamed_shape(C, E))
     return launch_streamed(C, st, E, F, rowt, eps_chunk, mt_chunk, stream);
   if (C.D > 128) {
