@@ -55,8 +55,8 @@ CHUNK = 64  # steps per fused-kernel launch (the library's chunk)
 
 
 # Sources the stock-environment and fused-rollout kernels (and their launch choices) are built from.
-PROFILED_SOURCES = ("api.hip", "device_common.h", "ensemble_kernels.hip", "env_kernels.hip", "fused.h",
-                    "fused_rollout.hip", "launch.h", "mlp_device.h")
+PROFILED_SOURCES = ("api.hip", "crypto_serve.hip", "device_common.h", "ensemble_kernels.hip", "env_kernels.hip",
+                    "fused.h", "fused_rollout.hip", "launch.h", "mlp_device.h", "status.h")
 
 
 def source_hash():
@@ -214,7 +214,9 @@ def serving_capacity(srv, n_req=64, n_envs=4096, horizon=1024):
     return {"workload": f"{n_req} requests x {n_envs} envs x {horizon} ticks admitted together",
             "env_steps_per_s": steps / (sum(ms) / 1e3), "launches": len(ms), "launch_ms": float(np.mean(ms)),
             "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                         "frac": tf / PEAK_BF16_TFLOPS, "traffic": None, "kernel": "crypto_chunk_kernel<4,5>",
+                         "frac": tf / PEAK_BF16_TFLOPS,
+                         "traffic": traffic_for("crypto_chunk_kernel<4,5>", steps / len(ms)),
+                         "kernel": "crypto_chunk_kernel<4,5>",
                          "flop_per_env_step": CRYPTO_FLOP_PER_ENV_STEP}}
 
 
