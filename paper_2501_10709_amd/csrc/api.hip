@@ -32,14 +32,13 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
 
-// Environments per 64-lane workgroup of the environment kernels: small tiles spread the serial
-// trading chains over more compute units; the tile is capped by the kernels' LDS budget.
 // Environments per workgroup of the environment kernels by problem size (measured on MI355X,
-// D = 30, driven rollouts): small tiles while the grid does not fill the GPU, large tiles once it
-// does (the per-step cost of a workgroup grows much slower than its tile).
+// D = 30, driven rollouts): tiles of 8 spread the serial trading chains over every compute unit
+// while the grid does not fill the GPU, and from 8192 environments the kernel runs them three to
+// a compute unit; from 16384, tiles of 16, also three to a compute unit (the per-step cost of a
+// workgroup grows much slower than its tile).  The tile is capped by the kernel's LDS budget.
 int env_tile(int N) {
-  if (N >= 16384) return 64;
-  if (N >= 8192) return 32;
+  if (N >= 16384) return 16;
   return 8;
 }
 

@@ -71,8 +71,13 @@ __host__ __device__ inline size_t tile_lds_bytes(int M, int D, int I) {
 // triple-buffered, so no role waits for another inside a step.  Vector-memory completions are
 // counted per wavefront in issue order, so with the roles split the chain never waits on HBM and
 // the store wavefront never waits for the fetches.
-template <int MODE>
-__global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvState st, StepArgs A) {
+//
+// OCC is the number of workgroups a compute unit is meant to hold: 1 (latency: all registers,
+// cash chunks of 8 stocks) when the grid does not fill the GPU; 2 or 3 (throughput: at most 256
+// or 168 registers per lane, chunks of 4, and for 3 half the fetch staging registers) when
+// there are more tiles than compute units and that many workgroups fit the LDS.
+template <int MODE, int OCC>
+__global__ __launch_bounds__(3 * kWave, OCC) void env_tile_kernel(EnvConst C, EnvState st, StepArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & (kWave - 1);
   const int role = threadIdx.x / kWave;  // 0 chain, 1 store, 2 fetch
@@ -121,7 +126,7 @@ __global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvStat
 
   const int n_iter = trades(MODE) ? A.n_steps : 1;
   const int total = n_mkt + ((MODE == kGiven) ? MD : 0);  // fetched floats per step
-  const int staged = min(total, kStage * kWave);
+  const int staged = min(total, (OCC >= 3 ? kStage / 2 : kStage) * kWave);
 
   // Fetch wavefront.  Flat index i of step it's inputs: close[t] (D; zeros when not trading),
   // close[tn] (D), ind[tn] (I*D), then, driven, the tile's actions (M*D) -- which is also the
@@ -134,10 +139,11 @@ __global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvStat
     if (i < n_mkt) return C.ind + static_cast<size_t>(tn) * C.I * D + (i - 2 * D);
     return A.act + (static_cast<size_t>(it) * N + n0) * D + (i - n_mkt);
   };
-  float stage[kStage];
+  constexpr int NSTAGE = OCC >= 3 ? kStage / 2 : kStage;
+  float stage[NSTAGE];
   auto fetch_issue = [&](int it) {
 #pragma unroll
-    for (int j = 0; j < kStage; ++j) {
+    for (int j = 0; j < NSTAGE; ++j) {
       const int i = lane + kWave * j;
       stage[j] = (i < staged && (i >= D || trades(MODE))) ? *src_of(it, i) : 0.0f;
     }
@@ -145,7 +151,7 @@ __global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvStat
   auto fetch_commit = [&](int it) {
     float* buf = s_in0 + (it % kInBufs) * IB;
 #pragma unroll
-    for (int j = 0; j < kStage; ++j) {
+    for (int j = 0; j < NSTAGE; ++j) {
       const int i = lane + kWave * j;
       if (i < staged) buf[i] = stage[j];
     }
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvStat
           chain_pairs_a(CL, Z, M, lane, kWave, C.hmax_f, C.one_m, C.one_p);
           wave_lds_sync();
           if (active)
-            chain_serial(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.c1, CL.rc1, CL.qd + lane * Z.RI, CL.px,
+            chain_serial<OCC == 1 ? 8 : 4>(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.c1, CL.rc1, CL.qd + lane * Z.RI, CL.px,
                          CL.kq + lane * Z.RI, Z.DP, C.one_p);
           wave_lds_sync();
           chain_pairs_c(CL, Z, M, lane, kWave, C.hold_scale);
@@ -262,20 +268,32 @@ __global__ __launch_bounds__(3 * kWave) void env_tile_kernel(EnvConst C, EnvStat
   }
 }
 
+template <int MODE, int OCC>
+hipError_t launch_tile(const EnvConst& C, const EnvState& st, const StepArgs& A, size_t lds, int grid,
+                       hipStream_t stream) {
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(env_tile_kernel<MODE, OCC>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((env_tile_kernel<MODE, OCC>), dim3(grid), dim3(3 * kWave), lds, stream, C, st, A);
+  return hipGetLastError();
+}
+
 template <int MODE>
 hipError_t dispatch_tile(const EnvConst& C, const EnvState& st, StepArgs A, hipStream_t stream) {
   A.M = max(1, min(A.M, 64));
   while (A.M > 1 && tile_lds_bytes(A.M, C.D, C.I) > kMaxLds) A.M /= 2;
   const size_t lds = tile_lds_bytes(A.M, C.D, C.I);
   if (lds > kMaxLds) return hipErrorInvalidValue;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(env_tile_kernel<MODE>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    if (e != hipSuccess) return e;
-  }
   const int grid = (C.N + A.M - 1) / A.M;
-  hipLaunchKernelGGL((env_tile_kernel<MODE>), dim3(grid), dim3(3 * kWave), lds, stream, C, st, A);
-  return hipGetLastError();
+  // Two workgroups per compute unit when there are more tiles than compute units and two fit.
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 0;
+  if (cus > 0 && grid > 2 * cus && 3 * lds <= kMaxLds) return launch_tile<MODE, 3>(C, st, A, lds, grid, stream);
+  if (cus > 0 && grid > cus && 2 * lds <= kMaxLds) return launch_tile<MODE, 2>(C, st, A, lds, grid, stream);
+  return launch_tile<MODE, 1>(C, st, A, lds, grid, stream);
 }
 
 __global__ void read_state_kernel(int N, int D, EnvState st, double* cash, int* hold,
