@@ -230,13 +230,20 @@ def bench_serving(dev, rate=200.0, n_requests=400):
     reqs = poisson_requests(5, n_requests, rate, m.n_ticks)
     offered = sum(q.n_envs * q.horizon for q in reqs)
     lat, makespan, steps = serve_poisson(srv, reqs)
+    sweep = []
+    for r in (100.0, 300.0):
+        rq = poisson_requests(6, n_requests // 2, r, m.n_ticks)
+        la, mk, st = serve_poisson(srv, rq)
+        sweep.append({"rate_per_s": r, "requests": len(rq), "p50_ms": float(np.percentile(la, 50) * 1e3),
+                      "p99_ms": float(np.percentile(la, 99) * 1e3), "throughput": st / mk,
+                      "offered": sum(q.n_envs * q.horizon for q in rq) / rq[-1].arrival_s})
     srv.close()
     return {"workload": f"crypto serving: {m.n_ticks} ticks, K=5 bf16 agents 16-128-128-3 (averaged softmax), "
                         f"eps 0.005, Poisson {rate:g} req/s, {n_requests} requests, N log-uniform 1-4096, "
                         "horizon log-uniform 1k-100k ticks, 64-env tiles, 256-tick chunks",
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "throughput": steps / makespan, "unit": "env-steps/s", "offered": offered / reqs[-1].arrival_s,
-            "makespan_s": makespan, "capacity": cap}
+            "makespan_s": makespan, "capacity": cap, "load_sweep": sweep}
 
 
 def cpu_baseline(w, seconds_hint=True):
@@ -261,6 +268,67 @@ def cpu_baseline(w, seconds_hint=True):
     return {"value": reps * cfg.n_envs * T / dt, "unit": "env-steps/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{reps} closed-loop oracle rollout(s) of all {cfg.n_envs} envs x {T} days, "
                       f"float64 numpy, {dt:.1f} s", "host_cpus": os.cpu_count()}
+
+
+def _oracle_shard(job):
+    """One process's share of the sharded CPU baseline: a closed-loop oracle rollout of n envs with
+    one BLAS thread.  Returns the seconds it took."""
+    name, n = job
+    from threadpoolctl import threadpool_limits
+    from oracle.rollout import rollout_closed_loop
+    from workload import WORKLOADS, make_actor_weights, make_market
+    w = WORKLOADS[name]
+    cfg = w.env
+    m = make_market(w.market_seed, cfg.n_stocks, cfg.n_days)
+    actors = make_actor_weights(w.actors)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        rollout_closed_loop(cfg, m.close, m.ind, actors, cfg.n_days, w.sigma, w.noise_key, n_envs=n)
+        return time.perf_counter() - t0
+
+
+def _noop(_):
+    return 0
+
+
+def cpu_baseline_sharded(key, procs=None):
+    """The oracle with the environments split across processes (they are independent), one BLAS
+    thread each.  Run before the GPU is touched: the pool's processes are started fresh."""
+    import concurrent.futures
+    import multiprocessing
+    from workload import WORKLOADS
+    w = WORKLOADS[key]
+    procs = procs or os.cpu_count() or 1
+    N, T = w.env.n_envs, w.env.n_days
+    shares = [N // procs + (1 if i < N % procs else 0) for i in range(procs)]
+    ctx = multiprocessing.get_context("spawn")
+    with concurrent.futures.ProcessPoolExecutor(procs, mp_context=ctx) as ex:
+        list(ex.map(_noop, range(procs)))              # start every worker first
+        t0 = time.perf_counter()
+        per = list(ex.map(_oracle_shard, [(key, n) for n in shares if n > 0]))
+        dt = time.perf_counter() - t0
+    return {"value": N * T / dt, "unit": "env-steps/s", "cores": procs, "kind": "oracle",
+            "sample": f"one closed-loop oracle rollout of {N} envs x {T} days split over {procs} processes "
+                      f"(one BLAS thread each), {dt:.1f} s wall, slowest share {max(per):.1f} s"}
+
+
+def hbm_copy_gbs(dev, nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth on this GPU: a 1 GiB device-to-device copy (read + write bytes)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (float(np.median(ts)) / 1e3) / 1e9
 
 
 def profile_kernel(args):
@@ -331,6 +399,9 @@ def main():
         profile_kernel(args)
         return
     w = WORKLOADS[args.workload]
+    sharded = None
+    if not args.no_cpu_baseline:
+        sharded = cpu_baseline_sharded(args.workload)
     cfg, acfg = w.env, w.actors
     N, D, T, S, H, K = cfg.n_envs, cfg.n_stocks, cfg.n_days, cfg.state_dim, acfg.hidden, acfg.n_actors
     dev = torch.device("cuda:0")
@@ -420,8 +491,13 @@ def main():
     }
     rec["batched_uneven"] = bench_batched(dev)
     rec["serving"] = bench_serving(dev)
+    copy = hbm_copy_gbs(dev)
+    rec["env_roofline"]["hbm_copy_GBs"] = copy
+    rec["env_roofline"]["frac_of_copy"] = achieved_gbs / copy
+    rec["env_roofline"]["large"]["frac_of_copy"] = large_gbs / copy
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
+        rec["cpu_baseline_sharded"] = sharded
     print(json.dumps(rec), flush=True)
 
 
