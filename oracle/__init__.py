@@ -16,6 +16,8 @@ Plain, slow, float64 numpy code written from the paper:
                   tensors and R(tau) = sum_t gamma^t r_t).
   * metrics.py -- backtest metrics (Section 6.1), softmax-of-Sharpe weights and
                   the majority vote (Section 5.2).
+  * learner.py -- the consumer of the samples: the Monte-Carlo policy gradient
+                  of eq. (4) with the agent-diversity KL term of eq. (5).
   * crypto.py  -- the single-asset crypto task: discrete target positions with a
                   proportional fee, the agents' Q-networks, the averaged-softmax
                   and majority-vote ensemble rules, exploration draws and the
