@@ -24,7 +24,7 @@ EXPORTS = (
     "ensemble_act", "ensemble_destroy", "fm_last_error", "fm_noise", "fm_version", "fm_backtest_metrics",
     "fm_sharpe_weights", "fm_batch_workspace_bytes", "fm_batch_create", "fm_batch_tune", "fm_batch_run",
     "fm_batch_destroy", "fm_serve_request_bytes", "fm_serve_workspace_bytes", "fm_serve_create", "fm_serve_submit",
-    "fm_serve_step", "fm_serve_poll", "fm_serve_destroy",
+    "fm_serve_step", "fm_serve_poll", "fm_serve_destroy", "fm_pg_workspace_bytes", "fm_policy_gradient",
 )
 FM_RULE_AVG_SOFTMAX, FM_RULE_MAJORITY_VOTE = 0, 1
 
@@ -134,6 +134,9 @@ def load(path: str = LIB_PATH):
         "fm_serve_step": (I32, [P, P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "fm_serve_poll": (I32, [P, I32, ctypes.POINTER(I64), I32, ctypes.POINTER(I32)]),
         "fm_serve_destroy": (None, [P]),
+        "fm_pg_workspace_bytes": (SZ, [I32, I32, I32, I32, I32, I32]),
+        "fm_policy_gradient": (I32, [I32, I32, I32, I32, P, P, I32, P, P, I32, I32, ctypes.c_float, U64, I64,
+                                     ctypes.c_float, P, P, SZ, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -403,3 +406,29 @@ def fm_serve_poll(server, wait=False, cap=4096):
 
 def fm_serve_destroy(server):
     load().fm_serve_destroy(server)
+
+
+# ------------------------------------------------------------------------------------------------
+# Learner (include/learner.h)
+# ------------------------------------------------------------------------------------------------
+
+def fm_pg_workspace_bytes(K, S, H, A, N, T) -> int:
+    return int(load().fm_pg_workspace_bytes(K, S, H, A, N, T))
+
+
+def fm_policy_gradient(K, S, H, A, d_w, agent, d_states, d_rew, N, T, sigma, noise_key, env_offset, lambda_kl,
+                       d_grad, d_workspace, mix=None, stream=None):
+    """Gradient of agent `agent`'s objective (eqs. 4 and 5) into d_grad (float32, one actor's
+    master-weight layout)."""
+    import numpy as np
+    import torch
+    h_mix = None
+    if mix is not None:
+        h_mix = np.ascontiguousarray(mix, dtype=np.float32)
+    per = S * H + H + H * H + H + H * A + A
+    _check(load().fm_policy_gradient(
+        K, S, H, A, _ptr(d_w, torch.float32, K * per, "d_w"), None if h_mix is None else h_mix.ctypes.data, agent,
+        _ptr(d_states, torch.float32, T * N * S, "d_states"), _ptr(d_rew, torch.float64, T * N, "d_rew"), N, T,
+        float(sigma), int(noise_key), int(env_offset), float(lambda_kl), _ptr(d_grad, torch.float32, per, "d_grad"),
+        _ptr(d_workspace, None, None, "d_workspace"), d_workspace.numel() * d_workspace.element_size(),
+        _stream(stream)))

@@ -1,0 +1,356 @@
+// The learner that consumes the rollout's samples (include/learner.h): the policy gradient of
+// eq. (4) with the agent-diversity term of eq. (5), by the chain rule through agent i's network.
+//
+// Pipeline, all on the caller's stream: the K actors' forward passes over the T*N sample rows
+// (agent i last, so its layer activations stay in the workspace); the returns R_n; per row the
+// derivative of the objective with respect to mu_i, times tanh' (the layer-3 delta); then back
+// through layers 3, 2, 1: each weight gradient X^T G is a reduction over the rows, split over
+// row chunks into float32 partial products and summed in float64 in chunk order; each delta of
+// the layer below is (G W^T) * (1 - X^2), written over the activation it masks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "../../include/learner.h"
+#include "device_common.h"
+#include "status.h"
+
+namespace fm {
+namespace lrn {
+
+constexpr int kTile = 64, kBK = 16, kThreads = 256, kMaxK = 8;
+
+enum Epilogue { kBiasTanh = 0, kMaskTanhGrad = 1, kStore = 2 };
+
+// C(m, n) = sum_k A(m, k) B(k, n) over k in the block's range, with element (m, k) of A at
+// A[m * sam + k * sak] and (k, n) of B at B[k * sbk + n * sbn].  blockIdx.z selects a chunk of
+// kc values of k (split reductions) and offsets C by z * scz.  Epilogues: kBiasTanh,
+// C = tanh(acc + bias[n]); kMaskTanhGrad, C = acc * (1 - X^2) with X at the same place as C (C may
+// be X itself: each element is read and written by one thread); kStore, C = acc.  Each thread
+// owns a 4 x 4 block of C and accumulates in float32 in ascending k.
+struct Gemm {
+  const float* A;
+  long sam, sak;
+  const float* B;
+  long sbk, sbn;
+  float* C;
+  long scm, scn, scz;
+  const float* bias;
+  const float* X;
+  int M, N, K, kc;
+};
+
+template <int EPI>
+__global__ __launch_bounds__(kThreads) void gemm_kernel(Gemm g) {
+  __shared__ float As[kBK][kTile + 4];
+  __shared__ float Bs[kBK][kTile + 4];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
+  const int k_begin = blockIdx.z * g.kc, k_end = min(g.K, k_begin + g.kc);
+  float acc[4][4] = {};
+  for (int k0 = k_begin; k0 < k_end; k0 += kBK) {
+    // 64 x 16 of A and 16 x 64 of B, four elements per thread each, zero outside the ranges.
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = tid + kThreads * e;
+      const int am = i % kTile, ak = i / kTile;
+      const int m = m0 + am, k = k0 + ak;
+      As[ak][am] = (m < g.M && k < k_end) ? g.A[m * g.sam + k * g.sak] : 0.0f;
+      const int bn = i % kTile, bk = i / kTile;
+      const int n = n0 + bn, kb = k0 + bk;
+      Bs[bk][bn] = (n < g.N && kb < k_end) ? g.B[kb * g.sbk + n * g.sbn] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kBK; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = acc[r][c] + a[r] * b[c];
+    }
+    __syncthreads();
+  }
+  float* C = g.C + blockIdx.z * g.scz;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int m = m0 + ty * 4 + r;
+    if (m >= g.M) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int n = n0 + tx * 4 + c;
+      if (n >= g.N) continue;
+      const long o = m * g.scm + n * g.scn;
+      if (EPI == kBiasTanh) {
+        C[o] = tanhf(acc[r][c] + g.bias[n]);
+      } else if (EPI == kMaskTanhGrad) {
+        const float x = g.X[o];
+        C[o] = acc[r][c] * (1.0f - x * x);
+      } else {
+        C[o] = acc[r][c];
+      }
+    }
+  }
+}
+
+// R_n = sum_t r[t][n] in ascending t.
+__global__ void returns_kernel(const double* rew, int T, int N, double* R) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  double acc = 0.0;
+  for (int t = 0; t < T; ++t) acc = acc + rew[static_cast<size_t>(t) * N + n];
+  R[n] = acc;
+}
+
+struct Mix {
+  float w[kMaxK];
+};
+
+// Layer-3 delta of agent i for row r = t*N + n and actions 4j..4j+3 (one noise block):
+//   u = (R_n / N) (abar + sigma eps - mu_i) / sigma^2 + lambda/(N T) sum_{k != i} (mu_i - mu_k) / sigma^2
+//   G3 = u (1 - mu_i^2).
+__global__ void delta3_kernel(const float* mu, int K, int agent, Mix mix, int rows, int N, int T, int A,
+                              const double* R, float sigma, uint64_t key, int64_t env_offset, float lambda_kl,
+                              float* G3) {
+  const int G = (A + 3) / 4;
+  const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<long>(rows) * G) return;
+  const int r = static_cast<int>(i / G), j = static_cast<int>(i % G);
+  const int t = r / N, n = r % N;
+  float z[4];
+  noise_block(key, static_cast<uint64_t>(env_offset + n), static_cast<uint64_t>(t), static_cast<uint64_t>(j), z);
+  const float inv_s2 = 1.0f / (sigma * sigma);
+  const float rn = static_cast<float>(R[n] / N);
+  const float kl = lambda_kl / (static_cast<float>(N) * static_cast<float>(T));
+  for (int q = 0; q < 4; ++q) {
+    const int a = 4 * j + q;
+    if (a >= A) break;
+    const size_t off = static_cast<size_t>(r) * A + a;
+    const size_t plane = static_cast<size_t>(rows) * A;
+    const float mi = mu[agent * plane + off];
+    float abar = 0.0f, div = 0.0f;
+    for (int k = 0; k < K; ++k) {
+      const float mk = mu[k * plane + off];
+      abar = abar + mix.w[k] * mk;
+      if (k != agent) div = div + (mi - mk);
+    }
+    const float u = rn * ((abar + sigma * z[q]) - mi) * inv_s2 + kl * div * inv_s2;
+    G3[off] = u * (1.0f - mi * mi);
+  }
+}
+
+// Pb[c][col] = sum of G[r][col] over the rows of chunk c (ascending r).
+__global__ void colsum_kernel(const float* Gm, int rows, int cols, int chunk, int n_chunks, float* Pb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_chunks * cols) return;
+  const int c = i / cols, col = i % cols;
+  const int r0 = c * chunk, r1 = min(rows, r0 + chunk);
+  float acc = 0.0f;
+  for (int r = r0; r < r1; ++r) acc = acc + Gm[static_cast<size_t>(r) * cols + col];
+  Pb[i] = acc;
+}
+
+// out[i] = sum over chunks c (ascending) of P[c][i], in float64, rounded once.
+__global__ void reduce_kernel(const float* P, int len, int n_chunks, float* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  double acc = 0.0;
+  for (int c = 0; c < n_chunks; ++c) acc = acc + static_cast<double>(P[static_cast<size_t>(c) * len + i]);
+  out[i] = static_cast<float>(acc);
+}
+
+struct Layout {
+  size_t mu, x1, x2, g3, R, P, Pb, total;
+  int rows, chunk, n_chunks;
+};
+
+Layout layout(int K, int S, int H, int A, int N, int T) {
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  Layout L{};
+  L.rows = N * T;
+  L.chunk = std::max(2048, (L.rows + 255) / 256);
+  L.n_chunks = (L.rows + L.chunk - 1) / L.chunk;
+  const size_t rows = L.rows;
+  size_t o = 0;
+  L.mu = o;
+  o = al(o + sizeof(float) * K * rows * A);
+  L.x1 = o;
+  o = al(o + sizeof(float) * rows * H);
+  L.x2 = o;
+  o = al(o + sizeof(float) * rows * H);
+  L.g3 = o;
+  o = al(o + sizeof(float) * rows * A);
+  L.R = o;
+  o = al(o + sizeof(double) * N);
+  const size_t pmax = std::max({static_cast<size_t>(S) * H, static_cast<size_t>(H) * H, static_cast<size_t>(H) * A});
+  L.P = o;
+  o = al(o + sizeof(float) * L.n_chunks * pmax);
+  L.Pb = o;
+  o = al(o + sizeof(float) * L.n_chunks * std::max(H, A));
+  L.total = o;
+  return L;
+}
+
+template <int EPI>
+hipError_t gemm(const Gemm& g, int z, hipStream_t stream) {
+  const dim3 grid((g.M + kTile - 1) / kTile, (g.N + kTile - 1) / kTile, z);
+  hipLaunchKernelGGL(gemm_kernel<EPI>, grid, dim3(kThreads), 0, stream, g);
+  return hipGetLastError();
+}
+
+// Weight gradient X^T G: Xr [rows][kin] (row stride ldx), Gr [rows][kout]; result into out
+// [kin][kout], bias gradient (column sums of G) into bout [kout].
+hipError_t weight_grad(const Layout& L, const float* Xr, int kin, int ldx, const float* Gr, int kout, float* P,
+                       float* Pb, float* out, float* bout, hipStream_t stream) {
+  Gemm g{};
+  g.A = Xr;
+  g.sam = 1;
+  g.sak = ldx;
+  g.B = Gr;
+  g.sbk = kout;
+  g.sbn = 1;
+  g.C = P;
+  g.scm = kout;
+  g.scn = 1;
+  g.scz = static_cast<long>(kin) * kout;
+  g.M = kin;
+  g.N = kout;
+  g.K = L.rows;
+  g.kc = L.chunk;
+  hipError_t e = gemm<kStore>(g, L.n_chunks, stream);
+  if (e != hipSuccess) return e;
+  const int len = kin * kout;
+  hipLaunchKernelGGL(reduce_kernel, dim3((len + 255) / 256), dim3(256), 0, stream, P, len, L.n_chunks, out);
+  const int nb = L.n_chunks * kout;
+  hipLaunchKernelGGL(colsum_kernel, dim3((nb + 255) / 256), dim3(256), 0, stream, Gr, L.rows, kout, L.chunk,
+                     L.n_chunks, Pb);
+  hipLaunchKernelGGL(reduce_kernel, dim3((kout + 255) / 256), dim3(256), 0, stream, Pb, kout, L.n_chunks, bout);
+  return hipGetLastError();
+}
+
+// Delta of the layer below: Gout [rows][kin] = (Gin [rows][kout] W^T) * (1 - X^2), W [kin][kout],
+// written over X [rows][kin].
+hipError_t back_delta(const Layout& L, const float* Gin, int kout, const float* W, int kin, float* X,
+                      hipStream_t stream) {
+  Gemm g{};
+  g.A = Gin;
+  g.sam = kout;
+  g.sak = 1;
+  g.B = W;
+  g.sbk = 1;
+  g.sbn = kout;
+  g.C = X;
+  g.scm = kin;
+  g.scn = 1;
+  g.X = X;
+  g.M = L.rows;
+  g.N = kin;
+  g.K = kout;
+  g.kc = kout;
+  return gemm<kMaskTanhGrad>(g, 1, stream);
+}
+
+// Y [rows][kout] = tanh(X [rows][kin] W + b).
+hipError_t layer(const Layout& L, const float* X, int kin, const float* W, const float* b, int kout, float* Y,
+                 hipStream_t stream) {
+  Gemm g{};
+  g.A = X;
+  g.sam = kin;
+  g.sak = 1;
+  g.B = W;
+  g.sbk = kout;
+  g.sbn = 1;
+  g.C = Y;
+  g.scm = kout;
+  g.scn = 1;
+  g.bias = b;
+  g.M = L.rows;
+  g.N = kout;
+  g.K = kin;
+  g.kc = kin;
+  return gemm<kBiasTanh>(g, 1, stream);
+}
+
+bool dims_ok(int K, int S, int H, int A, int N, int T) {
+  if (K < 1 || K > kMaxK || S < 1 || S > 1024 || H < 1 || H > 1024 || A < 1 || A > 128 || N < 1 || T < 1)
+    return false;
+  return static_cast<int64_t>(N) * T <= (int64_t(1) << 26);
+}
+
+}  // namespace lrn
+}  // namespace fm
+
+extern "C" {
+
+size_t fm_pg_workspace_bytes(int32_t K, int32_t S, int32_t H, int32_t A, int32_t N, int32_t T) {
+  if (!fm::lrn::dims_ok(K, S, H, A, N, T)) return 0;
+  return fm::lrn::layout(K, S, H, A, N, T).total;
+}
+
+fm_status fm_policy_gradient(int32_t K, int32_t S, int32_t H, int32_t A, const float* d_w, const float* h_mix,
+                             int32_t agent, const float* d_states, const double* d_rew, int32_t N, int32_t T,
+                             float sigma, uint64_t noise_key, int64_t env_offset, float lambda_kl, float* d_grad,
+                             void* d_workspace, size_t workspace_bytes, hipStream_t stream) {
+  using namespace fm::lrn;
+  if (!dims_ok(K, S, H, A, N, T))
+    return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: sizes out of range (K 1..8, S/H 1..1024, A 1..128, N*T <= 2^26)");
+  if (agent < 0 || agent >= K) return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: agent out of range");
+  if (!d_w || !d_states || !d_rew || !d_grad || !d_workspace)
+    return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: NULL buffer");
+  if (!(sigma > 0.0f) || !std::isfinite(sigma)) return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: sigma must be finite and > 0");
+  if (!(lambda_kl >= 0.0f) || !std::isfinite(lambda_kl))
+    return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: lambda_kl must be finite and >= 0");
+  if (env_offset < 0) return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: env_offset must be >= 0");
+  const Layout L = layout(K, S, H, A, N, T);
+  if (workspace_bytes < L.total || reinterpret_cast<uintptr_t>(d_workspace) % 256)
+    return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: workspace smaller than fm_pg_workspace_bytes or not 256-byte aligned");
+  Mix mix{};
+  for (int k = 0; k < K; ++k) {
+    mix.w[k] = h_mix ? h_mix[k] : 1.0f / K;
+    if (!std::isfinite(mix.w[k])) return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: mix weights must be finite");
+  }
+  unsigned char* ws = static_cast<unsigned char*>(d_workspace);
+  float* mu = reinterpret_cast<float*>(ws + L.mu);
+  float* x1 = reinterpret_cast<float*>(ws + L.x1);
+  float* x2 = reinterpret_cast<float*>(ws + L.x2);
+  float* g3 = reinterpret_cast<float*>(ws + L.g3);
+  double* R = reinterpret_cast<double*>(ws + L.R);
+  float* P = reinterpret_cast<float*>(ws + L.P);
+  float* Pb = reinterpret_cast<float*>(ws + L.Pb);
+  const size_t per = static_cast<size_t>(S) * H + H + static_cast<size_t>(H) * H + H + static_cast<size_t>(H) * A + A;
+  const size_t oW1 = 0, ob1 = static_cast<size_t>(S) * H, oW2 = ob1 + H, ob2 = oW2 + static_cast<size_t>(H) * H,
+               oW3 = ob2 + H, ob3 = oW3 + static_cast<size_t>(H) * A;
+  hipError_t e = hipSuccess;
+  // Forward passes, agent i last so that x1, x2 hold its activations.
+  for (int step = 0; step < K && e == hipSuccess; ++step) {
+    const int k = step < K - 1 ? (step < agent ? step : step + 1) : agent;
+    const float* w = d_w + per * k;
+    e = layer(L, d_states, S, w + oW1, w + ob1, H, x1, stream);
+    if (e == hipSuccess) e = layer(L, x1, H, w + oW2, w + ob2, H, x2, stream);
+    if (e == hipSuccess) e = layer(L, x2, H, w + oW3, w + ob3, A, mu + static_cast<size_t>(k) * L.rows * A, stream);
+  }
+  if (e != hipSuccess) return fm::device_error(e, "fm_policy_gradient (forward)");
+  hipLaunchKernelGGL(returns_kernel, dim3((N + 255) / 256), dim3(256), 0, stream, d_rew, T, N, R);
+  const long nd = static_cast<long>(L.rows) * ((A + 3) / 4);
+  hipLaunchKernelGGL(delta3_kernel, dim3(static_cast<unsigned>((nd + 255) / 256)), dim3(256), 0, stream, mu, K,
+                     agent, mix, L.rows, N, T, A, R, sigma, noise_key, env_offset, lambda_kl, g3);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fm::device_error(e, "fm_policy_gradient (delta)");
+  const float* wi = d_w + per * agent;
+  // Layer 3, then the delta of layer 2 over x2, layer 2, the delta of layer 1 over x1, layer 1.
+  e = weight_grad(L, x2, H, H, g3, A, P, Pb, d_grad + oW3, d_grad + ob3, stream);
+  if (e == hipSuccess) e = back_delta(L, g3, A, wi + oW3, H, x2, stream);
+  if (e == hipSuccess) e = weight_grad(L, x1, H, H, x2, H, P, Pb, d_grad + oW2, d_grad + ob2, stream);
+  if (e == hipSuccess) e = back_delta(L, x2, H, wi + oW2, H, x1, stream);
+  if (e == hipSuccess) e = weight_grad(L, d_states, S, S, x1, H, P, Pb, d_grad + oW1, d_grad + ob1, stream);
+  if (e != hipSuccess) return fm::device_error(e, "fm_policy_gradient (backward)");
+  return FM_OK;
+}
+
+}  // extern "C"

@@ -145,3 +145,10 @@ def test_serve_config_validation(lib):
         setattr(cfg, field, old)
     assert B.fm_serve_request_bytes(0) == 0 and B.fm_serve_request_bytes(1) == 256
     assert B.fm_serve_request_bytes(100) == 6400
+
+
+def test_pg_workspace_validation(lib):
+    assert B.fm_pg_workspace_bytes(3, 211, 256, 30, 2048, 252) > 0
+    for bad in ((0, 211, 256, 30, 2048, 252), (9, 211, 256, 30, 2048, 252), (3, 211, 256, 200, 2048, 252),
+                (3, 211, 256, 30, 0, 252), (3, 211, 2048, 30, 16, 4)):
+        assert B.fm_pg_workspace_bytes(*bad) == 0, bad
