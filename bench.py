@@ -246,6 +246,50 @@ def bench_serving(dev, rate=200.0, n_requests=400):
             "makespan_s": makespan, "capacity": cap, "load_sweep": sweep}
 
 
+def bench_learner(dev, w, reps=5):
+    """The learner consuming a paper-scale rollout: the gradient of eqs. (4)-(5) for agent 0 from
+    the stored [T][N] states and rewards (float32 master weights), per call."""
+    import torch
+    from paper_2501_10709_amd import binding as B
+    from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
+    from workload import make_actor_weights, make_market, pack_actor_weights
+    cfg, acfg = w.env, w.actors
+    N, D, T, S, H, K = cfg.n_envs, cfg.n_stocks, cfg.n_days, cfg.state_dim, acfg.hidden, acfg.n_actors
+    m = make_market(w.market_seed, D, T)
+    packed = pack_actor_weights(make_actor_weights(acfg))
+    env = VecEnv(cfg, m.close, m.ind, device=dev)
+    ens = Ensemble(packed, K, S, H, D, dtype="bf16", max_batch=N, device=dev)
+    s0 = env.reset()
+    out = env.rollout(T, ens=ens, sigma=w.sigma, noise_key=w.noise_key, path="fused", store=("obs", "rew"))
+    states = torch.cat([s0[None], out["obs"][:-1]], 0).contiguous()
+    rew = out["rew"].contiguous()
+    del out
+    wts = torch.as_tensor(packed).to(dev)
+    per = S * H + H + H * H + H + H * D + D
+    grad = torch.empty(per, dtype=torch.float32, device=dev)
+    ws = torch.empty(B.fm_pg_workspace_bytes(K, S, H, D, N, T), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    ts = []
+    for i in range(reps + 2):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        B.fm_policy_gradient(K, S, H, D, wts, 0, states, rew, N, T, w.sigma, w.noise_key, 0, 0.1, grad, ws)
+        b.record(stream)
+        torch.cuda.synchronize()
+        if i >= 2:
+            ts.append(a.elapsed_time(b))
+    ms = float(np.median(ts))
+    rows = N * T
+    flop = rows * (2 * K * (S * H + H * H + H * D) + 2 * (S * H + H * H + H * D) + 2 * (D * H + H * H))
+    tf = flop / (ms / 1e3) / 1e12
+    del ws, states, rew
+    torch.cuda.empty_cache()
+    return {"workload": f"policy gradient (eqs. 4-5, lambda 0.1) for one of {K} actors {S}-{H}-{H}-{D} from a "
+                        f"{N} x {T} rollout", "ms": ms, "samples_per_s": rows / (ms / 1e3),
+            "roofline": {"bound": "fp32", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
+                         "kernel": "gemm_kernel (float32 SIMT tiles)", "flop_per_sample": flop / rows}}
+
+
 def cpu_baseline(w, seconds_hint=True):
     """The oracle (float64 numpy) on the same workload, timed on the host."""
     from oracle.rollout import rollout_closed_loop
@@ -349,6 +393,9 @@ def profile_kernel(args):
     if args.kernel == "batched":
         print(json.dumps(bench_batched(dev, reps=max(1, args.steps))), flush=True)
         return
+    if args.kernel == "learner":
+        print(json.dumps(bench_learner(dev, WORKLOADS[args.workload], reps=max(1, args.steps))), flush=True)
+        return
     if args.kernel == "serve":
         _, srv = crypto_server(dev)
         print(json.dumps(serving_capacity(srv, n_req=max(1, args.steps) * 16)), flush=True)
@@ -382,7 +429,7 @@ def main():
     ap.add_argument("--workload", default="paper", choices=["paper", "precision", "envlarge"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=None, help="timed rollouts of the plain float32 path")
-    ap.add_argument("--kernel", choices=["fused", "driven", "plain", "copy", "batched", "serve"], default=None,
+    ap.add_argument("--kernel", choices=["fused", "driven", "plain", "copy", "batched", "serve", "learner"], default=None,
                     help="profiling mode: one warm-up and --steps launches of one kernel, nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -491,6 +538,7 @@ def main():
     }
     rec["batched_uneven"] = bench_batched(dev)
     rec["serving"] = bench_serving(dev)
+    rec["learner"] = bench_learner(dev, w)
     copy = hbm_copy_gbs(dev)
     rec["env_roofline"]["hbm_copy_GBs"] = copy
     rec["env_roofline"]["frac_of_copy"] = achieved_gbs / copy
