@@ -4,9 +4,9 @@
 // Pipeline, all on the caller's stream: the K actors' forward passes over the T*N sample rows
 // (agent i last, so its layer activations stay in the workspace); the returns R_n; per row the
 // derivative of the objective with respect to mu_i, times tanh' (the layer-3 delta); then back
-// through layers 3, 2, 1: each weight gradient X^T G is a reduction over the rows, split over
-// row chunks into float32 partial products and summed in float64 in chunk order; each delta of
-// the layer below is (G W^T) * (1 - X^2), written over the activation it masks.
+// through layers 3, 2, 1: each weight and bias gradient [X | 1]^T G is a reduction over the rows,
+// split over row chunks into float32 partial products and summed in float64 in chunk order; each
+// delta of the layer below is (G W^T) * (1 - X^2), written over the activation it masks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,7 +20,7 @@
 namespace fm {
 namespace lrn {
 
-constexpr int kTile = 64, kBK = 16, kThreads = 256, kMaxK = 8;
+constexpr int kTile = 128, kBK = 8, kThreads = 256, kRT = kTile / 16, kMaxK = 8;
 
 enum Epilogue { kBiasTanh = 0, kMaskTanhGrad = 1, kStore = 2 };
 
@@ -28,8 +28,9 @@ enum Epilogue { kBiasTanh = 0, kMaskTanhGrad = 1, kStore = 2 };
 // A[m * sam + k * sak] and (k, n) of B at B[k * sbk + n * sbn].  blockIdx.z selects a chunk of
 // kc values of k (split reductions) and offsets C by z * scz.  Epilogues: kBiasTanh,
 // C = tanh(acc + bias[n]); kMaskTanhGrad, C = acc * (1 - X^2) with X at the same place as C (C may
-// be X itself: each element is read and written by one thread); kStore, C = acc.  Each thread
-// owns a 4 x 4 block of C and accumulates in float32 in ascending k.
+// be X itself: each element is read and written by one thread); kStore, C = acc.  A workgroup
+// computes a 128 x 128 tile; each thread owns 8 x 8 elements, rows ty + 16r and columns
+// tx + 16c, and accumulates in float32 in ascending k.
 struct Gemm {
   const float* A;
   long sam, sak;
@@ -40,6 +41,7 @@ struct Gemm {
   const float* bias;
   const float* X;
   int M, N, K, kc;
+  int ones_row;  // rows m >= ones_row of A read as 1 (appends the column sums of B: bias gradients)
 };
 
 template <int EPI>
@@ -49,42 +51,43 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(Gemm g) {
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
   const int k_begin = blockIdx.z * g.kc, k_end = min(g.K, k_begin + g.kc);
-  float acc[4][4] = {};
+  // Loads walk the operand's unit-stride index across neighbouring threads (coalesced).
+  const bool a_kfast = g.sak == 1, b_kfast = g.sbk == 1;
+  float acc[kRT][kRT] = {};
   for (int k0 = k_begin; k0 < k_end; k0 += kBK) {
-    // 64 x 16 of A and 16 x 64 of B, four elements per thread each, zero outside the ranges.
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < kTile * kBK / kThreads; ++e) {
       const int i = tid + kThreads * e;
-      const int am = i % kTile, ak = i / kTile;
+      const int am = a_kfast ? i / kBK : i % kTile, ak = a_kfast ? i % kBK : i / kTile;
       const int m = m0 + am, k = k0 + ak;
-      As[ak][am] = (m < g.M && k < k_end) ? g.A[m * g.sam + k * g.sak] : 0.0f;
-      const int bn = i % kTile, bk = i / kTile;
+      As[ak][am] = (m < g.M && k < k_end) ? (m < g.ones_row ? g.A[m * g.sam + k * g.sak] : 1.0f) : 0.0f;
+      const int bn = b_kfast ? i / kBK : i % kTile, bk = b_kfast ? i % kBK : i / kTile;
       const int n = n0 + bn, kb = k0 + bk;
       Bs[bk][bn] = (n < g.N && kb < k_end) ? g.B[kb * g.sbk + n * g.sbn] : 0.0f;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < kBK; ++kk) {
-      float a[4], b[4];
+      float a[kRT], b[kRT];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+      for (int r = 0; r < kRT; ++r) a[r] = As[kk][ty + 16 * r];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
+      for (int c = 0; c < kRT; ++c) b[c] = Bs[kk][tx + 16 * c];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < kRT; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = acc[r][c] + a[r] * b[c];
+        for (int c = 0; c < kRT; ++c) acc[r][c] = acc[r][c] + a[r] * b[c];
     }
     __syncthreads();
   }
   float* C = g.C + blockIdx.z * g.scz;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int m = m0 + ty * 4 + r;
+  for (int r = 0; r < kRT; ++r) {
+    const int m = m0 + ty + 16 * r;
     if (m >= g.M) continue;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int n = n0 + tx * 4 + c;
+    for (int c = 0; c < kRT; ++c) {
+      const int n = n0 + tx + 16 * c;
       if (n >= g.N) continue;
       const long o = m * g.scm + n * g.scn;
       if (EPI == kBiasTanh) {
@@ -145,17 +148,6 @@ __global__ void delta3_kernel(const float* mu, int K, int agent, Mix mix, int ro
   }
 }
 
-// Pb[c][col] = sum of G[r][col] over the rows of chunk c (ascending r).
-__global__ void colsum_kernel(const float* Gm, int rows, int cols, int chunk, int n_chunks, float* Pb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_chunks * cols) return;
-  const int c = i / cols, col = i % cols;
-  const int r0 = c * chunk, r1 = min(rows, r0 + chunk);
-  float acc = 0.0f;
-  for (int r = r0; r < r1; ++r) acc = acc + Gm[static_cast<size_t>(r) * cols + col];
-  Pb[i] = acc;
-}
-
 // out[i] = sum over chunks c (ascending) of P[c][i], in float64, rounded once.
 __global__ void reduce_kernel(const float* P, int len, int n_chunks, float* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -166,7 +158,7 @@ __global__ void reduce_kernel(const float* P, int len, int n_chunks, float* out)
 }
 
 struct Layout {
-  size_t mu, x1, x2, g3, R, P, Pb, total;
+  size_t mu, x1, x2, g3, R, P, total;
   int rows, chunk, n_chunks;
 };
 
@@ -188,11 +180,10 @@ Layout layout(int K, int S, int H, int A, int N, int T) {
   o = al(o + sizeof(float) * rows * A);
   L.R = o;
   o = al(o + sizeof(double) * N);
-  const size_t pmax = std::max({static_cast<size_t>(S) * H, static_cast<size_t>(H) * H, static_cast<size_t>(H) * A});
+  const size_t pmax = std::max({static_cast<size_t>(S + 1) * H, static_cast<size_t>(H + 1) * H,
+                                static_cast<size_t>(H + 1) * A});
   L.P = o;
   o = al(o + sizeof(float) * L.n_chunks * pmax);
-  L.Pb = o;
-  o = al(o + sizeof(float) * L.n_chunks * std::max(H, A));
   L.total = o;
   return L;
 }
@@ -204,10 +195,11 @@ hipError_t gemm(const Gemm& g, int z, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// Weight gradient X^T G: Xr [rows][kin] (row stride ldx), Gr [rows][kout]; result into out
-// [kin][kout], bias gradient (column sums of G) into bout [kout].
+// Weight and bias gradients [X | 1]^T G: Xr [rows][kin] (row stride ldx), Gr [rows][kout]; the
+// result [kin + 1][kout] (weights, then the bias as the row of ones) into out, which is the
+// layout of W followed by b in the master weights.
 hipError_t weight_grad(const Layout& L, const float* Xr, int kin, int ldx, const float* Gr, int kout, float* P,
-                       float* Pb, float* out, float* bout, hipStream_t stream) {
+                       float* out, hipStream_t stream) {
   Gemm g{};
   g.A = Xr;
   g.sam = 1;
@@ -218,19 +210,16 @@ hipError_t weight_grad(const Layout& L, const float* Xr, int kin, int ldx, const
   g.C = P;
   g.scm = kout;
   g.scn = 1;
-  g.scz = static_cast<long>(kin) * kout;
-  g.M = kin;
+  g.scz = static_cast<long>(kin + 1) * kout;
+  g.M = kin + 1;
   g.N = kout;
   g.K = L.rows;
   g.kc = L.chunk;
+  g.ones_row = kin;
   hipError_t e = gemm<kStore>(g, L.n_chunks, stream);
   if (e != hipSuccess) return e;
-  const int len = kin * kout;
+  const int len = (kin + 1) * kout;
   hipLaunchKernelGGL(reduce_kernel, dim3((len + 255) / 256), dim3(256), 0, stream, P, len, L.n_chunks, out);
-  const int nb = L.n_chunks * kout;
-  hipLaunchKernelGGL(colsum_kernel, dim3((nb + 255) / 256), dim3(256), 0, stream, Gr, L.rows, kout, L.chunk,
-                     L.n_chunks, Pb);
-  hipLaunchKernelGGL(reduce_kernel, dim3((kout + 255) / 256), dim3(256), 0, stream, Pb, kout, L.n_chunks, bout);
   return hipGetLastError();
 }
 
@@ -253,6 +242,7 @@ hipError_t back_delta(const Layout& L, const float* Gin, int kout, const float* 
   g.N = kin;
   g.K = kout;
   g.kc = kout;
+  g.ones_row = g.M;
   return gemm<kMaskTanhGrad>(g, 1, stream);
 }
 
@@ -274,6 +264,7 @@ hipError_t layer(const Layout& L, const float* X, int kin, const float* W, const
   g.N = kout;
   g.K = kin;
   g.kc = kin;
+  g.ones_row = g.M;
   return gemm<kBiasTanh>(g, 1, stream);
 }
 
@@ -322,7 +313,6 @@ fm_status fm_policy_gradient(int32_t K, int32_t S, int32_t H, int32_t A, const f
   float* g3 = reinterpret_cast<float*>(ws + L.g3);
   double* R = reinterpret_cast<double*>(ws + L.R);
   float* P = reinterpret_cast<float*>(ws + L.P);
-  float* Pb = reinterpret_cast<float*>(ws + L.Pb);
   const size_t per = static_cast<size_t>(S) * H + H + static_cast<size_t>(H) * H + H + static_cast<size_t>(H) * A + A;
   const size_t oW1 = 0, ob1 = static_cast<size_t>(S) * H, oW2 = ob1 + H, ob2 = oW2 + static_cast<size_t>(H) * H,
                oW3 = ob2 + H, ob3 = oW3 + static_cast<size_t>(H) * A;
@@ -344,11 +334,11 @@ fm_status fm_policy_gradient(int32_t K, int32_t S, int32_t H, int32_t A, const f
   if (e != hipSuccess) return fm::device_error(e, "fm_policy_gradient (delta)");
   const float* wi = d_w + per * agent;
   // Layer 3, then the delta of layer 2 over x2, layer 2, the delta of layer 1 over x1, layer 1.
-  e = weight_grad(L, x2, H, H, g3, A, P, Pb, d_grad + oW3, d_grad + ob3, stream);
+  e = weight_grad(L, x2, H, H, g3, A, P, d_grad + oW3, stream);
   if (e == hipSuccess) e = back_delta(L, g3, A, wi + oW3, H, x2, stream);
-  if (e == hipSuccess) e = weight_grad(L, x1, H, H, x2, H, P, Pb, d_grad + oW2, d_grad + ob2, stream);
+  if (e == hipSuccess) e = weight_grad(L, x1, H, H, x2, H, P, d_grad + oW2, stream);
   if (e == hipSuccess) e = back_delta(L, x2, H, wi + oW2, H, x1, stream);
-  if (e == hipSuccess) e = weight_grad(L, d_states, S, S, x1, H, P, Pb, d_grad + oW1, d_grad + ob1, stream);
+  if (e == hipSuccess) e = weight_grad(L, d_states, S, S, x1, H, P, d_grad + oW1, stream);
   if (e != hipSuccess) return fm::device_error(e, "fm_policy_gradient (backward)");
   return FM_OK;
 }
