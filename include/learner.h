@@ -2,7 +2,8 @@
  * learner.h -- C ABI of the learner that consumes the rollout's samples on the GPU.
  *
  * The training loop of Section 3.2 alternates a simulation phase (the rollout, finrl_mi.h) with
- * a learning phase that estimates the policy gradient from the sampled trajectories, eq. (4):
+ * a learning phase; Section 4.1 estimates the policy gradient from the sampled trajectories by
+ * the Monte-Carlo sum of eq. (4):
  *     grad J(theta_i) = (1/N) sum_n sum_t R(tau_n) grad log pi_i(a_t^n | s_t^n),
  * and Section 5.1 adds an agent-diversity term to agent i's objective, eq. (5): the loss becomes
  * L - lambda sum_{j != i} KL(pi_j || pi_i).  fm_policy_gradient returns the gradient of

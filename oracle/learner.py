@@ -1,7 +1,7 @@
 """Oracle for the learner that consumes the rollout's samples (TEST INFRASTRUCTURE ONLY; see the
 package docstring).
 
-Section 3.2 writes the policy gradient as the Monte-Carlo estimate of eq. (4),
+Section 4.1 writes the policy gradient as the Monte-Carlo estimate of eq. (4),
     grad J = (1/N) sum_n sum_t R(tau_n) grad log pi(a_t^n | s_t^n),
 and Section 5.1 adds to an agent's objective the diversity term of eq. (5), lambda sum_{j != i}
 KL(pi_j || pi_i) (the loss L_new = L - lambda sum KL, so the objective to ascend is J + lambda sum KL).
