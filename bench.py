@@ -287,7 +287,7 @@ def bench_learner(dev, w, reps=5):
     return {"workload": f"policy gradient (eqs. 4-5, lambda 0.1) for one of {K} actors {S}-{H}-{H}-{D} from a "
                         f"{N} x {T} rollout", "ms": ms, "samples_per_s": rows / (ms / 1e3),
             "roofline": {"bound": "fp32", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
-                         "kernel": "gemm_kernel (float32 SIMT tiles)", "flop_per_sample": flop / rows}}
+                         "kernel": "gemm_kernel (float32 MFMA 16x16x4 tiles)", "flop_per_sample": flop / rows}}
 
 
 def cpu_baseline(w, seconds_hint=True):

@@ -15,12 +15,13 @@
 
 #include "../../include/learner.h"
 #include "device_common.h"
+#include "mlp_device.h"
 #include "status.h"
 
 namespace fm {
 namespace lrn {
 
-constexpr int kTile = 128, kBK = 8, kThreads = 256, kRT = kTile / 16, kMaxK = 8;
+constexpr int kTile = 128, kBK = 8, kThreads = 256, kMaxK = 8;
 
 enum Epilogue { kBiasTanh = 0, kMaskTanhGrad = 1, kStore = 2 };
 
@@ -29,8 +30,8 @@ enum Epilogue { kBiasTanh = 0, kMaskTanhGrad = 1, kStore = 2 };
 // kc values of k (split reductions) and offsets C by z * scz.  Epilogues: kBiasTanh,
 // C = tanh(acc + bias[n]); kMaskTanhGrad, C = acc * (1 - X^2) with X at the same place as C (C may
 // be X itself: each element is read and written by one thread); kStore, C = acc.  A workgroup
-// computes a 128 x 128 tile; each thread owns 8 x 8 elements, rows ty + 16r and columns
-// tx + 16c, and accumulates in float32 in ascending k.
+// computes a 128 x 128 tile, each of its four wavefronts a 64 x 64 quarter as 4 x 4 blocks of
+// float32 MFMAs (16 x 16 x 4), accumulating over k in ascending order of 4-element steps.
 struct Gemm {
   const float* A;
   long sam, sak;
@@ -46,14 +47,20 @@ struct Gemm {
 
 template <int EPI>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(Gemm g) {
-  __shared__ float As[kBK][kTile + 4];
-  __shared__ float Bs[kBK][kTile + 4];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  // Rows padded to 144 floats: the two k rows a half-wavefront reads sit 16 banks apart.
+  __shared__ float As[kBK][kTile + 16];
+  __shared__ float Bs[kBK][kTile + 16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;  // this wavefront's 64 x 64 quarter
   const int k_begin = blockIdx.z * g.kc, k_end = min(g.K, k_begin + g.kc);
   // Loads walk the operand's unit-stride index across neighbouring threads (coalesced).
   const bool a_kfast = g.sak == 1, b_kfast = g.sbk == 1;
-  float acc[kRT][kRT] = {};
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = k_begin; k0 < k_end; k0 += kBK) {
 #pragma unroll
     for (int e = 0; e < kTile * kBK / kThreads; ++e) {
@@ -66,40 +73,45 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(Gemm g) {
       Bs[bk][bn] = (n < g.N && kb < k_end) ? g.B[kb * g.sbk + n * g.sbn] : 0.0f;
     }
     __syncthreads();
+    // v_mfma_f32_16x16x4_f32: lane l supplies A[row l%16][k l/16] and B[k l/16][col l%16].
 #pragma unroll
-    for (int kk = 0; kk < kBK; ++kk) {
-      float a[kRT], b[kRT];
+    for (int kq = 0; kq < kBK; kq += 4) {
+      float a[4], b[4];
 #pragma unroll
-      for (int r = 0; r < kRT; ++r) a[r] = As[kk][ty + 16 * r];
+      for (int i = 0; i < 4; ++i) a[i] = As[kq + (lane >> 4)][wm + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int c = 0; c < kRT; ++c) b[c] = Bs[kk][tx + 16 * c];
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kq + (lane >> 4)][wn + 16 * j + (lane & 15)];
 #pragma unroll
-      for (int r = 0; r < kRT; ++r)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int c = 0; c < kRT; ++c) acc[r][c] = acc[r][c] + a[r] * b[c];
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
+  // Lane l holds column l%16 and rows 4(l/16)..4(l/16)+3 of each 16 x 16 block.
   float* C = g.C + blockIdx.z * g.scz;
 #pragma unroll
-  for (int r = 0; r < kRT; ++r) {
-    const int m = m0 + ty + 16 * r;
-    if (m >= g.M) continue;
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int c = 0; c < kRT; ++c) {
-      const int n = n0 + tx + 16 * c;
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + wn + 16 * j + (lane & 15);
       if (n >= g.N) continue;
-      const long o = m * g.scm + n * g.scn;
-      if (EPI == kBiasTanh) {
-        C[o] = tanhf(acc[r][c] + g.bias[n]);
-      } else if (EPI == kMaskTanhGrad) {
-        const float x = g.X[o];
-        C[o] = acc[r][c] * (1.0f - x * x);
-      } else {
-        C[o] = acc[r][c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        if (m >= g.M) continue;
+        const long o = m * g.scm + n * g.scn;
+        const float v = acc[i][j][r];
+        if (EPI == kBiasTanh) {
+          C[o] = tanhf(v + g.bias[n]);
+        } else if (EPI == kMaskTanhGrad) {
+          const float x = g.X[o];
+          C[o] = v * (1.0f - x * x);
+        } else {
+          C[o] = v;
+        }
       }
     }
-  }
 }
 
 // R_n = sum_t r[t][n] in ascending t.
