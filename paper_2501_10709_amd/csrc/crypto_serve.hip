@@ -79,22 +79,6 @@ struct ChunkArgs {
   int chunk;
 };
 
-__host__ __device__ constexpr size_t a16(size_t x) { return (x + 15) / 16 * 16; }
-
-template <int R, int K>
-struct Lds {
-  static constexpr size_t w1 = 0;                                    // s16x4 [K][4][2][64]
-  static constexpr size_t w3 = w1 + size_t(K) * kNW * 2 * 64 * 8;    // bf16x8 [K][4][64]
-  static constexpr size_t b1 = w3 + size_t(K) * kNW * 64 * 16;       // f32 [K][128]
-  static constexpr size_t b2 = b1 + size_t(K) * kH * 4;
-  static constexpr size_t b3 = b2 + size_t(K) * kH * 4;              // f32 [K][4]
-  static constexpr size_t mix = b3 + size_t(K) * 16;                 // f32 [K]
-  static constexpr size_t x = a16(mix + size_t(K) * 4);              // bf16 [R][16][16]
-  static constexpr size_t h = x + size_t(R) * 16 * kF * 2;           // bf16x8 [K][4][R][64]
-  static constexpr size_t part = h + size_t(K) * kNW * R * 64 * 16;  // floatx4 [4][K][R][16]
-  static constexpr size_t total = part + size_t(kNW) * K * R * 16 * 16;
-};
-
 typedef __attribute__((ext_vector_type(8))) short s16x8;
 
 // relu(x) rounded to bfloat16 for eight accumulators.  Rounding keeps the sign, so the ReLU is
@@ -413,7 +397,6 @@ __global__ void zero_counter(int* c) {
 
 template <int R, int K>
 hipError_t launch(const ChunkArgs& a, int grid, hipStream_t stream) {
-  static_assert(Lds<R, K>::total <= 160 * 1024 - 256, "LDS budget");
   zero_counter<<<1, 64, 0, stream>>>(a.counter);
   crypto_chunk_kernel<R, K><<<grid, kNT, 0, stream>>>(a);
   return hipGetLastError();

@@ -127,7 +127,7 @@ def serve_poisson(server: CryptoServer, requests, time_scale: float = 1.0):
         for rid in ids:
             done_at[rid_of[rid]] = t
             server.requests.pop(rid, None)
-        if active == 0 and queued == 0 and i < n and len(done_at) + 0 < n:
+        if active == 0 and queued == 0 and i < n:
             wait = arrival[i] - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(wait)
