@@ -343,8 +343,9 @@ struct BuyChunk {
 // all buys, in ascending stock order.  A buy fills whole when its debit fits the cash and not at
 // all when one share does not (selects); otherwise the partial fill decides (the one divergent
 // branch).  c1s, rc1s: the day's one-share debits and their reciprocals (shared by all
-// environments).  CH stocks per register chunk (DP is a multiple of CH).
-template <int CH = kChunk>
+// environments).  CH stocks per register chunk (DP is a multiple of CH).  With PF the next
+// chunk's terms are read while the current one is consumed; without, after it (fewer registers).
+template <int CH = kChunk, bool PF = true>
 __device__ __forceinline__ void chain_serial(double& cash, const double* __restrict__ pro,
                                              const double* __restrict__ deb, const double* __restrict__ c1s,
                                              const double* __restrict__ rc1s, const int* __restrict__ qd,
@@ -358,7 +359,7 @@ __device__ __forceinline__ void chain_serial(double& cash, const double* __restr
   for (int d0 = 0; d0 < DP; d0 += CH) {
     BuyChunk<CH> nxt;
     const int dn = d0 + CH < DP ? d0 + CH : d0;
-    nxt.load(deb + dn, c1s + dn, rc1s + dn, qd + dn, px + dn);
+    if constexpr (PF) nxt.load(deb + dn, c1s + dn, rc1s + dn, qd + dn, px + dn);
     int k[CH];
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
@@ -373,7 +374,10 @@ __device__ __forceinline__ void chain_serial(double& cash, const double* __restr
 #pragma unroll
     for (int j = 0; j < CH / 4; ++j)
       reinterpret_cast<int4*>(kq + d0)[j] = int4{k[4 * j], k[4 * j + 1], k[4 * j + 2], k[4 * j + 3]};
-    cur = nxt;
+    if constexpr (PF)
+      cur = nxt;
+    else
+      cur.load(deb + dn, c1s + dn, rc1s + dn, qd + dn, px + dn);
   }
 }
 

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(3 * kWave, OCC) void env_tile_kernel(EnvConst C, En
 
   const int n_iter = trades(MODE) ? A.n_steps : 1;
   const int total = n_mkt + ((MODE == kGiven) ? MD : 0);  // fetched floats per step
-  const int staged = min(total, (OCC >= 3 ? kStage / 2 : kStage) * kWave);
+  const int staged = min(total, (OCC >= 4 ? kStage / 4 : OCC >= 3 ? kStage / 2 : kStage) * kWave);
 
   // Fetch wavefront.  Flat index i of step it's inputs: close[t] (D; zeros when not trading),
   // close[tn] (D), ind[tn] (I*D), then, driven, the tile's actions (M*D) -- which is also the
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(3 * kWave, OCC) void env_tile_kernel(EnvConst C, En
     if (i < n_mkt) return C.ind + static_cast<size_t>(tn) * C.I * D + (i - 2 * D);
     return A.act + (static_cast<size_t>(it) * N + n0) * D + (i - n_mkt);
   };
-  constexpr int NSTAGE = OCC >= 3 ? kStage / 2 : kStage;
+  constexpr int NSTAGE = OCC >= 4 ? kStage / 4 : OCC >= 3 ? kStage / 2 : kStage;
   float stage[NSTAGE];
   auto fetch_issue = [&](int it) {
 #pragma unroll
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(3 * kWave, OCC) void env_tile_kernel(EnvConst C, En
           chain_pairs_a(CL, Z, M, lane, kWave, C.hmax_f, C.one_m, C.one_p);
           wave_lds_sync();
           if (active)
-            chain_serial<OCC == 1 ? 8 : 4>(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.c1, CL.rc1, CL.qd + lane * Z.RI, CL.px,
+            chain_serial<OCC == 1 ? 8 : 4, (OCC < 4)>(cash, CL.pro + lane * Z.RD, CL.deb + lane * Z.RD, CL.c1, CL.rc1, CL.qd + lane * Z.RI, CL.px,
                          CL.kq + lane * Z.RI, Z.DP, C.one_p);
           wave_lds_sync();
           chain_pairs_c(CL, Z, M, lane, kWave, C.hold_scale);
@@ -291,6 +291,7 @@ hipError_t dispatch_tile(const EnvConst& C, const EnvState& st, StepArgs A, hipS
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 0;
+  if (cus > 0 && grid > 3 * cus && 4 * lds <= kMaxLds) return launch_tile<MODE, 4>(C, st, A, lds, grid, stream);
   if (cus > 0 && grid > 2 * cus && 3 * lds <= kMaxLds) return launch_tile<MODE, 3>(C, st, A, lds, grid, stream);
   if (cus > 0 && grid > cus && 2 * lds <= kMaxLds) return launch_tile<MODE, 2>(C, st, A, lds, grid, stream);
   return launch_tile<MODE, 1>(C, st, A, lds, grid, stream);
