@@ -151,3 +151,28 @@ def test_request_validation(market):
     with pytest.raises(B.FmError):
         srv.submit(60, 10, 100, 1, 0)         # larger than the pool
     srv.close()
+
+
+def test_poisson_serving_loop_completes_every_request(market):
+    """The continuous-batching loop (submissions at Poisson arrival times, steps, completions):
+    every request completes once, with latencies at least its own compute time and results equal
+    to running it alone."""
+    from paper_2501_10709_amd.serve import serve_poisson
+    from workload.crypto import poisson_requests
+    reqs = poisson_requests(8, 12, 2000.0, market.n_ticks, n_range=(1, 200), horizon_range=(50, 400))
+    srv, _ = _server(market, chunk=64)
+    lat, makespan, steps = serve_poisson(srv, reqs)
+    srv.close()
+    assert lat.shape == (12,) and (lat > 0).all() and makespan > 0
+    assert steps == sum(q.n_envs * q.horizon for q in reqs)
+    q = reqs[3]
+    srv1, _ = _server(market, chunk=64)
+    a = srv1.submit(q.n_envs, q.horizon, q.start_tick, q.stride, q.key)
+    srv1.run_all()
+    alone = srv1.result(a)[0]
+    srv1.close()
+    srv2, _ = _server(market, chunk=64)
+    ids = [srv2.submit(r.n_envs, r.horizon, r.start_tick, r.stride, r.key) for r in reqs[:6]]
+    srv2.run_all()
+    assert srv2.result(ids[3])[0].tobytes() == alone.tobytes()
+    srv2.close()
