@@ -33,12 +33,13 @@ def _server(market, K=5, rule=0, eps=0.05, rows=64, chunk=100, **kw):
     return srv, actors
 
 
-def _check_request(market, actors, q, res, act, prob, rule, eps):
+def _check_request(market, actors, q, res, act, prob, rule, eps, fee=2e-4):
     K = len(actors)
     dev = device_weights(actors, "bf16")
     obs = []
     st, probs, chosen, greedy, explored, _ = oc.rollout(
-        market, dev, q["n"], q["T"], q["start"], q["stride"], q["key"], eps, mode=rule, actions=act, obs_out=obs)
+        market, dev, q["n"], q["T"], q["start"], q["stride"], q["key"], eps, fee=fee, mode=rule, actions=act,
+        obs_out=obs)
     assert (res["ticks"] == q["T"]).all()
     assert (res["position"] == st["pos"]).all()
     assert (res["trades"] == st["trades"]).all()
@@ -84,6 +85,27 @@ def test_parity_against_oracle(market, rule, K, rows):
         print(f"rule {rule} K {K} rows {rows} request n={q['n']} T={q['T']}", flush=True)
         frac = _check_request(market, actors, q, res, act.astype(np.int64), prob, rule, eps)
         assert frac > 0.3
+    srv.close()
+
+
+@pytest.mark.parametrize("eps,fee,rule,K", [(1.0, 2e-4, 0, 3), (0.0, 0.0, 1, 5)])
+def test_degenerate_requests(market, eps, fee, rule, K):
+    """Every action explored (eps = 1) or none (eps = 0, with no fee); a one-tick horizon; tiles
+    filled exactly and by one environment more; a request whose last mark is the table's last tick."""
+    n_ticks = len(market.mid)
+    edge = dict(n=3, T=40, stride=5, key=33)
+    edge["start"] = n_ticks - 1 - edge["T"] - edge["stride"] * (edge["n"] - 1)
+    cases = [dict(n=64, T=1, start=0, stride=0, key=31), dict(n=65, T=130, start=64, stride=1, key=32), edge]
+    srv, actors = _server(market, K=K, rule=rule, eps=eps, rows=64, chunk=64, fee=fee)
+    ids = [srv.submit(q["n"], q["T"], q["start"], q["stride"], q["key"], store_act=True, store_prob=True)
+           for q in cases]
+    assert sorted(srv.run_all()) == sorted(ids)
+    for rid, q in zip(ids, cases):
+        res, act, prob = srv.result(rid)
+        print(f"eps {eps} fee {fee} rule {rule} K {K} request n={q['n']} T={q['T']} start={q['start']}", flush=True)
+        _check_request(market, actors, q, res, act.astype(np.int64), prob, rule, eps, fee=fee)
+        # The rewards telescope: the final value is cash0 plus their sum, up to rounding.
+        assert np.allclose(res["value"] - 1e5, res["sum_r"], rtol=0, atol=1e-6)
     srv.close()
 
 

@@ -113,3 +113,50 @@ def test_episode_return_statistics_reported():
           f"|diff| = {diff / spread:.2f} standard errors; per-env max |diff| "
           f"{np.abs(gpu_ret - ora_ret).max():.3g}", flush=True)
     assert np.isfinite(gpu_ret).all()
+
+
+@pytest.mark.timeout(400)
+def test_policy_gradient_paper_scale():
+    """The learner at the benchmark's size and launch configuration (N = 2048, T = 252, three
+    actors 211-256-256-30, lambda 0.1, agent 0, from a bfloat16 fused rollout) against the
+    oracle's float64 gradient over all 516,096 rows: every entry within 2e-3 of the largest
+    entry of that parameter's gradient.  The oracle takes about a minute here."""
+    import torch
+    from oracle import learner as OL
+    from paper_2501_10709_amd import binding as B
+    from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
+    from workload import make_actor_weights, pack_actor_weights
+    w = PAPER_SCALE
+    cfg, acfg = w.env, w.actors
+    N, D, T, S, H, K = cfg.n_envs, cfg.n_stocks, cfg.n_days, cfg.state_dim, acfg.hidden, acfg.n_actors
+    dev = cuda()
+    m = make_market(w.market_seed, D, T)
+    actors = make_actor_weights(acfg)
+    packed = pack_actor_weights(actors)
+    env = VecEnv(cfg, m.close, m.ind, device=dev)
+    ens = Ensemble(packed, K, S, H, D, dtype="bf16", max_batch=N, device=dev)
+    s0 = env.reset()
+    out = env.rollout(T, ens=ens, sigma=w.sigma, noise_key=w.noise_key, path="fused", store=("obs", "rew"))
+    states = torch.cat([s0[None], out["obs"][:-1]], 0).contiguous()
+    rew = out["rew"].contiguous()
+    per = S * H + H + H * H + H + H * D + D
+    grad = torch.empty(per, dtype=torch.float32, device=dev)
+    ws = torch.empty(B.fm_pg_workspace_bytes(K, S, H, D, N, T), dtype=torch.uint8, device=dev)
+    print(f"policy gradient paper scale N {N} T {T} H {H}", flush=True)
+    B.fm_policy_gradient(K, S, H, D, torch.as_tensor(packed).to(dev), 0, states, rew, N, T, w.sigma, w.noise_key, 0,
+                         0.1, grad, ws)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().astype(np.float64)
+    st, rw = _np(states), _np(rew)
+    del out, states, rew, ws, env, ens
+    torch.cuda.empty_cache()
+    want = OL.policy_gradient(actors, 0, st, rw, w.sigma, w.noise_key, 0, 0.1)
+    o = 0
+    for name, shp in (("W1", (S, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (H, D)), ("b3", (D,))):
+        n = int(np.prod(shp))
+        got = g[o:o + n].reshape(shp)
+        o += n
+        scale = np.abs(want[name]).max()
+        err = np.abs(got - want[name]).max()
+        print(f"  {name}: max |err| {err:.3g} of scale {scale:.3g}", flush=True)
+        assert scale > 0 and err <= 2e-3 * scale, (name, err, scale)
