@@ -21,7 +21,7 @@
 namespace fm {
 namespace lrn {
 
-constexpr int kTile = 128, kBK = 8, kThreads = 256, kMaxK = 8;
+constexpr int kTile = 128, kBK = 16, kThreads = 256, kMaxK = 8;
 
 enum Epilogue { kBiasTanh = 0, kMaskTanhGrad = 1, kStore = 2 };
 
@@ -54,25 +54,52 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(Gemm g) {
   const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;  // this wavefront's 64 x 64 quarter
   const int k_begin = blockIdx.z * g.kc, k_end = min(g.K, k_begin + g.kc);
-  // Loads walk the operand's unit-stride index across neighbouring threads (coalesced).
+  // Loads walk the operand's unit-stride index across neighbouring threads (coalesced).  Thread
+  // tid moves elements e = 0..kPer-1 of each operand's k-block: A element (am, ak), B (bk, bn).
+  constexpr int kPer = kTile * kBK / kThreads;
   const bool a_kfast = g.sak == 1, b_kfast = g.sbk == 1;
+  const int am0 = a_kfast ? tid / kBK : tid % kTile, ak0 = a_kfast ? tid % kBK : tid / kTile;
+  const int bn0 = b_kfast ? tid / kBK : tid % kTile, bk0 = b_kfast ? tid % kBK : tid / kTile;
+  constexpr int kStepFast = kThreads / kBK, kStepSlow = kThreads / kTile;
+  auto a_at = [&](int e, int& am, int& ak) {
+    am = a_kfast ? am0 + kStepFast * e : am0;
+    ak = a_kfast ? ak0 : ak0 + kStepSlow * e;
+  };
+  auto b_at = [&](int e, int& bk, int& bn) {
+    bn = b_kfast ? bn0 + kStepFast * e : bn0;
+    bk = b_kfast ? bk0 : bk0 + kStepSlow * e;
+  };
+  // The next k-block is read into registers while the current one is multiplied.
+  float ra[kPer], rb[kPer];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      int am, ak, bk, bn;
+      a_at(e, am, ak);
+      b_at(e, bk, bn);
+      const int m = m0 + am, k = k0 + ak;
+      ra[e] = (m < g.M && k < k_end) ? (m < g.ones_row ? g.A[m * g.sam + k * g.sak] : 1.0f) : 0.0f;
+      const int n = n0 + bn, kb = k0 + bk;
+      rb[e] = (n < g.N && kb < k_end) ? g.B[kb * g.sbk + n * g.sbn] : 0.0f;
+    }
+  };
   floatx4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  if (k_begin < k_end) fetch(k_begin);
   for (int k0 = k_begin; k0 < k_end; k0 += kBK) {
 #pragma unroll
-    for (int e = 0; e < kTile * kBK / kThreads; ++e) {
-      const int i = tid + kThreads * e;
-      const int am = a_kfast ? i / kBK : i % kTile, ak = a_kfast ? i % kBK : i / kTile;
-      const int m = m0 + am, k = k0 + ak;
-      As[ak][am] = (m < g.M && k < k_end) ? (m < g.ones_row ? g.A[m * g.sam + k * g.sak] : 1.0f) : 0.0f;
-      const int bn = b_kfast ? i / kBK : i % kTile, bk = b_kfast ? i % kBK : i / kTile;
-      const int n = n0 + bn, kb = k0 + bk;
-      Bs[bk][bn] = (n < g.N && kb < k_end) ? g.B[kb * g.sbk + n * g.sbn] : 0.0f;
+    for (int e = 0; e < kPer; ++e) {
+      int am, ak, bk, bn;
+      a_at(e, am, ak);
+      b_at(e, bk, bn);
+      As[ak][am] = ra[e];
+      Bs[bk][bn] = rb[e];
     }
     __syncthreads();
+    if (k0 + kBK < k_end) fetch(k0 + kBK);
     // v_mfma_f32_16x16x4_f32: lane l supplies A[row l%16][k l/16] and B[k l/16][col l%16].
 #pragma unroll
     for (int kq = 0; kq < kBK; kq += 4) {
