@@ -30,8 +30,10 @@ enum Epilogue { kBiasTanh = 0, kMaskTanhGrad = 1, kStore = 2 };
 // kc values of k (split reductions) and offsets C by z * scz.  Epilogues: kBiasTanh,
 // C = tanh(acc + bias[n]); kMaskTanhGrad, C = acc * (1 - X^2) with X at the same place as C (C may
 // be X itself: each element is read and written by one thread); kStore, C = acc.  A workgroup
-// computes a 128 x 128 tile, each of its four wavefronts a 64 x 64 quarter as 4 x 4 blocks of
-// float32 MFMAs (16 x 16 x 4), accumulating over k in ascending order of 4-element steps.
+// computes a 128 x TN tile: for TN = 128 each of its four wavefronts a 64 x 64 quarter, for
+// TN = 32 (outputs at most 32 wide) a 32 x 32 quarter of the rows, as blocks of float32 MFMAs
+// (16 x 16 x 4), accumulating over k in ascending order of 4-element steps.  The tile width
+// changes only which threads compute an element, not its arithmetic.
 struct Gemm {
   const float* A;
   long sam, sak;
@@ -45,57 +47,68 @@ struct Gemm {
   int ones_row;  // rows m >= ones_row of A read as 1 (appends the column sums of B: bias gradients)
 };
 
-template <int EPI>
+template <int EPI, int TN>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(Gemm g) {
-  // Rows padded to 144 floats: the two k rows a half-wavefront reads sit 16 banks apart.
+  static_assert(TN == kTile || TN == 32, "tiles 128 x 128 or 128 x 32");
+  // Wavefronts along n (WN) and m; each owns BI x BJ blocks of 16 x 16.
+  constexpr int WN = TN == kTile ? 2 : 1, BI = kTile / (4 / WN) / 16, BJ = TN / WN / 16;
+  // Rows padded by 16 floats: the two k rows a half-wavefront reads sit 16 banks apart.
   __shared__ float As[kBK][kTile + 16];
-  __shared__ float Bs[kBK][kTile + 16];
+  __shared__ float Bs[kBK][TN + 16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;  // this wavefront's 64 x 64 quarter
+  const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * TN;
+  const int wm = (wave / WN) * 16 * BI, wn = (wave % WN) * 16 * BJ;  // this wavefront's quarter
   const int k_begin = blockIdx.z * g.kc, k_end = min(g.K, k_begin + g.kc);
   // Loads walk the operand's unit-stride index across neighbouring threads (coalesced).  Thread
-  // tid moves elements e = 0..kPer-1 of each operand's k-block: A element (am, ak), B (bk, bn).
-  constexpr int kPer = kTile * kBK / kThreads;
+  // tid moves elements e = 0..kPerA-1 of A's k-block (am, ak) and 0..kPerB-1 of B's (bk, bn).
+  constexpr int kPerA = kTile * kBK / kThreads, kPerB = TN * kBK / kThreads;
   const bool a_kfast = g.sak == 1, b_kfast = g.sbk == 1;
   const int am0 = a_kfast ? tid / kBK : tid % kTile, ak0 = a_kfast ? tid % kBK : tid / kTile;
-  const int bn0 = b_kfast ? tid / kBK : tid % kTile, bk0 = b_kfast ? tid % kBK : tid / kTile;
-  constexpr int kStepFast = kThreads / kBK, kStepSlow = kThreads / kTile;
+  const int bn0 = b_kfast ? tid / kBK : tid % TN, bk0 = b_kfast ? tid % kBK : tid / TN;
+  constexpr int kStepFast = kThreads / kBK, kStepSlowA = kThreads / kTile, kStepSlowB = kThreads / TN;
   auto a_at = [&](int e, int& am, int& ak) {
     am = a_kfast ? am0 + kStepFast * e : am0;
-    ak = a_kfast ? ak0 : ak0 + kStepSlow * e;
+    ak = a_kfast ? ak0 : ak0 + kStepSlowA * e;
   };
   auto b_at = [&](int e, int& bk, int& bn) {
     bn = b_kfast ? bn0 + kStepFast * e : bn0;
-    bk = b_kfast ? bk0 : bk0 + kStepSlow * e;
+    bk = b_kfast ? bk0 : bk0 + kStepSlowB * e;
   };
   // The next k-block is read into registers while the current one is multiplied.
-  float ra[kPer], rb[kPer];
+  float ra[kPerA], rb[kPerB];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      int am, ak, bk, bn;
+    for (int e = 0; e < kPerA; ++e) {
+      int am, ak;
       a_at(e, am, ak);
-      b_at(e, bk, bn);
       const int m = m0 + am, k = k0 + ak;
       ra[e] = (m < g.M && k < k_end) ? (m < g.ones_row ? g.A[m * g.sam + k * g.sak] : 1.0f) : 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < kPerB; ++e) {
+      int bk, bn;
+      b_at(e, bk, bn);
       const int n = n0 + bn, kb = k0 + bk;
       rb[e] = (n < g.N && kb < k_end) ? g.B[kb * g.sbk + n * g.sbn] : 0.0f;
     }
   };
-  floatx4 acc[4][4];
+  floatx4 acc[BI][BJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < BJ; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
   if (k_begin < k_end) fetch(k_begin);
   for (int k0 = k_begin; k0 < k_end; k0 += kBK) {
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      int am, ak, bk, bn;
+    for (int e = 0; e < kPerA; ++e) {
+      int am, ak;
       a_at(e, am, ak);
-      b_at(e, bk, bn);
       As[ak][am] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < kPerB; ++e) {
+      int bk, bn;
+      b_at(e, bk, bn);
       Bs[bk][bn] = rb[e];
     }
     __syncthreads();
@@ -103,24 +116,24 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(Gemm g) {
     // v_mfma_f32_16x16x4_f32: lane l supplies A[row l%16][k l/16] and B[k l/16][col l%16].
 #pragma unroll
     for (int kq = 0; kq < kBK; kq += 4) {
-      float a[4], b[4];
+      float a[BI], b[BJ];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kq + (lane >> 4)][wm + 16 * i + (lane & 15)];
+      for (int i = 0; i < BI; ++i) a[i] = As[kq + (lane >> 4)][wm + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kq + (lane >> 4)][wn + 16 * j + (lane & 15)];
+      for (int j = 0; j < BJ; ++j) b[j] = Bs[kq + (lane >> 4)][wn + 16 * j + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < BJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
   // Lane l holds column l%16 and rows 4(l/16)..4(l/16)+3 of each 16 x 16 block.
   float* C = g.C + blockIdx.z * g.scz;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < BJ; ++j) {
       const int n = n0 + wn + 16 * j + (lane & 15);
       if (n >= g.N) continue;
 #pragma unroll
@@ -227,10 +240,16 @@ Layout layout(int K, int S, int H, int A, int N, int T) {
   return L;
 }
 
+// Outputs at most 32 wide (the action layer) take 128 x 32 tiles instead of padding to 128.
 template <int EPI>
 hipError_t gemm(const Gemm& g, int z, hipStream_t stream) {
-  const dim3 grid((g.M + kTile - 1) / kTile, (g.N + kTile - 1) / kTile, z);
-  hipLaunchKernelGGL(gemm_kernel<EPI>, grid, dim3(kThreads), 0, stream, g);
+  if (g.N <= 32) {
+    const dim3 grid((g.M + kTile - 1) / kTile, 1, z);
+    hipLaunchKernelGGL((gemm_kernel<EPI, 32>), grid, dim3(kThreads), 0, stream, g);
+  } else {
+    const dim3 grid((g.M + kTile - 1) / kTile, (g.N + kTile - 1) / kTile, z);
+    hipLaunchKernelGGL((gemm_kernel<EPI, kTile>), grid, dim3(kThreads), 0, stream, g);
+  }
   return hipGetLastError();
 }
 
