@@ -14,7 +14,9 @@ def _close(got, want):
     both_nan = np.isnan(got) & np.isnan(want)
     same_inf = np.isinf(got) & np.isinf(want) & (np.sign(got) == np.sign(want))
     fin = np.isfinite(want)
-    ok = both_nan | same_inf | (fin & (np.abs(got - want) <= 1e-10 * np.maximum(np.abs(want), 1e-300)))
+    with np.errstate(invalid="ignore"):  # inf - inf where both are infinite; judged by same_inf
+        near = np.abs(got - want) <= 1e-10 * np.maximum(np.abs(want), 1e-300)
+    ok = both_nan | same_inf | (fin & near)
     return ok
 
 
