@@ -159,6 +159,8 @@ __global__ void returns_kernel(const double* rew, int T, int N, double* R) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   double acc = 0.0;
+  // Unrolled so that the loads issue ahead of the additions, which stay in ascending t.
+#pragma unroll 8
   for (int t = 0; t < T; ++t) acc = acc + rew[static_cast<size_t>(t) * N + n];
   R[n] = acc;
 }
@@ -205,6 +207,7 @@ __global__ void reduce_kernel(const float* P, int len, int n_chunks, float* out)
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= len) return;
   double acc = 0.0;
+#pragma unroll 8
   for (int c = 0; c < n_chunks; ++c) acc = acc + static_cast<double>(P[static_cast<size_t>(c) * len + i]);
   out[i] = static_cast<float>(acc);
 }
