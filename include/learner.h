@@ -13,8 +13,9 @@
  * a = abar(s) + sigma eps the action the rollout sampled before clipping: abar = sum_k w_k mu_k(s)
  * and eps regenerated from the rollout's noise generator (key, env_offset + n, day t).  For equal
  * sigma, KL(pi_j || pi_i) = |mu_j - mu_i|^2 / (2 sigma^2).  Arithmetic is float32 with
- * fixed summation orders (the result is reproducible bit for bit); the per-row terms are summed
- * over rows in float64 before the result is rounded to float32.
+ * fixed summation orders (the result is reproducible bit for bit; tanh is evaluated from one
+ * exponential and one reciprocal, absolute error below 1e-6); the per-row terms are summed over
+ * rows in float64 before the result is rounded to float32.
  *
  * Conventions follow finrl_mi.h (caller-owned d_* buffers, no device allocation, validation
  * before anything is enqueued, FM_ERR_* statuses with fm_last_error()).

@@ -28,7 +28,7 @@ enum Epilogue { kBiasTanh = 0, kMaskTanhGrad = 1, kStore = 2 };
 // C(m, n) = sum_k A(m, k) B(k, n) over k in the block's range, with element (m, k) of A at
 // A[m * sam + k * sak] and (k, n) of B at B[k * sbk + n * sbn].  blockIdx.z selects a chunk of
 // kc values of k (split reductions) and offsets C by z * scz.  Epilogues: kBiasTanh,
-// C = tanh(acc + bias[n]); kMaskTanhGrad, C = acc * (1 - X^2) with X at the same place as C (C may
+// C = tanh(acc + bias[n]) (from one exp2 and one reciprocal, absolute error below 1e-6); kMaskTanhGrad, C = acc * (1 - X^2) with X at the same place as C (C may
 // be X itself: each element is read and written by one thread); kStore, C = acc.  A workgroup
 // computes a 128 x TN tile: for TN = 128 each of its four wavefronts a 64 x 64 quarter, for
 // TN = 32 (outputs at most 32 wide) a 32 x 32 quarter of the rows, as blocks of float32 MFMAs
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(Gemm g) {
         const long o = m * g.scm + n * g.scn;
         const float v = acc[i][j][r];
         if (EPI == kBiasTanh) {
-          C[o] = tanhf(v + g.bias[n]);
+          C[o] = fast_tanh(v + g.bias[n]);
         } else if (EPI == kMaskTanhGrad) {
           const float x = g.X[o];
           C[o] = v * (1.0f - x * x);
