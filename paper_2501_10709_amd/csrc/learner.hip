@@ -45,6 +45,10 @@ struct Gemm {
   const float* X;
   int M, N, K, kc;
   int ones_row;  // rows m >= ones_row of A read as 1 (appends the column sums of B: bias gradients)
+  // colsum: the workgroups of row tile 0 also sum B's columns over their k range (ascending k,
+  // float32) and store them as row bias_row of C -- the column sums without a row tile of their
+  // own when M is a multiple of the tile height.
+  int colsum, bias_row;
 };
 
 template <int EPI, int TN>
@@ -97,6 +101,8 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(Gemm g) {
   for (int i = 0; i < BI; ++i)
 #pragma unroll
     for (int j = 0; j < BJ; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  const bool do_colsum = g.colsum && blockIdx.x == 0 && tid < TN;
+  float csum = 0.0f;
   if (k_begin < k_end) fetch(k_begin);
   for (int k0 = k_begin; k0 < k_end; k0 += kBK) {
 #pragma unroll
@@ -113,6 +119,11 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(Gemm g) {
     }
     __syncthreads();
     if (k0 + kBK < k_end) fetch(k0 + kBK);
+    if (do_colsum) {
+      // Rows beyond k_end were stored as zero, so they add nothing.
+#pragma unroll
+      for (int kk = 0; kk < kBK; ++kk) csum = csum + Bs[kk][tid];
+    }
     // v_mfma_f32_16x16x4_f32: lane l supplies A[row l%16][k l/16] and B[k l/16][col l%16].
 #pragma unroll
     for (int kq = 0; kq < kBK; kq += 4) {
@@ -130,6 +141,7 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(Gemm g) {
   }
   // Lane l holds column l%16 and rows 4(l/16)..4(l/16)+3 of each 16 x 16 block.
   float* C = g.C + blockIdx.z * g.scz;
+  if (do_colsum && n0 + tid < g.N) C[static_cast<long>(g.bias_row) * g.scm + (n0 + tid) * g.scn] = csum;
 #pragma unroll
   for (int i = 0; i < BI; ++i)
 #pragma unroll
@@ -272,11 +284,16 @@ hipError_t weight_grad(const Layout& L, const float* Xr, int kin, int ldx, const
   g.scm = kout;
   g.scn = 1;
   g.scz = static_cast<long>(kin + 1) * kout;
-  g.M = kin + 1;
+  // With kin a multiple of the tile height the bias row (the column sums of G) would take a row
+  // tile of its own; the first row tile's workgroups sum the columns instead.
+  const bool own = kin % kTile == 0;
+  g.M = own ? kin : kin + 1;
   g.N = kout;
   g.K = L.rows;
   g.kc = L.chunk;
   g.ones_row = kin;
+  g.colsum = own ? 1 : 0;
+  g.bias_row = kin;
   hipError_t e = gemm<kStore>(g, L.n_chunks, stream);
   if (e != hipSuccess) return e;
   const int len = (kin + 1) * kout;

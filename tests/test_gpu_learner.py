@@ -38,14 +38,15 @@ def _unflatten(flat, S, H, A):
     return out
 
 
-@pytest.mark.parametrize("agent,lam,N,T,K", [(0, 0.0, 24, 16, 3), (2, 0.5, 37, 9, 3), (1, 2.0, 130, 5, 3),
-                                             (0, 1.0, 1, 1, 1)])
-def test_policy_gradient_matches_oracle(agent, lam, N, T, K):
-    """The last case is degenerate: one actor (no diversity term whatever lambda), one
-    environment, one day."""
+@pytest.mark.parametrize("agent,lam,N,T,K,H", [(0, 0.0, 24, 16, 3, 64), (2, 0.5, 37, 9, 3, 64), (1, 2.0, 130, 5, 3, 64),
+                                               (0, 1.0, 1, 1, 1, 64), (1, 0.3, 50, 7, 3, 128)])
+def test_policy_gradient_matches_oracle(agent, lam, N, T, K, H):
+    """The fourth case is degenerate: one actor (no diversity term whatever lambda), one
+    environment, one day.  The last has a hidden width of one row tile (128), where the bias
+    gradients come from column sums inside the weight-gradient product."""
     import torch
     from paper_2501_10709_amd import binding as B
-    D, H, sigma, key, off = 5, 64, 0.1, 9, 4
+    D, sigma, key, off = 5, 0.1, 9, 4
     cfg, actors, states, rew = _rollout(N, D, T, K, H, sigma, key, off, seed=agent + 3)
     S, A = cfg.state_dim, D
     w = torch.as_tensor(pack_actor_weights(actors)).cuda()
@@ -53,7 +54,7 @@ def test_policy_gradient_matches_oracle(agent, lam, N, T, K):
     ws = torch.empty(B.fm_pg_workspace_bytes(K, S, H, A, N, T), dtype=torch.uint8, device="cuda")
     g1 = torch.empty(per, dtype=torch.float32, device="cuda")
     g2 = torch.empty_like(g1)
-    print(f"policy gradient agent {agent} lambda {lam} N {N} T {T} K {K}", flush=True)
+    print(f"policy gradient agent {agent} lambda {lam} N {N} T {T} K {K} H {H}", flush=True)
     B.fm_policy_gradient(K, S, H, A, w, agent, states, rew, N, T, sigma, key, off, lam, g1, ws)
     B.fm_policy_gradient(K, S, H, A, w, agent, states, rew, N, T, sigma, key, off, lam, g2, ws)
     torch.cuda.synchronize()
