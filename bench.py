@@ -290,8 +290,9 @@ def bench_learner(dev, w, reps=5):
                          "kernel": "gemm_kernel (float32 MFMA 16x16x4 tiles)", "flop_per_sample": flop / rows}}
 
 
-def cpu_baseline(w, seconds_hint=True):
-    """The oracle (float64 numpy) on the same workload, timed on the host."""
+def cpu_baseline(w, budget_s=10.0, max_reps=4):
+    """The oracle (float64 numpy) on the same workload, timed on the host: whole closed-loop
+    rollouts of all the workload's environments until about budget_s seconds of CPU work."""
     from oracle.rollout import rollout_closed_loop
     from workload import make_actor_weights, make_market
     try:
@@ -304,7 +305,7 @@ def cpu_baseline(w, seconds_hint=True):
     actors = make_actor_weights(w.actors)
     T = cfg.n_days
     reps, dt = 0, 0.0
-    while reps < 1 or (dt < 10.0 and reps < 4):   # whole rollouts, about 10 s of CPU work
+    while reps < 1 or (dt < budget_s and reps < max_reps):
         t0 = time.perf_counter()
         rollout_closed_loop(cfg, m.close, m.ind, actors, T, w.sigma, w.noise_key)
         dt += time.perf_counter() - t0
@@ -546,6 +547,9 @@ def main():
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
         rec["cpu_baseline_sharded"] = sharded
+        c1 = cpu_baseline(WORKLOADS["tiny"], budget_s=3.0, max_reps=1000)
+        c1["workload"] = WORKLOADS["tiny"].name
+        rec["cpu_baseline_tiny"] = c1
     print(json.dumps(rec), flush=True)
 
 

@@ -135,6 +135,13 @@ int32_t env_day(const fm_env* env);
  * launch.  Returns FM_ERR_INVALID for NULL or out-of-range values.  *h_tile (may be NULL) gets
  * the value in effect. */
 fm_status env_set_tile(fm_env* env, int32_t envs_per_group, int32_t* h_tile);
+
+/* Tuning of the fused rollout (no effect on results beyond float32 summation order within the
+ * bfloat16 tolerance): schedule 0 picks the compile-time schedule for the shapes that have one
+ * and the generic (runtime-shape) schedule otherwise, 2 always takes the generic one; row_tiles
+ * 1 or 2 sets 16 or 32 MFMA rows per workgroup (0: by N); tile_envs 1..32 the environments per
+ * workgroup (0: fill the compute units).  FM_ERR_INVALID for NULL or out-of-range values. */
+fm_status env_set_fused_tuning(fm_env* env, int32_t schedule, int32_t row_tiles, int32_t tile_envs);
 void env_destroy(fm_env* env);
 
 /* ---------------------------------------------------------------------------------------------
@@ -231,6 +238,11 @@ fm_status fm_batch_create(const fm_batch_group* h_groups, int32_t n_groups, void
  * the fastest.  *h_rows and *h_blocks (may be NULL) get the choice.  Invalidates a captured
  * graph.  Trajectory buffers are overwritten by the trials. */
 fm_status fm_batch_tune(fm_batch* batch, int32_t* h_rows, int32_t* h_blocks);
+
+/* Sets the tile shape by hand instead of the autotuner: rows (16 or 32 environments per work item)
+ * and the persistent grid (blocks, 1..65536 workgroups).  FM_ERR_UNSUPPORTED if a group's tile of
+ * that many rows exceeds the LDS budget.  Invalidates a captured graph. */
+fm_status fm_batch_set_tiling(fm_batch* batch, int32_t rows, int32_t blocks);
 
 /* Runs every group's n_steps on the batch's stream and advances each environment's day.
  * use_graph != 0 captures the chunk launches into a hipGraph on first use and replays it.

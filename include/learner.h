@@ -11,7 +11,7 @@
  * with respect to agent i's parameters, where pi_k(a|s) = N(mu_k(s), sigma^2 I), mu_k the actor
  * network (tanh after every layer), R_n = sum_t r_t^n (rewards as stored, summed in t order), and
  * a = abar(s) + sigma eps the action the rollout sampled before clipping: abar = sum_k w_k mu_k(s)
- * and eps regenerated from the rollout's noise generator (key, env_offset + n, day t).  For equal
+ * and eps regenerated from the rollout's noise generator (key, env_offset + n, day t0 + t).  For equal
  * sigma, KL(pi_j || pi_i) = |mu_j - mu_i|^2 / (2 sigma^2).  Arithmetic is float32 with
  * fixed summation orders (the result is reproducible bit for bit; tanh is evaluated from one
  * exponential and one reciprocal, absolute error below 1e-6); the per-row terms are summed over
@@ -41,12 +41,18 @@ size_t fm_pg_workspace_bytes(int32_t K, int32_t S, int32_t H, int32_t A, int32_t
  * W3[H][A], b3[A] (x W convention).  h_mix: host [K] ensemble weights w_k (NULL = 1/K).
  * agent: i in 0..K-1.  d_states: [T][N][S] float32, the state each action was taken in (s_0 from
  * reset, then the stored next states).  d_rew: [T][N] float64 rewards.  sigma > 0 and noise_key,
- * env_offset: those of the rollout.  lambda_kl >= 0.  d_grad: float32, one actor's parameters in
- * the layout of d_w (overwritten).  Enqueued on stream; returns without synchronising. */
+ * env_offset: those of the rollout.  t0 >= 0: the day of the first sample row (its state s_0 is the
+ * state on day t0; 0 for a rollout from reset, the day read by env_day for one resumed with
+ * env_write_state or run in pieces); row t's noise is the one drawn on day t0 + t.  lambda_kl >= 0.
+ * d_grad: float32, one actor's parameters in the layout of d_w (overwritten).
+ * abar is recomputed from the float32 master weights: for a rollout whose ensemble ran in
+ * bfloat16 the reconstructed sample differs from the one drawn by the bfloat16 arithmetic error of
+ * abar (about 3e-3 at 211-256-256-30), i.e. the gradient is taken at the float32 policy's samples.
+ * Enqueued on stream; returns without synchronising. */
 fm_status fm_policy_gradient(int32_t K, int32_t S, int32_t H, int32_t A, const float* d_w, const float* h_mix,
                              int32_t agent, const float* d_states, const double* d_rew, int32_t N, int32_t T,
-                             float sigma, uint64_t noise_key, int64_t env_offset, float lambda_kl, float* d_grad,
-                             void* d_workspace, size_t workspace_bytes, hipStream_t stream);
+                             float sigma, uint64_t noise_key, int64_t env_offset, int32_t t0, float lambda_kl,
+                             float* d_grad, void* d_workspace, size_t workspace_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -8,8 +8,8 @@ KL(pi_j || pi_i) (the loss L_new = L - lambda sum KL, so the objective to ascend
 Readings:
   * agent i's policy is Gaussian, pi_i(a|s) = N(mu_i(s), sigma^2 I), with mu_i the actor network
     (tanh after every layer); the action sample is the one the rollout drew before clipping,
-    a = abar(s) + sigma eps(n, t) with abar the ensemble mean and eps from the rollout's noise
-    generator (key, global env index, day);
+    a = abar(s) + sigma eps(n, t0 + t) with abar the ensemble mean and eps from the rollout's noise
+    generator (key, global env index, absolute day; sample row t was drawn on day t0 + t);
   * R(tau_n) = sum_t r_t^n (gamma = 1, the stored rewards summed in t order);
   * the KL term is averaged over the N*T states: for equal sigma,
     KL(pi_j || pi_i) = |mu_j - mu_i|^2 / (2 sigma^2);
@@ -38,8 +38,9 @@ def forward_cache(p, x):
     return x1, x2, mu
 
 
-def sampled_actions(actors, states, sigma, noise_key, env_offset, mix=None):
-    """a = abar(s) + sigma eps for every (t, n): float64 [T][N][A] (no clipping)."""
+def sampled_actions(actors, states, sigma, noise_key, env_offset, mix=None, t0=0):
+    """a = abar(s) + sigma eps for every (t, n), eps drawn on day t0 + t: float64 [T][N][A] (no
+    clipping)."""
     T, N, S = states.shape
     rows = np.asarray(states, np.float64).reshape(T * N, S)
     K = len(actors)
@@ -49,7 +50,7 @@ def sampled_actions(actors, states, sigma, noise_key, env_offset, mix=None):
         term = w[k] * actor_forward(p, rows)
         abar = term if abar is None else abar + term
     A = abar.shape[1]
-    eps = np.stack([noise(noise_key, env_offset + np.arange(N), t, A) for t in range(T)])
+    eps = np.stack([noise(noise_key, env_offset + np.arange(N), t0 + t, A) for t in range(T)])
     return abar.reshape(T, N, A) + np.float64(np.float32(sigma)) * eps
 
 
@@ -77,13 +78,14 @@ def objective(actors, i, states, actions, R, sigma, lam):
     return J + lam * kl / (N * T)
 
 
-def policy_gradient(actors, i, states, rewards, sigma, noise_key, env_offset, lam, mix=None):
+def policy_gradient(actors, i, states, rewards, sigma, noise_key, env_offset, lam, mix=None, t0=0):
     """Gradient of `objective` with respect to actor i's parameters, with the actions the rollout
-    sampled: dict W1, b1, W2, b2, W3, b3 (float64, the master weights' shapes)."""
+    sampled (row t on day t0 + t): dict W1, b1, W2, b2, W3, b3 (float64, the master weights'
+    shapes)."""
     T, N, S = states.shape
     rows = np.asarray(states, np.float64).reshape(T * N, S)
     s2 = np.float64(np.float32(sigma)) ** 2
-    acts = sampled_actions(actors, states, sigma, noise_key, env_offset, mix)
+    acts = sampled_actions(actors, states, sigma, noise_key, env_offset, mix, t0)
     A = acts.shape[-1]
     a = acts.reshape(T * N, A)
     R = returns(rewards)

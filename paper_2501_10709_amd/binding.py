@@ -20,9 +20,10 @@ FM_PATH_PLAIN, FM_PATH_FUSED = 0, 1
 # Symbols declared in include/finrl_mi.h.
 EXPORTS = (
     "env_workspace_bytes", "env_create", "env_reset", "env_step", "env_rollout", "env_read_state",
-    "env_write_state", "env_day", "env_set_tile", "env_destroy", "ensemble_workspace_bytes", "ensemble_create",
+    "env_write_state", "env_day", "env_set_tile", "env_set_fused_tuning", "env_destroy", "ensemble_workspace_bytes", "ensemble_create",
     "ensemble_act", "ensemble_destroy", "fm_last_error", "fm_noise", "fm_version", "fm_backtest_metrics",
-    "fm_sharpe_weights", "fm_batch_workspace_bytes", "fm_batch_create", "fm_batch_tune", "fm_batch_run",
+    "fm_sharpe_weights", "fm_batch_workspace_bytes", "fm_batch_create", "fm_batch_tune", "fm_batch_set_tiling",
+    "fm_batch_run",
     "fm_batch_destroy", "fm_serve_request_bytes", "fm_serve_workspace_bytes", "fm_serve_create", "fm_serve_submit",
     "fm_serve_step", "fm_serve_poll", "fm_serve_destroy", "fm_pg_workspace_bytes", "fm_policy_gradient",
 )
@@ -111,6 +112,7 @@ def load(path: str = LIB_PATH):
         "env_write_state": (I32, [P, P, P, P, P, I32]),
         "env_day": (I32, [P]),
         "env_set_tile": (I32, [P, I32, ctypes.POINTER(I32)]),
+        "env_set_fused_tuning": (I32, [P, I32, I32, I32]),
         "env_destroy": (None, [P]),
         "ensemble_workspace_bytes": (SZ, [I32, I32, I32, I32, I32, I32]),
         "ensemble_create": (I32, [I32, I32, I32, I32, I32, P, P, I32, P, SZ, P, ctypes.POINTER(P)]),
@@ -125,6 +127,7 @@ def load(path: str = LIB_PATH):
         "fm_batch_workspace_bytes": (SZ, [ctypes.POINTER(FmBatchGroup), I32]),
         "fm_batch_create": (I32, [ctypes.POINTER(FmBatchGroup), I32, P, SZ, P, ctypes.POINTER(P)]),
         "fm_batch_tune": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "fm_batch_set_tiling": (I32, [P, I32, I32]),
         "fm_batch_run": (I32, [P, I32]),
         "fm_batch_destroy": (None, [P]),
         "fm_serve_request_bytes": (SZ, [I32]),
@@ -136,7 +139,7 @@ def load(path: str = LIB_PATH):
         "fm_serve_destroy": (None, [P]),
         "fm_pg_workspace_bytes": (SZ, [I32, I32, I32, I32, I32, I32]),
         "fm_policy_gradient": (I32, [I32, I32, I32, I32, P, P, I32, P, P, I32, I32, ctypes.c_float, U64, I64,
-                                     ctypes.c_float, P, P, SZ, P]),
+                                     I32, ctypes.c_float, P, P, SZ, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -249,6 +252,10 @@ def env_set_tile(env, envs_per_group: int) -> int:
     return out.value
 
 
+def env_set_fused_tuning(env, schedule=0, row_tiles=0, tile_envs=0):
+    _check(load().env_set_fused_tuning(env, int(schedule), int(row_tiles), int(tile_envs)))
+
+
 def env_destroy(env):
     load().env_destroy(env)
 
@@ -357,6 +364,10 @@ def fm_batch_tune(batch):
     return rows.value, blocks.value
 
 
+def fm_batch_set_tiling(batch, rows, blocks):
+    _check(load().fm_batch_set_tiling(batch, int(rows), int(blocks)))
+
+
 def fm_batch_run(batch, use_graph=False):
     _check(load().fm_batch_run(batch, 1 if use_graph else 0))
 
@@ -417,9 +428,9 @@ def fm_pg_workspace_bytes(K, S, H, A, N, T) -> int:
 
 
 def fm_policy_gradient(K, S, H, A, d_w, agent, d_states, d_rew, N, T, sigma, noise_key, env_offset, lambda_kl,
-                       d_grad, d_workspace, mix=None, stream=None):
+                       d_grad, d_workspace, mix=None, stream=None, t0=0):
     """Gradient of agent `agent`'s objective (eqs. 4 and 5) into d_grad (float32, one actor's
-    master-weight layout)."""
+    master-weight layout).  t0: the day of the first sample row."""
     import numpy as np
     import torch
     h_mix = None
@@ -429,6 +440,7 @@ def fm_policy_gradient(K, S, H, A, d_w, agent, d_states, d_rew, N, T, sigma, noi
     _check(load().fm_policy_gradient(
         K, S, H, A, _ptr(d_w, torch.float32, K * per, "d_w"), None if h_mix is None else h_mix.ctypes.data, agent,
         _ptr(d_states, torch.float32, T * N * S, "d_states"), _ptr(d_rew, torch.float64, T * N, "d_rew"), N, T,
-        float(sigma), int(noise_key), int(env_offset), float(lambda_kl), _ptr(d_grad, torch.float32, per, "d_grad"),
+        float(sigma), int(noise_key), int(env_offset), int(t0), float(lambda_kl),
+        _ptr(d_grad, torch.float32, per, "d_grad"),
         _ptr(d_workspace, None, None, "d_workspace"), d_workspace.numel() * d_workspace.element_size(),
         _stream(stream)))

@@ -111,6 +111,7 @@ struct fm_env {
   int device;
   int day;
   int tile;
+  fm::FusedTuning fused;  // fused-rollout tuning (schedule, row tiles, environments per workgroup)
 };
 
 struct fm_ensemble {
@@ -460,6 +461,20 @@ fm_status fm_batch_tune(fm_batch* b, int32_t* h_rows, int32_t* h_blocks) {
   return FM_OK;
 }
 
+fm_status fm_batch_set_tiling(fm_batch* b, int32_t rows, int32_t blocks) {
+  if (!b) return fail(FM_ERR_INVALID, "batch is NULL");
+  if (rows != 16 && rows != 32) return fail(FM_ERR_INVALID, "fm_batch_set_tiling: rows must be 16 or 32");
+  if (blocks < 1 || blocks > 65536) return fail(FM_ERR_INVALID, "fm_batch_set_tiling: blocks must be in 1..65536");
+  for (const fm_batch_group& G : b->groups)
+    if (fm::batched_lds_bytes(rows, G.env->C, G.ens->E) > fm::batched_max_lds())
+      return fail(FM_ERR_UNSUPPORTED, "fm_batch_set_tiling: a group's tile of " + std::to_string(rows) +
+                                          " environments exceeds the LDS budget");
+  DeviceGuard guard(b->device);
+  batch_drop_graph(b);
+  b->blocks = blocks;
+  return batch_items(b, rows);
+}
+
 fm_status fm_batch_run(fm_batch* b, int32_t use_graph) {
   if (!b) return fail(FM_ERR_INVALID, "batch is NULL");
   for (int g = 0; g < b->n_groups; ++g)
@@ -623,7 +638,7 @@ fm_status env_rollout(fm_env* env, const fm_ensemble* ens, int32_t n_steps,
     const hipError_t e = fm::launch_fused_rollout(C, env->st, ens->E, env->day, n_steps, opts->sigma,
                                                   opts->noise_key, opts->env_offset, opts->d_obs_traj,
                                                   opts->d_act_traj, opts->d_rew_traj, opts->d_qty_traj,
-                                                  env->eps_chunk, env->mt_chunk, st, &why);
+                                                  env->eps_chunk, env->mt_chunk, st, &why, env->fused);
     if (!why.empty()) return fail(FM_ERR_UNSUPPORTED, why);
     fm_status s = device_status(e, "env_rollout (fused)");
     if (s != FM_OK) return s;
@@ -685,6 +700,17 @@ fm_status env_set_tile(fm_env* env, int32_t envs_per_group, int32_t* h_tile) {
   if (envs_per_group < 0 || envs_per_group > 64) return fail(FM_ERR_INVALID, "envs_per_group must be in 0..64");
   env->tile = envs_per_group == 0 ? env_tile(env->C.N) : envs_per_group;
   if (h_tile) *h_tile = env->tile;
+  return FM_OK;
+}
+
+fm_status env_set_fused_tuning(fm_env* env, int32_t schedule, int32_t row_tiles, int32_t tile_envs) {
+  if (!env) return fail(FM_ERR_INVALID, "env is NULL");
+  if (schedule != 0 && schedule != 2) return fail(FM_ERR_INVALID, "schedule must be 0 (by shape) or 2 (generic)");
+  if (row_tiles < 0 || row_tiles > 2) return fail(FM_ERR_INVALID, "row_tiles must be 0, 1 or 2");
+  if (tile_envs < 0 || tile_envs > 32) return fail(FM_ERR_INVALID, "tile_envs must be in 0..32");
+  env->fused.schedule = schedule;
+  env->fused.row_tiles = row_tiles;
+  env->fused.tile_envs = tile_envs;
   return FM_OK;
 }
 

@@ -30,6 +30,7 @@
 
 #include "../../include/crypto_serve.h"
 #include "device_common.h"
+#include "pool_alloc.h"
 #include "mlp_device.h"
 #include "status.h"
 
@@ -505,44 +506,6 @@ std::vector<unsigned char> pack_agents(const fm_serve_config& c, const PackLayou
   return img;
 }
 
-// First-fit allocator over [0, size) with coalescing of freed ranges.
-class PoolAlloc {
- public:
-  void reset(size_t size) {
-    free_.clear();
-    if (size) free_[0] = size;
-  }
-  bool alloc(size_t n, size_t* off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it)
-      if (it->second >= n) {
-        *off = it->first;
-        const size_t rest = it->second - n;
-        const size_t at = it->first + n;
-        free_.erase(it);
-        if (rest) free_[at] = rest;
-        return true;
-      }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    auto it = free_.emplace(off, n).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-
- private:
-  std::map<size_t, size_t> free_;
-};
 
 }  // namespace cx
 }  // namespace fm

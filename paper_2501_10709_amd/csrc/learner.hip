@@ -185,15 +185,16 @@ struct Mix {
 //   u = (R_n / N) (abar + sigma eps - mu_i) / sigma^2 + lambda/(N T) sum_{k != i} (mu_i - mu_k) / sigma^2
 //   G3 = u (1 - mu_i^2).
 __global__ void delta3_kernel(const float* mu, int K, int agent, Mix mix, int rows, int N, int T, int A,
-                              const double* R, float sigma, uint64_t key, int64_t env_offset, float lambda_kl,
-                              float* G3) {
+                              const double* R, float sigma, uint64_t key, int64_t env_offset, int t0,
+                              float lambda_kl, float* G3) {
   const int G = (A + 3) / 4;
   const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= static_cast<long>(rows) * G) return;
   const int r = static_cast<int>(i / G), j = static_cast<int>(i % G);
   const int t = r / N, n = r % N;
   float z[4];
-  noise_block(key, static_cast<uint64_t>(env_offset + n), static_cast<uint64_t>(t), static_cast<uint64_t>(j), z);
+  // Row t of the samples was drawn on day t0 + t: the noise is keyed by the absolute day.
+  noise_block(key, static_cast<uint64_t>(env_offset + n), static_cast<uint64_t>(t0 + t), static_cast<uint64_t>(j), z);
   const float inv_s2 = 1.0f / (sigma * sigma);
   const float rn = static_cast<float>(R[n] / N);
   const float kl = lambda_kl / (static_cast<float>(N) * static_cast<float>(T));
@@ -364,8 +365,8 @@ size_t fm_pg_workspace_bytes(int32_t K, int32_t S, int32_t H, int32_t A, int32_t
 
 fm_status fm_policy_gradient(int32_t K, int32_t S, int32_t H, int32_t A, const float* d_w, const float* h_mix,
                              int32_t agent, const float* d_states, const double* d_rew, int32_t N, int32_t T,
-                             float sigma, uint64_t noise_key, int64_t env_offset, float lambda_kl, float* d_grad,
-                             void* d_workspace, size_t workspace_bytes, hipStream_t stream) {
+                             float sigma, uint64_t noise_key, int64_t env_offset, int32_t t0, float lambda_kl,
+                             float* d_grad, void* d_workspace, size_t workspace_bytes, hipStream_t stream) {
   using namespace fm::lrn;
   if (!dims_ok(K, S, H, A, N, T))
     return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: sizes out of range (K 1..8, S/H 1..1024, A 1..128, N*T <= 2^26)");
@@ -376,6 +377,8 @@ fm_status fm_policy_gradient(int32_t K, int32_t S, int32_t H, int32_t A, const f
   if (!(lambda_kl >= 0.0f) || !std::isfinite(lambda_kl))
     return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: lambda_kl must be finite and >= 0");
   if (env_offset < 0) return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: env_offset must be >= 0");
+  if (t0 < 0 || static_cast<int64_t>(t0) + T > (int64_t{1} << 31) - 1)
+    return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: t0 must be >= 0 and t0 + T must fit int32");
   const Layout L = layout(K, S, H, A, N, T);
   if (workspace_bytes < L.total || reinterpret_cast<uintptr_t>(d_workspace) % 256)
     return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient: workspace smaller than fm_pg_workspace_bytes or not 256-byte aligned");
@@ -407,7 +410,7 @@ fm_status fm_policy_gradient(int32_t K, int32_t S, int32_t H, int32_t A, const f
   hipLaunchKernelGGL(returns_kernel, dim3((N + 255) / 256), dim3(256), 0, stream, d_rew, T, N, R);
   const long nd = static_cast<long>(L.rows) * ((A + 3) / 4);
   hipLaunchKernelGGL(delta3_kernel, dim3(static_cast<unsigned>((nd + 255) / 256)), dim3(256), 0, stream, mu, K,
-                     agent, mix, L.rows, N, T, A, R, sigma, noise_key, env_offset, lambda_kl, g3);
+                     agent, mix, L.rows, N, T, A, R, sigma, noise_key, env_offset, t0, lambda_kl, g3);
   e = hipGetLastError();
   if (e != hipSuccess) return fm::device_error(e, "fm_policy_gradient (delta)");
   const float* wi = d_w + per * agent;

@@ -83,6 +83,11 @@ class VecEnv:
         """Environments per workgroup of the environment kernels (0: size-based default)."""
         return B.env_set_tile(self.handle, envs_per_group)
 
+    def set_fused_tuning(self, schedule=0, row_tiles=0, tile_envs=0):
+        """Fused-rollout tuning: schedule (0 by shape, 2 generic), MFMA row tiles per workgroup
+        (1, 2; 0 by N) and environments per workgroup (0: fill the compute units)."""
+        B.env_set_fused_tuning(self.handle, schedule, row_tiles, tile_envs)
+
     def reset(self, return_obs=True):
         obs = torch.empty((self.N, self.S), dtype=torch.float32, device=self.device) if return_obs else None
         B.env_reset(self.handle, obs)
@@ -183,6 +188,10 @@ class Batch:
     def tune(self):
         """Autotune the tile rows and persistent grid; returns (rows, blocks)."""
         return B.fm_batch_tune(self.handle)
+
+    def set_tiling(self, rows, blocks):
+        """Tile rows (16 or 32) and persistent grid chosen by hand instead of by the autotuner."""
+        B.fm_batch_set_tiling(self.handle, rows, blocks)
 
     def run(self, use_graph=False):
         B.fm_batch_run(self.handle, use_graph)

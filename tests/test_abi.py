@@ -112,6 +112,8 @@ def test_sharpe_weights_match_oracle():
 def test_env_set_tile_validation(lib):
     assert lib.env_set_tile(None, 8, None) == B.FM_ERR_INVALID
     assert "NULL" in B.fm_last_error()
+    assert lib.env_set_fused_tuning(None, 0, 0, 0) == B.FM_ERR_INVALID
+    assert "NULL" in B.fm_last_error()
 
 
 def test_batch_argument_validation(lib):
@@ -123,6 +125,7 @@ def test_batch_argument_validation(lib):
     assert lib.fm_batch_workspace_bytes(groups, 1) == 0  # NULL env / ensemble
     assert lib.fm_batch_run(None, 0) == B.FM_ERR_INVALID
     assert lib.fm_batch_tune(None, None, None) == B.FM_ERR_INVALID
+    assert lib.fm_batch_set_tiling(None, 16, 256) == B.FM_ERR_INVALID
 
 
 def test_serve_config_validation(lib):

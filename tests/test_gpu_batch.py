@@ -103,3 +103,73 @@ def test_batch_requires_recorded_days():
     with pytest.raises(B.FmError):
         batch.run()  # the environments are no longer at their starting days
     batch.close()
+
+
+# Hidden width 256 (every MLP wavefront walks four output tiles per layer), wide groups (D = 100:
+# state width 701) and horizons over three and more 64-day chunks, as the benchmark's batch has.
+GROUPS_256 = [(100, 20, 130, 21), (30, 40, 140, 22), (50, 17, 70, 23), (5, 70, 20, 24), (30, 33, 200, 25)]
+
+
+def _build_256(dev, groups):
+    from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
+    made = []
+    for D, N, T, seed in groups:
+        cfg, m = env_case(N, D, 5, T, seed)
+        S = 7 * D + 1
+        acfg, actors, packed = actors_case(3, S, 256, D, seed_base=100 * seed)
+        ens = Ensemble(packed, 3, S, 256, D, dtype="bf16", max_batch=N, device=dev)
+        env = VecEnv(cfg, m.close, m.ind, device=dev)
+        made.append((cfg, m, actors, ens, env))
+    return made
+
+
+@pytest.mark.parametrize("tiling", ["tuned", (16, 128), (16, 512), (32, 256)])
+def test_batch_hidden_256_matches_oracle(tiling):
+    """The benchmark's shapes under the autotuner's choice and under forced tilings, each run
+    eagerly and then replayed from its graph: the eager run against the oracle (states and
+    quantities exact, rewards 1e-12, actions 2e-2), the replay bit for bit against the eager run.
+    A 32-row tile of the D = 100 group does not fit the LDS, so that tiling runs without it (and
+    asking for it is refused)."""
+    import torch
+    from paper_2501_10709_amd import binding as B
+    from paper_2501_10709_amd.vecenv import Batch
+    dev = cuda()
+    groups = GROUPS_256 if tiling == "tuned" or tiling[0] == 16 else GROUPS_256[1:]
+    made = _build_256(dev, groups)
+    for *_, env in made:
+        env.reset(return_obs=False)
+    spec = [dict(env=env, ens=ens, n_steps=cfg.n_days, sigma=0.1, noise_key=9, env_offset=5000 * i,
+                 store=("obs", "act", "rew", "qty")) for i, (cfg, m, actors, ens, env) in enumerate(made)]
+    batch = Batch(spec)
+    if tiling == "tuned":
+        rows, blocks = batch.tune()
+    else:
+        rows, blocks = tiling
+        batch.set_tiling(rows, blocks)
+    print(f"[batch256] rows {rows} blocks {blocks} groups {len(made)}", flush=True)
+    obs0 = [_np(env.reset()) for *_, env in made]
+    out = batch.run(use_graph=False)
+    torch.cuda.synchronize()
+    eager = [{k: v.clone() for k, v in o.items()} for o in out]
+    for i, (cfg, m, actors, ens, env) in enumerate(made):
+        traj = {k: _np(v) for k, v in eager[i].items()}
+        check_replay(cfg, m, traj, obs0[i])
+        worst = check_actions(actors, "bf16", traj, obs0[i], 0.1, 9, TOL_BF16, env_offset=5000 * i)
+        assert np.abs(traj["qty"]).sum() > 0
+        print(f"  group {i} D={cfg.n_stocks} N={cfg.n_envs} T={cfg.n_days}: worst action error {worst:.3e}",
+              flush=True)
+    for *_, env in made:
+        env.reset(return_obs=False)
+    out = batch.run(use_graph=True)
+    torch.cuda.synchronize()
+    for g, (o, e) in enumerate(zip(out, eager)):
+        for k in e:
+            assert torch.equal(o[k], e[k]), (g, k)
+    if tiling != "tuned" and tiling[0] == 32:
+        wide = _build_256(dev, GROUPS_256[:1])
+        wide[0][4].reset(return_obs=False)
+        b2 = Batch([dict(env=wide[0][4], ens=wide[0][3], n_steps=10)])
+        with pytest.raises(B.FmError):
+            b2.set_tiling(32, 256)
+        b2.close()
+    batch.close()

@@ -59,14 +59,42 @@ def test_paper_scale_closed_loop_sampled(dtype, path, tol):
 
 
 def test_precision_scale_fused_sampled():
-    """N=8192 (two row tiles per workgroup), bfloat16 fused path, 40 steps."""
+    """N=8192 (32-row workgroups), bfloat16 fused path, all 252 steps: four 64-day launches, so the
+    trading state crosses three chunk boundaries in HBM."""
     w = PRECISION
-    print("[full] fused bf16 N=8192 T=40", flush=True)
-    cfg, m, actors, obs0, traj = _closed(w, 8192, 40, "bf16", "fused")
+    print("[full] fused bf16 N=8192 T=252", flush=True)
+    cfg, m, actors, obs0, traj = _closed(w, 8192, 252, "bf16", "fused")
     ids = _sample(8192, seed=1)
     sub = {k: _np(v[:, ids]) for k, v in traj.items()}
     check_replay(cfg, m, sub, obs0[ids])
     check_actions(actors, "bf16", sub, obs0[ids], w.sigma, w.noise_key, TOL_BF16, id_map=ids)
+
+
+@pytest.mark.parametrize("D,N,T", [(50, 300, 70), (30, 130, 66)])
+def test_generic_schedule_hidden_256(D, N, T):
+    """The fused kernel's generic schedule (runtime shapes) at the paper's hidden width 256: a
+    50-stock set (state width 351, beyond the streamed schedule's 32 stocks) and the paper's
+    30-stock shape forced onto it, ragged N, horizons over one 64-day launch."""
+    import torch
+    from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
+    dev = cuda()
+    w = PAPER_SCALE
+    cfg = w.env.replace(n_envs=N, n_stocks=D, n_days=T)
+    m = make_market(w.market_seed + D, D, T)
+    acfg, actors, packed = actors_case(3, cfg.state_dim, 256, D, bias_std=0.1, seed_base=4000 + D)
+    ens = Ensemble(packed, 3, cfg.state_dim, 256, D, dtype="bf16", max_batch=N, device=dev)
+    env = VecEnv(cfg, m.close, m.ind, device=dev)
+    print(f"[full] fused generic D={D} N={N} T={T} H=256", flush=True)
+    if D <= 32:
+        env.set_fused_tuning(schedule=2)  # the generic schedule for a shape the streamed one takes
+    obs0 = _np(env.reset())
+    traj = env.rollout(T, ens=ens, sigma=w.sigma, noise_key=w.noise_key, path="fused")
+    torch.cuda.synchronize()
+    ids = np.unique(np.concatenate([np.arange(N - 20, N), _sample(N, k=30, seed=D)]))
+    sub = {k: _np(v[:, ids]) for k, v in traj.items()}
+    check_replay(cfg, m, sub, obs0[ids])
+    worst = check_actions(actors, "bf16", sub, obs0[ids], w.sigma, w.noise_key, TOL_BF16, id_map=ids)
+    print(f"  worst action error {worst:.3e}", flush=True)
 
 
 def test_ragged_two_row_tiles_fused():
@@ -119,8 +147,8 @@ def test_episode_return_statistics_reported():
 def test_policy_gradient_paper_scale():
     """The learner at the benchmark's size and launch configuration (N = 2048, T = 252, three
     actors 211-256-256-30, lambda 0.1, agent 0, from a bfloat16 fused rollout) against the
-    oracle's float64 gradient over all 516,096 rows: every entry within 2e-3 of the largest
-    entry of that parameter's gradient.  The oracle takes about a minute here."""
+    oracle's float64 gradient over all 516,096 rows: every entry within 1e-5 of the largest
+    entry of that parameter's gradient (the observed error is about 1.4e-7 of it).  The oracle takes about a minute here."""
     import torch
     from oracle import learner as OL
     from paper_2501_10709_amd import binding as B
@@ -159,4 +187,4 @@ def test_policy_gradient_paper_scale():
         scale = np.abs(want[name]).max()
         err = np.abs(got - want[name]).max()
         print(f"  {name}: max |err| {err:.3g} of scale {scale:.3g}", flush=True)
-        assert scale > 0 and err <= 2e-3 * scale, (name, err, scale)
+        assert scale > 0 and err <= 1e-5 * scale, (name, err, scale)

@@ -70,3 +70,61 @@ def test_output_bias_gradient_closed_form():
 def test_returns_sum_in_time_order():
     r = np.array([[1e16, 1.0], [1.0, 2.0], [-1e16, 3.0]])
     np.testing.assert_array_equal(L.returns(r), [((1e16 + 1.0) + -1e16), 6.0])
+
+
+def _constant_agents(mus, S=4, H=3):
+    """Agents whose weights are all zero and whose output biases are atanh(mu_k): each outputs the
+    constant mean mu_k on every state (float64 parameters, so tanh(atanh(mu)) = mu to 1 ulp)."""
+    out = []
+    for mu in mus:
+        mu = np.asarray(mu, np.float64)
+        A = mu.size
+        out.append({"W1": np.zeros((S, H)), "b1": np.zeros(H), "W2": np.zeros((H, H)), "b2": np.zeros(H),
+                    "W3": np.zeros((H, A)), "b3": np.arctanh(mu)})
+    return out
+
+
+@pytest.mark.parametrize("i,want", [
+    # Agent 0 at (0.5, -0.5) against (-0.25, 0.25) and (0.125, 0.0), lambda = 2, sigma = 0.5:
+    # component 0: (0.5 + 0.25) + (0.5 - 0.125) = 1.125, times 1 - 0.25 = 0.75, over 0.25, times 2;
+    # component 1: (-0.5 - 0.25) + (-0.5 - 0.0) = -1.25, same factors.
+    (0, [6.75, -7.5]),
+    # Agent 1 at (-0.25, 0.25): (-0.75 - 0.375, 0.75 + 0.25) times (1 - 0.0625) / 0.25 times 2.
+    (1, [-8.4375, 7.5]),
+    # Agent 2 at (0.125, 0.0): (-0.375 + 0.375, 0.5 - 0.25) times (1 - 0.015625, 1) / 0.25 times 2.
+    (2, [0.0, 2.0]),
+])
+def test_diversity_gradient_closed_form(i, want):
+    """Eq. (5) on its own (zero rewards, so eq. (4) drops out): agents with constant means mu_k.
+    Ascending J + lambda sum_{j != i} KL(pi_j || pi_i), KL = |mu_j - mu_i|^2 / (2 sigma^2) averaged
+    over the N T states, moves agent i's output bias by lambda sum_{j != i} (mu_i - mu_j) (1 - mu_i^2)
+    / sigma^2: away from the other agents, and independent of N and T.  The expected values are
+    worked by hand above; a flipped sign, a missing factor 2 or a lambda / N scale fails them."""
+    agents = _constant_agents([[0.5, -0.5], [-0.25, 0.25], [0.125, 0.0]])
+    for T, N in ((1, 1), (3, 5)):
+        states = np.random.default_rng(T).standard_normal((T, N, 4)).astype(np.float32)
+        g = L.policy_gradient(agents, i, states, np.zeros((T, N)), 0.5, 7, 0, 2.0)
+        np.testing.assert_allclose(g["b3"], want, rtol=0, atol=1e-12)
+        # Nothing else moves: every hidden activation is tanh(0) = 0 and every weight is zero.
+        for name in ("W1", "b1", "W2", "b2", "W3"):
+            assert np.abs(g[name]).max() == 0.0, name
+
+
+def test_sampled_actions_follow_the_absolute_day():
+    """Samples of a rollout that starts on a later day (resumed, or run in pieces): the pre-clip
+    actions rebuilt for rows taken from day t0 on, clipped and rounded to float32, are exactly the
+    actions the closed-loop oracle rollout drew on those days.  Keyed by the row index instead of
+    the day, they are not."""
+    from oracle.rollout import rollout_closed_loop
+    from workload import EnvConfig, make_market
+    D, T, N, t0, sigma, key = 4, 7, 6, 3, 0.3, 21
+    cfg = EnvConfig(n_envs=N, n_stocks=D, n_ind=5, n_days=T)
+    m = make_market(5, D, T)
+    actors = make_actor_weights(ActorConfig(n_actors=2, in_dim=cfg.state_dim, hidden=8, out_dim=D, seed_base=70,
+                                            bias_std=0.2))
+    ro = rollout_closed_loop(cfg, m.close, m.ind, actors, T, sigma, key)
+    states = ro["obs"][t0:T]  # the states acted on at days t0 .. T-1
+    got = np.clip(L.sampled_actions(actors, states, sigma, key, 0, t0=t0), -1, 1).astype(np.float32)
+    np.testing.assert_array_equal(got, ro["act"][t0:])
+    wrong = np.clip(L.sampled_actions(actors, states, sigma, key, 0), -1, 1).astype(np.float32)
+    assert not np.array_equal(wrong, ro["act"][t0:])
