@@ -136,11 +136,14 @@ int32_t env_day(const fm_env* env);
  * the value in effect. */
 fm_status env_set_tile(fm_env* env, int32_t envs_per_group, int32_t* h_tile);
 
-/* Tuning of the fused rollout (no effect on results beyond float32 summation order within the
- * bfloat16 tolerance): schedule 0 picks the compile-time schedule for the shapes that have one
- * and the generic (runtime-shape) schedule otherwise, 2 always takes the generic one; row_tiles
- * 1 or 2 sets 16 or 32 MFMA rows per workgroup (0: by N); tile_envs 1..32 the environments per
- * workgroup (0: fill the compute units).  FM_ERR_INVALID for NULL or out-of-range values. */
+/* Tuning of the fused rollout (results stay within the bfloat16 tolerance; the environment
+ * arithmetic is unchanged): schedule 0 picks, by shape, the resident schedule (weights held on
+ * chip; K = 3, hidden 256, <= 31 stocks), else the streamed one (weights streamed from L2;
+ * K = 3, hidden 256, <= 32 stocks), else the generic (runtime-shape) one; 1 skips the resident
+ * schedule; 2 always takes the generic one.  row_tiles 1 or 2 sets the streamed schedule's 16
+ * or 32 MFMA rows per workgroup (0: by N); tile_envs the environments per workgroup (resident
+ * <= 8, streamed <= 16 * row_tiles; 0: fill the compute units).  FM_ERR_INVALID for NULL or
+ * out-of-range values. */
 fm_status env_set_fused_tuning(fm_env* env, int32_t schedule, int32_t row_tiles, int32_t tile_envs);
 void env_destroy(fm_env* env);
 

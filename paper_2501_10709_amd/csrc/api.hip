@@ -705,7 +705,7 @@ fm_status env_set_tile(fm_env* env, int32_t envs_per_group, int32_t* h_tile) {
 
 fm_status env_set_fused_tuning(fm_env* env, int32_t schedule, int32_t row_tiles, int32_t tile_envs) {
   if (!env) return fail(FM_ERR_INVALID, "env is NULL");
-  if (schedule != 0 && schedule != 2) return fail(FM_ERR_INVALID, "schedule must be 0 (by shape) or 2 (generic)");
+  if (schedule < 0 || schedule > 2) return fail(FM_ERR_INVALID, "schedule must be 0 (by shape), 1 (streamed) or 2 (generic)");
   if (row_tiles < 0 || row_tiles > 2) return fail(FM_ERR_INVALID, "row_tiles must be 0, 1 or 2");
   if (tile_envs < 0 || tile_envs > 32) return fail(FM_ERR_INVALID, "tile_envs must be in 0..32");
   env->fused.schedule = schedule;

@@ -21,13 +21,16 @@ inline size_t fused_table_floats() { return static_cast<size_t>(kFusedChunk) * 8
 
 // Rows (environments) per workgroup of the fused kernel: 16 * row_tiles.
 struct FusedTuning {
-  int row_tiles = 0;  // 0: choose from the problem size
-  int schedule = 0;   // 0: streamed when the shape allows, 2: always the generic schedule
-  int tile_envs = 0;  // streamed: environments per workgroup, 0: fill the compute units
+  int row_tiles = 0;  // streamed: 0 chooses from the problem size
+  int schedule = 0;   // 0: resident, else streamed, when the shape allows; 1: streamed when the
+                      // shape allows; 2: always the generic schedule
+  int tile_envs = 0;  // resident / streamed: environments per workgroup, 0: fill the compute units
 };
 
 // True when the streamed MLP schedule handles this ensemble and environment.
 bool fused_streamed_shape(const EnvConst& C, const EnsDev& E);
+// True when the resident schedule (weights held on chip) handles them.
+bool fused_resident_shape(const EnvConst& C, const EnsDev& E);
 
 // Returns hipSuccess and leaves *why empty on success; sets *why for unsupported shapes.
 hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0,

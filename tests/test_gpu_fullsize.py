@@ -29,7 +29,7 @@ def _sample(N, k=40, seed=0):
     return np.array(sorted(ids))
 
 
-def _closed(w, N, T, dtype, path, store=("obs", "act", "rew", "qty")):
+def _closed(w, N, T, dtype, path, store=("obs", "act", "rew", "qty"), schedule=0):
     import torch
     from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
     dev = cuda()
@@ -38,18 +38,21 @@ def _closed(w, N, T, dtype, path, store=("obs", "act", "rew", "qty")):
     acfg, actors, packed = actors_case(3, cfg.state_dim, w.actors.hidden, cfg.n_stocks, bias_std=0.0)
     ens = Ensemble(packed, 3, cfg.state_dim, w.actors.hidden, cfg.n_stocks, dtype=dtype, max_batch=N, device=dev)
     env = VecEnv(cfg, m.close, m.ind, device=dev)
+    env.set_fused_tuning(schedule=schedule)
     obs0 = _np(env.reset())
     traj = env.rollout(T, ens=ens, sigma=w.sigma, noise_key=w.noise_key, path=path, store=store)
     torch.cuda.synchronize()
     return cfg, m, actors, obs0, traj
 
 
-@pytest.mark.parametrize("dtype,path,tol", [("bf16", "fused", TOL_BF16), ("f32", "plain", TOL_F32)])
-def test_paper_scale_closed_loop_sampled(dtype, path, tol):
-    """N=2048, D=30, T=252, three 211-256-256-30 actors: the benchmark's launch configuration."""
+@pytest.mark.parametrize("dtype,path,tol,schedule", [("bf16", "fused", TOL_BF16, 0), ("f32", "plain", TOL_F32, 0),
+                                                     ("bf16", "fused", TOL_BF16, 1)])
+def test_paper_scale_closed_loop_sampled(dtype, path, tol, schedule):
+    """N=2048, D=30, T=252, three 211-256-256-30 actors: the benchmark's launch configuration
+    (the fused path's resident schedule), and the streamed schedule on the same shape."""
     w = PAPER_SCALE
-    print(f"[full] {path} {dtype} N=2048 T=252", flush=True)
-    cfg, m, actors, obs0, traj = _closed(w, 2048, 252, dtype, path)
+    print(f"[full] {path} {dtype} N=2048 T=252 schedule {schedule}", flush=True)
+    cfg, m, actors, obs0, traj = _closed(w, 2048, 252, dtype, path, schedule=schedule)
     ids = _sample(2048)
     sub = {k: _np(v[:, ids]) for k, v in traj.items()}
     check_replay(cfg, m, sub, obs0[ids])
@@ -58,12 +61,14 @@ def test_paper_scale_closed_loop_sampled(dtype, path, tol):
     print(f"  worst action error {worst:.3e}", flush=True)
 
 
-def test_precision_scale_fused_sampled():
-    """N=8192 (32-row workgroups), bfloat16 fused path, all 252 steps: four 64-day launches, so the
-    trading state crosses three chunk boundaries in HBM."""
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_precision_scale_fused_sampled(schedule):
+    """N=8192, bfloat16 fused path, all 252 steps: four 64-day launches, so the trading state
+    crosses three chunk boundaries in HBM.  The resident schedule runs 1024 workgroups of eight
+    environments; the streamed one 32-row workgroups."""
     w = PRECISION
-    print("[full] fused bf16 N=8192 T=252", flush=True)
-    cfg, m, actors, obs0, traj = _closed(w, 8192, 252, "bf16", "fused")
+    print(f"[full] fused bf16 N=8192 T=252 schedule {schedule}", flush=True)
+    cfg, m, actors, obs0, traj = _closed(w, 8192, 252, "bf16", "fused", schedule=schedule)
     ids = _sample(8192, seed=1)
     sub = {k: _np(v[:, ids]) for k, v in traj.items()}
     check_replay(cfg, m, sub, obs0[ids])
@@ -97,10 +102,11 @@ def test_generic_schedule_hidden_256(D, N, T):
     print(f"  worst action error {worst:.3e}", flush=True)
 
 
-def test_ragged_two_row_tiles_fused():
-    """A batch that is not a multiple of the 32-row workgroup tile."""
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_ragged_two_row_tiles_fused(schedule):
+    """A batch that is not a multiple of the workgroup tile (8 environments resident, 32 streamed)."""
     w = PRECISION
-    cfg, m, actors, obs0, traj = _closed(w, 4100, 6, "bf16", "fused")
+    cfg, m, actors, obs0, traj = _closed(w, 4100, 6, "bf16", "fused", schedule=schedule)
     ids = np.concatenate([np.arange(4064, 4100), _sample(4100, k=20, seed=2)])
     ids = np.unique(ids)
     sub = {k: _np(v[:, ids]) for k, v in traj.items()}

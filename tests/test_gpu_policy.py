@@ -107,25 +107,34 @@ def test_ensemble_mix_weights_and_single_actor():
 
 
 CLOSED = [
-    # name, N, H, dtype, path, T
-    ("plain f32 tiny", 16, 64, "f32", "plain", 30),
-    ("plain f32 ragged H=256", 37, 256, "f32", "plain", 12),
-    ("plain bf16", 24, 256, "bf16", "plain", 10),
-    ("fused bf16 tiny", 16, 64, "bf16", "fused", 30),
-    ("fused bf16 ragged H=256", 45, 256, "bf16", "fused", 12),
+    # name, N, H, dtype, path, T, fused tuning (schedule, tile_envs), stocks
+    ("plain f32 tiny", 16, 64, "f32", "plain", 30, (0, 0), 30),
+    ("plain f32 ragged H=256", 37, 256, "f32", "plain", 12, (0, 0), 30),
+    ("plain bf16", 24, 256, "bf16", "plain", 10, (0, 0), 30),
+    ("fused bf16 tiny", 16, 64, "bf16", "fused", 30, (0, 0), 30),
+    ("fused bf16 ragged H=256", 45, 256, "bf16", "fused", 12, (0, 0), 30),
+    # The resident schedule with full and ragged tiles of 8, 5 and 3 environments, and the
+    # streamed schedule, over more than one 64-day launch; 31 stocks (the resident limit) and 7.
+    ("resident tiles of 8", 45, 256, "bf16", "fused", 70, (0, 8), 30),
+    ("resident tiles of 5", 23, 256, "bf16", "fused", 20, (0, 5), 30),
+    ("resident tiles of 3 D=31", 10, 256, "bf16", "fused", 20, (0, 3), 31),
+    ("resident D=7", 19, 256, "bf16", "fused", 20, (0, 8), 7),
+    ("streamed tiles of 16", 45, 256, "bf16", "fused", 70, (1, 16), 30),
 ]
 
 
-@pytest.mark.parametrize("name,N,H,dtype,path,T", CLOSED, ids=[c[0] for c in CLOSED])
-def test_closed_loop_rollout(name, N, H, dtype, path, T):
+@pytest.mark.parametrize("name,N,H,dtype,path,T,tuning,D", CLOSED, ids=[c[0] for c in CLOSED])
+def test_closed_loop_rollout(name, N, H, dtype, path, T, tuning, D):
     import torch
     from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
     dev = cuda()
     print(f"[closed] {name}", flush=True)
-    cfg, m = env_case(N, 30, 5, T, 1001)
-    acfg, actors, packed = actors_case(3, 211, H, 30)
-    ens = Ensemble(packed, 3, 211, H, 30, dtype=dtype, max_batch=N, device=dev)
+    S = 7 * D + 1
+    cfg, m = env_case(N, D, 5, T, 1001)
+    acfg, actors, packed = actors_case(3, S, H, D)
+    ens = Ensemble(packed, 3, S, H, D, dtype=dtype, max_batch=N, device=dev)
     env = VecEnv(cfg, m.close, m.ind, device=dev)
+    env.set_fused_tuning(schedule=tuning[0], tile_envs=tuning[1])
     obs0 = _np(env.reset())
     traj = env.rollout(T, ens=ens, sigma=0.1, noise_key=7, path=path)
     traj = {k: _np(v) for k, v in traj.items()}
@@ -136,14 +145,16 @@ def test_closed_loop_rollout(name, N, H, dtype, path, T):
     print(f"  worst action error {worst:.3e}", flush=True)
 
 
-def test_fused_rollout_resumes_mid_trajectory():
-    """Two fused launches (9 + 11 steps) give the same trajectory as one of 20 steps."""
+@pytest.mark.parametrize("H", [64, 256])
+def test_fused_rollout_resumes_mid_trajectory(H):
+    """Two fused launches (9 + 11 steps) give the same trajectory as one of 20 steps (generic
+    schedule at H = 64, resident at 256)."""
     import torch
     from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
     dev = cuda()
     cfg, m = env_case(20, 30, 5, 20, 1001)
-    acfg, actors, packed = actors_case(3, 211, 64, 30)
-    ens = Ensemble(packed, 3, 211, 64, 30, dtype="bf16", max_batch=20, device=dev)
+    acfg, actors, packed = actors_case(3, 211, H, 30)
+    ens = Ensemble(packed, 3, 211, H, 30, dtype="bf16", max_batch=20, device=dev)
     env = VecEnv(cfg, m.close, m.ind, device=dev)
     env.reset(return_obs=False)
     full = env.rollout(20, ens=ens, sigma=0.1, noise_key=7, path="fused")
