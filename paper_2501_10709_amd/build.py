@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB_NAME = "libfinrl_mi.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["api.hip", "env_kernels.hip", "ensemble_kernels.hip", "fused_rollout.hip", "metrics_kernels.hip", "crypto_serve.hip", "learner.hip"]
+SOURCES = ["api.hip", "env_kernels.hip", "ensemble_kernels.hip", "fused_rollout.hip", "fused_resident.hip", "metrics_kernels.hip", "crypto_serve.hip", "learner.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -28,6 +28,12 @@ HIPCC_FLAGS = [
     "-Wall", "-Wno-unused-function",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
+
+
+# Per-source extra flags.  The resident rollout keeps the second layer's weights in both register
+# files; its MFMA results go to the vector registers so that the accumulation registers hold
+# weights only.
+EXTRA_FLAGS = {"fused_resident.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _hipcc() -> str:
@@ -45,7 +51,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         out = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
                         if "packed-fp32-ops' is not a recognized feature" not in l)

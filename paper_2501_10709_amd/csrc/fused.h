@@ -19,6 +19,24 @@ constexpr int kFusedChunk = 64;
 inline size_t fused_eps_floats(size_t N, size_t D) { return static_cast<size_t>(kFusedChunk) * N * D; }
 inline size_t fused_table_floats() { return static_cast<size_t>(kFusedChunk) * 8 * 512; }
 
+// Arguments of a fused launch over a chunk of steps.
+struct FusedArgs {
+  int t0, n_steps;
+  float sigma;
+  uint64_t key;
+  int64_t env_offset;
+  float* obs_traj;
+  float* act_traj;
+  double* rew_traj;
+  int* qty_traj;
+  const float* eps;  // streamed and resident schedules: the chunk's noise [n_steps][N][D]
+  const float* mt;   // streamed and resident schedules: the chunk's layer-1 market shares [n_steps][K][H]
+  int tile_envs = 0; // streamed and resident schedules: environments per workgroup
+};
+
+// Environments per workgroup of the resident schedule (one compute unit each).
+constexpr int kResRows = 8;
+
 // Rows (environments) per workgroup of the fused kernel: 16 * row_tiles.
 struct FusedTuning {
   int row_tiles = 0;  // streamed: 0 chooses from the problem size
@@ -31,6 +49,15 @@ struct FusedTuning {
 bool fused_streamed_shape(const EnvConst& C, const EnsDev& E);
 // True when the resident schedule (weights held on chip) handles them.
 bool fused_resident_shape(const EnvConst& C, const EnsDev& E);
+
+// The per-chunk inputs of the streamed and resident schedules, for days t .. t+n-1: the market
+// table mt[c][k][j] (actor k's layer-1 share of day t+c's market entries, bias included) and,
+// when sigma != 0, the noise eps[c][n][d].
+hipError_t launch_chunk_inputs(const EnvConst& C, const EnsDev& E, int t, int n, float sigma, uint64_t key,
+                               int64_t env_offset, float* eps_chunk, float* mt_chunk, hipStream_t stream);
+// The resident schedule over F's steps, chunk by chunk (fused_resident.hip).
+hipError_t launch_resident(const EnvConst& C, const EnvState& st, const EnsDev& E, FusedArgs F, float* eps_chunk,
+                           float* mt_chunk, hipStream_t stream);
 
 // Returns hipSuccess and leaves *why empty on success; sets *why for unsupported shapes.
 hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0,

@@ -27,19 +27,6 @@ namespace fm {
 
 namespace {
 
-struct FusedArgs {
-  int t0, n_steps;
-  float sigma;
-  uint64_t key;
-  int64_t env_offset;
-  float* obs_traj;
-  float* act_traj;
-  double* rew_traj;
-  int* qty_traj;
-  const float* eps;  // streamed schedule: the chunk's noise [n_steps][N][D]
-  const float* mt;   // streamed schedule: the chunk's layer-1 market shares [n_steps][K][H]
-  int tile_envs = 0; // streamed schedule: environments per workgroup (<= its 16 * ROWT rows)
-};
 
 // Calls f(std::integral_constant<int, i>) for i = 0 .. N-1, fully unrolled.
 template <class Fn, int... I>
@@ -795,389 +782,6 @@ __global__ __launch_bounds__(kStreamThreads) void fused_streamed_kernel(EnvConst
   }
 }
 
-// ------------------------------------------------------------------------------------------
-// Resident kernel for the 211 -> 256 -> 256 -> 30, K = 3 shape (at most 31 stocks, so the
-// per-environment rows of the split first layer are one 32-row k-step).  The weights stay on
-// chip for the whole launch instead of being streamed from L2 every step:
-//   * W2 of all three actors (384 KB bfloat16) in registers: wavefront w holds the B fragments
-//     of output tiles 4w .. 4w+3 of every actor (3 x 8 k-steps x 4 tiles x 4 registers = 384 of
-//     its 512 registers; the MFMAs read them in place, most from the accumulation registers);
-//   * W1e (the first layer's cash and holdings rows) and W3 of all actors in LDS (96 KB).
-// A workgroup owns up to kResRows = 8 environments, all four wavefronts on one compute unit.
-// The 16 MFMA rows repeat the 8 environments, so each accumulator's lanes 32-63 duplicate
-// lanes 0-31; before an epilogue two accumulators are merged with one lane swap (lanes 32-63
-// of the first take lanes 0-31 of the second), so each tanh is evaluated once per value.
-// Per step, between four workgroup barriers:
-//   L1  all waves: the per-environment rows on MFMA (A: the state rows' cash and holdings
-//       entries, B: W1e from LDS) plus the day's market share (bias included) from the table;
-//   L2  all waves: B from registers;
-//   L3  wavefront a < 3 computes actor a's two output tiles over all 256 inputs (B: W3 from
-//       LDS) and leaves w_a tanh(z + b3_a) in LDS;
-//   env wavefront 0: the action (sum over actors in actor order, noise, clip), orders, sells,
-//       the serial cash recurrences, buys, position values, value and reward, the next state
-//       rows' cash and holdings entries -- with wavefront-local synchronisation only;
-//       wavefronts 1-3 meanwhile: the noise of the next step (Philox4x64-10 + Box-Muller), the
-//       next step's staged market rows and table row into LDS and the requests for the step
-//       after it, and the stores of the previous step's results.
-// ------------------------------------------------------------------------------------------
-constexpr int kResRows = 8;
-constexpr int kResThreads = 256;
-constexpr int kResK = 3, kResH = 256, kResKK = 8;
-constexpr int kResX0 = 40;       // state-row stride (bf16): cash, <= 31 holdings, zeros
-constexpr int kResXS = 264;      // hidden-row stride (bf16)
-constexpr int kResIn = 256;      // staged market entries per day, (2 + I) * D <= 256
-
-constexpr size_t res_a16(size_t b) { return (b + 15) / 16 * 16; }
-
-struct ResLds {
-  // Byte offsets.
-  static constexpr size_t w1e = 0;                                            // [K][16][64] bf16x8
-  static constexpr size_t w3 = w1e + sizeof(bf16x8) * kResK * 16 * 64;        // [K][2][8][64] bf16x8
-  static constexpr size_t x1 = w3 + sizeof(bf16x8) * kResK * 2 * kResKK * 64; // [K][8][264] bf16
-  static constexpr size_t xsz = sizeof(__bf16) * kResK * kResRows * kResXS;
-  static constexpr size_t x2 = x1 + res_a16(xsz);
-  static constexpr size_t x0 = x2 + res_a16(xsz);                                 // [2][8][40] bf16
-  static constexpr size_t b2 = x0 + sizeof(__bf16) * 2 * kResRows * kResX0;   // [K][256] f32
-  static constexpr size_t b3 = b2 + sizeof(float) * kResK * kResH;            // [K][32] f32
-  static constexpr size_t mix = b3 + sizeof(float) * kResK * 32;              // [4] f32
-  static constexpr size_t mu = mix + 16;                                      // [K][8][32] f32
-  static constexpr size_t in = mu + sizeof(float) * kResK * kResRows * 32;    // [3][256] f32
-  static constexpr size_t mt = in + sizeof(float) * 3 * kResIn;               // [2][K][256] f32
-  // Per-step rows of the tile, dense as in HBM: noise, actions, quantities [2][M][D], state
-  // entries [2][M][D+1] (cash, holdings), rewards [2][M]; holdings [M][D].  Sized for D <= 32.
-  static constexpr size_t eps = mt + sizeof(float) * 2 * kResK * kResH;
-  static constexpr size_t act = eps + sizeof(float) * 2 * kResRows * 32;
-  static constexpr size_t qty = act + sizeof(float) * 2 * kResRows * 32;
-  static constexpr size_t env = qty + sizeof(int) * 2 * kResRows * 32;
-  static constexpr size_t rew = res_a16(env + sizeof(float) * 2 * kResRows * 33);
-  static constexpr size_t hold = rew + sizeof(double) * 2 * kResRows;
-  static constexpr size_t state = hold + sizeof(int) * kResRows * 32;         // cash, asset, cumrew [3][8] f64
-  static constexpr size_t total = res_a16(state + sizeof(double) * 3 * kResRows);
-};
-
-// An opaque zero, redefined at every use: addresses derived from it are recomputed where they
-// are used instead of being hoisted out of the step loop.  The resident kernel keeps 384
-// registers of weights live, which leaves no room for loop-invariant temporaries.
-__device__ __forceinline__ int opaque_zero() {
-  int z = 0;
-  asm volatile("" : "+s"(z));
-  return z;
-}
-
-// The resident kernel's LDS regions.
-struct ResView {
-  bf16x8 *w1e, *w3;
-  __bf16 *x1, *x2, *x0;
-  float *b2, *b3, *mix, *mu, *in, *mt, *eps, *act, *env;
-  int *qty, *hold;
-  double *rew, *cash, *asset, *cumrew;
-  unsigned char* scratch;  // the chain's scratch: the layer-1 outputs' region
-  __device__ explicit ResView(unsigned char* p)
-      : w1e(reinterpret_cast<bf16x8*>(p + ResLds::w1e)),
-        w3(reinterpret_cast<bf16x8*>(p + ResLds::w3)),
-        x1(reinterpret_cast<__bf16*>(p + ResLds::x1)),
-        x2(reinterpret_cast<__bf16*>(p + ResLds::x2)),
-        x0(reinterpret_cast<__bf16*>(p + ResLds::x0)),
-        b2(reinterpret_cast<float*>(p + ResLds::b2)),
-        b3(reinterpret_cast<float*>(p + ResLds::b3)),
-        mix(reinterpret_cast<float*>(p + ResLds::mix)),
-        mu(reinterpret_cast<float*>(p + ResLds::mu)),
-        in(reinterpret_cast<float*>(p + ResLds::in)),
-        mt(reinterpret_cast<float*>(p + ResLds::mt)),
-        eps(reinterpret_cast<float*>(p + ResLds::eps)),
-        act(reinterpret_cast<float*>(p + ResLds::act)),
-        env(reinterpret_cast<float*>(p + ResLds::env)),
-        qty(reinterpret_cast<int*>(p + ResLds::qty)),
-        hold(reinterpret_cast<int*>(p + ResLds::hold)),
-        rew(reinterpret_cast<double*>(p + ResLds::rew)),
-        cash(reinterpret_cast<double*>(p + ResLds::state)),
-        asset(reinterpret_cast<double*>(p + ResLds::state) + kResRows),
-        cumrew(reinterpret_cast<double*>(p + ResLds::state) + 2 * kResRows),
-        scratch(p + ResLds::x1) {}
-};
-
-// Step j's inputs into LDS (one wavefront): market rows close[t] | close[t+1] | ind[t+1]
-// (t = t0 + j) and the day's table row.  All loads are issued before the first LDS store.
-__device__ __forceinline__ void res_stage(const ResView& L, const EnvConst& C, const FusedArgs& F, int lane, int j) {
-  constexpr int RM = kResIn / 64, RT = kResK * kResH / 64;
-  const int t = F.t0 + j, D = C.D, I = C.I, n_in = (2 + I) * D;
-  float vm[RM], vt[RT];
-#pragma unroll
-  for (int r = 0; r < RM; ++r) {
-    const int i = lane + 64 * r;
-    float v = 0.0f;
-    if (i < D) v = C.close[static_cast<size_t>(t) * D + i];
-    else if (i < 2 * D) v = C.close[static_cast<size_t>(t + 1) * D + (i - D)];
-    else if (i < n_in) v = C.ind[static_cast<size_t>(t + 1) * I * D + (i - 2 * D)];
-    vm[r] = v;
-  }
-  const float* tb = F.mt + static_cast<size_t>(j) * kResK * kResH;
-#pragma unroll
-  for (int r = 0; r < RT; ++r) vt[r] = tb[lane + 64 * r];
-  float* in = L.in + (j % 3) * kResIn;
-#pragma unroll
-  for (int r = 0; r < RM; ++r) in[lane + 64 * r] = vm[r];
-  float* mt = L.mt + (j & 1) * kResK * kResH;
-#pragma unroll
-  for (int r = 0; r < RT; ++r) mt[lane + 64 * r] = vt[r];
-}
-
-// Noise of step j for the tile (one wavefront): lane l draws block l & 7 of environment l >> 3.
-__device__ __forceinline__ void res_noise(const ResView& L, const EnvConst& C, const FusedArgs& F, int n0, int M,
-                                          int lane, int j) {
-  if (F.sigma == 0.0f) return;
-  const int D = C.D, m = lane >> 3, g = lane & 7;
-  if (m < M && 4 * g < D) {
-    float z[4];
-    noise_block(F.key, static_cast<uint64_t>(F.env_offset + n0 + m), static_cast<uint64_t>(F.t0 + j),
-                static_cast<uint64_t>(g), z);
-    float* e = L.eps + (j & 1) * kResRows * 32 + m * D + 4 * g;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (4 * g + r < D) e[r] = z[r];
-  }
-}
-
-// Step j's results from LDS to the trajectories (one wavefront): part 0 the rewards, 1 the
-// actions and quantities, 2 the state rows.
-__device__ __forceinline__ void res_results(const ResView& L, const EnvConst& C, const FusedArgs& F, int n0, int M,
-                                            int lane, int j, int part) {
-  const int b = j & 1, D = C.D, N = C.N;
-  const size_t row0 = static_cast<size_t>(j) * N + n0;
-  if (part == 0) {
-    if (F.rew_traj && lane < M) F.rew_traj[row0 + lane] = L.rew[b * kResRows + lane];
-  } else if (part == 1) {
-    const float* a = L.act + b * kResRows * 32;
-    const int* q = L.qty + b * kResRows * 32;
-    if (F.act_traj) wave_store_row(F.act_traj + row0 * D, M * D, lane, [&](int e) { return a[e]; });
-    if (F.qty_traj) wave_store_row(F.qty_traj + row0 * D, M * D, lane, [&](int e) { return q[e]; });
-  } else if (F.obs_traj) {
-    store_state_rows(F.obs_traj + row0 * C.S, M, C.S, D, L.env + b * kResRows * 33, D + 1, L.in + (j % 3) * kResIn,
-                     C.price_scale, lane);
-  }
-}
-
-// Epilogue of two 16x16 accumulators whose rows 8-15 repeat rows 0-7: lanes 32-63 of the first
-// take lanes 0-31 of the second, so lane l holds row 4((l & 31) >> 4) + q of the first (l < 32)
-// or second tile, column l & 15; out(q, value) stores it.
-template <class Out>
-__device__ __forceinline__ void res_pair_epilogue(const floatx4& a0, const floatx4& a1, Out out) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(a0[q]), __float_as_uint(a1[q]), false, false);
-    out(q, __uint_as_float(sw[0]));
-  }
-}
-
-__global__ __launch_bounds__(kResThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
-  using SP = Streamed<1, 1, 6, kMlpWaves>;  // the packed-weight offsets of this shape
-  constexpr int K = kResK, H = kResH, KK = kResKK, MR = kResRows;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int D = C.D, N = C.N;
-  const int n0 = blockIdx.x * F.tile_envs;
-  const int M = min(F.tile_envs, N - n0);
-
-  // ---------------------------------------------------------------- set-up
-  // Resident weights: W2 fragments of this wavefront's output tiles into registers.
-  bf16x8 w2[K][KK][4];
-#pragma unroll
-  for (int a = 0; a < K; ++a)
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        w2[a][kk][i] = *reinterpret_cast<const bf16x8*>(
-            E.base + SP::kActor * a + SP::kW2 + static_cast<size_t>((4 * wave + i) * KK + kk) * 1024 + lane * 16);
-  {
-    const ResView L(smem);
-    // W1e and W3 fragments into LDS (the packed layouts, 1 KB per fragment), biases, mixing.
-    for (int f = wave; f < K * 16; f += 4)
-      L.w1e[f * 64 + lane] = *reinterpret_cast<const bf16x8*>(E.base + E.off_w1e + static_cast<size_t>(f) * 1024 + lane * 16);
-    for (int f = wave; f < K * 2 * KK; f += 4) {
-      const int a = f / (2 * KK), r = f - a * 2 * KK;
-      L.w3[f * 64 + lane] = *reinterpret_cast<const bf16x8*>(E.base + SP::kActor * a + SP::kW3 + static_cast<size_t>(r) * 1024 + lane * 16);
-    }
-    for (int i = tid; i < K * H; i += kResThreads) {
-      const int a = i / H, c = i - a * H;
-      L.b2[i] = *reinterpret_cast<const float*>(E.base + SP::kActor * a + SP::kB2 + 4 * c);
-    }
-    for (int i = tid; i < K * 32; i += kResThreads) {
-      const int a = i / 32, c = i - a * 32;
-      L.b3[i] = *reinterpret_cast<const float*>(E.base + SP::kActor * a + SP::kB3 + 4 * c);
-    }
-    if (tid < K) L.mix[tid] = E.mix[tid];
-    // State rows: both buffers zero (padding and absent environments stay zero), noise zero.
-    for (int i = tid; i < 2 * MR * kResX0; i += kResThreads) L.x0[i] = static_cast<__bf16>(0.0f);
-    for (int i = tid; i < 2 * MR * 32; i += kResThreads) L.eps[i] = 0.0f;
-    __syncthreads();
-    // The trading state, and the first rows' cash and holdings entries.
-    if (tid < M) {
-      const int n = n0 + tid;
-      L.cash[tid] = st.cash[n];
-      L.asset[tid] = st.asset[n];
-      L.cumrew[tid] = st.cumrew[n];
-      L.x0[tid * kResX0] = static_cast<__bf16>(static_cast<float>(st.cash[n] * static_cast<double>(C.cash_scale)));
-    }
-    for (int i = tid; i < M * D; i += kResThreads) {
-      const int m = i / D, d = i - m * D;
-      const int h = st.hold[static_cast<size_t>(d) * N + n0 + m];
-      L.hold[i] = h;
-      L.x0[m * kResX0 + 1 + d] = static_cast<__bf16>(static_cast<float>(h) * C.hold_scale);
-    }
-    if (wave == 2) res_stage(L, C, F, lane, 0);
-    if (wave == 1) res_noise(L, C, F, n0, M, lane, 0);
-    __syncthreads();
-  }
-
-  for (int it = 0; it < F.n_steps; ++it) {
-    const int b = it & 1;
-    const ResView L(smem + opaque_zero());
-    const int ln = lane + opaque_zero();
-    const int arow = ln & 7, agrp = ln >> 4;                            // A-fragment row (8-15 repeat 0-7), k group
-    const int prow = (ln & 31) >> 4, half = ln >> 5, pcol = ln & 15;    // packed accumulator lanes
-    // ------------------------------------------------------------ L1: per-environment rows
-    {
-      const bf16x8 A = *reinterpret_cast<const bf16x8*>(L.x0 + b * MR * kResX0 + arow * kResX0 + 8 * agrp);
-      const float* tb = L.mt + b * K * H;
-#pragma unroll
-      for (int a = 0; a < K; ++a) {
-        floatx4 acc[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          acc[i] = mfma_bf16(A, L.w1e[(a * 16 + 4 * wave + i) * 64 + ln], floatx4{0.0f, 0.0f, 0.0f, 0.0f});
-        __bf16* out = L.x1 + a * MR * kResXS;
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-          const int col = 16 * (4 * wave + 2 * p + half) + pcol;
-          const float bc = tb[a * H + col];
-          res_pair_epilogue(acc[2 * p], acc[2 * p + 1], [&](int q, float v) {
-            out[(4 * prow + q) * kResXS + col] = static_cast<__bf16>(fast_tanh(v + bc));
-          });
-        }
-      }
-    }
-    __syncthreads();  // 1: layer-1 outputs complete
-    // ------------------------------------------------------------ L2: weights in registers
-#pragma unroll
-    for (int a = 0; a < K; ++a) {
-      floatx4 acc[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-      const __bf16* src = L.x1 + a * MR * kResXS + arow * kResXS + 8 * agrp;
-#pragma unroll
-      for (int kk = 0; kk < KK; ++kk) {
-        const bf16x8 A = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = mfma_bf16(A, w2[a][kk][i], acc[i]);
-      }
-      __bf16* out = L.x2 + a * MR * kResXS;
-#pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const int col = 16 * (4 * wave + 2 * p + half) + pcol;
-        const float bc = L.b2[a * H + col];
-        res_pair_epilogue(acc[2 * p], acc[2 * p + 1], [&](int q, float v) {
-          out[(4 * prow + q) * kResXS + col] = static_cast<__bf16>(fast_tanh(v + bc));
-        });
-      }
-    }
-    __syncthreads();  // 2: layer-2 outputs complete
-    // ------------------------------------------------------------ L3: actor a on wavefront a
-    if (wave < K) {
-      const int a = wave;
-      floatx4 acc[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
-      const __bf16* src = L.x2 + a * MR * kResXS + arow * kResXS + 8 * agrp;
-#pragma unroll
-      for (int kk = 0; kk < KK; ++kk) {
-        const bf16x8 A = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
-#pragma unroll
-        for (int c = 0; c < 2; ++c) acc[c] = mfma_bf16(A, L.w3[((a * 2 + c) * KK + kk) * 64 + ln], acc[c]);
-      }
-      const int col = 16 * half + pcol;
-      const float bc = L.b3[a * 32 + col], wk = L.mix[a];
-      float* out = L.mu + a * MR * 32;
-      res_pair_epilogue(acc[0], acc[1], [&](int q, float v) { out[(4 * prow + q) * 32 + col] = wk * fast_tanh(v + bc); });
-    } else if (it >= 1) {
-      res_results(L, C, F, n0, M, ln, it - 1, 2);  // the previous step's state rows
-    }
-    __syncthreads();  // 3: the actors' weighted means complete
-    if (wave == 0) {
-      // -------------------------------------------------------- the trading chain
-      const ChainShape Z = ChainShape::of(D);
-      const float* in = L.in + (it % 3) * kResIn;
-      ChainLds CL;
-      CL.carve_scratch(L.scratch, Z, MR);  // the layer-1 outputs are dead until the next step
-      CL.act = nullptr;
-      CL.hold = L.hold;
-      CL.qty = L.qty + b * MR * 32;
-      CL.env = L.env + b * MR * 33;
-      CL.px = in;
-      CL.pn = in + D;
-      float* actb = L.act + b * MR * 32;
-      const float* eps = L.eps + b * MR * 32;
-      const float* mu = L.mu;
-      const float sigma = F.sigma;
-      chain_day_terms(CL, Z, ln, 64, C.one_p);
-      chain_pairs_a(CL, Z, M, ln, 64, C.hmax_f, C.one_m, C.one_p, [&](int m, int d, int e) {
-        // a_bar = sum_k w_k mu_k in actor order, then the noise and the clip.
-        const float* mk = mu + m * 32 + d;
-        float a = mk[0];
-        a = a + mk[MR * 32];
-        a = a + mk[2 * MR * 32];
-        if (sigma != 0.0f) a = a + sigma * eps[e];
-        a = fminf(fmaxf(a, -1.0f), 1.0f);
-        actb[e] = a;
-        return a;
-      });
-      wave_lds_sync();
-      if (ln < M) {
-        double cash = L.cash[ln];
-        chain_serial<4, false>(cash, CL.pro + ln * Z.RD, CL.deb + ln * Z.RD, CL.c1, CL.rc1, CL.qd + ln * Z.RI, in,
-                               CL.kq + ln * Z.RI, Z.DP, C.one_p);
-        L.cash[ln] = cash;
-      }
-      wave_lds_sync();
-      __bf16* xn = L.x0 + (b ^ 1) * MR * kResX0;
-      chain_pairs_c(CL, Z, M, ln, 64, C.hold_scale,
-                    [&](int m, int d, float he) { xn[m * kResX0 + 1 + d] = static_cast<__bf16>(he); });
-      wave_lds_sync();
-      if (ln < M) {
-        const double cash = L.cash[ln];
-        const double v_new = chain_value<4>(cash, CL.val + ln * Z.RD, Z.DP);
-        const double r = (v_new - L.asset[ln]) * C.reward_scale;
-        L.cumrew[ln] = L.cumrew[ln] + r;
-        L.asset[ln] = v_new;
-        const float ce = static_cast<float>(cash * static_cast<double>(C.cash_scale));
-        CL.env[ln * (D + 1)] = ce;
-        xn[ln * kResX0] = static_cast<__bf16>(ce);
-        L.rew[b * MR + ln] = r;
-      }
-    } else if (wave == 1) {
-      if (it + 1 < F.n_steps) res_noise(L, C, F, n0, M, ln, it + 1);
-      if (it >= 1) res_results(L, C, F, n0, M, ln, it - 1, 0);
-    } else if (wave == 2) {
-      if (it >= 1) res_results(L, C, F, n0, M, ln, it - 1, 1);
-      if (it + 1 < F.n_steps) res_stage(L, C, F, ln, it + 1);
-    }
-    __syncthreads();  // 4: the next state rows and inputs are staged
-  }
-  // The last step's results, then the trading state back to HBM.
-  const ResView L(smem);
-  if (F.n_steps >= 1 && wave != 2) res_results(L, C, F, n0, M, lane, F.n_steps - 1, wave == 0 ? 0 : (wave == 1 ? 1 : 2));
-  if (tid < M) {
-    const int n = n0 + tid;
-    st.cash[n] = L.cash[tid];
-    st.asset[n] = L.asset[tid];
-    st.cumrew[n] = L.cumrew[tid];
-  }
-  for (int i = tid; i < M * D; i += kResThreads) {
-    const int m = i / D, d = i - m * D;
-    st.hold[static_cast<size_t>(d) * N + n0 + m] = L.hold[i];
-  }
-}
-
 // One tile (16*ROWT environments starting at tile*16*ROWT) through the steps of F, generic
 // schedule: the body of the generic kernel and of the batched persistent kernel.
 template <int ROWT, int TMAX>
@@ -1359,21 +963,11 @@ hipError_t launch_streamed(const EnvConst& C, const EnvState& st, const EnsDev& 
                            float* eps_chunk, float* mt_chunk, hipStream_t stream) {
   const int t_end = F.t0 + F.n_steps;
   const size_t N = C.N, D = C.D, S = C.S;
-  const int Fm = (1 + C.I) * C.D;
   for (int t = F.t0; t < t_end; t += kFusedChunk) {
     const int n = t_end - t < kFusedChunk ? t_end - t : kFusedChunk;
     const size_t i0 = static_cast<size_t>(t - F.t0);
-    hipLaunchKernelGGL(market_table_kernel, dim3(n, E.K), dim3(kStreamH), sizeof(float) * Fm, stream, C, E, t,
-                       mt_chunk);
-    hipError_t err = hipGetLastError();
+    hipError_t err = launch_chunk_inputs(C, E, t, n, F.sigma, F.key, F.env_offset, eps_chunk, mt_chunk, stream);
     if (err != hipSuccess) return err;
-    if (F.sigma != 0.0f) {
-      const size_t total = static_cast<size_t>(n) * N * ((D + 3) / 4);
-      hipLaunchKernelGGL(noise_chunk_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream,
-                         F.key, F.env_offset, t, n, C.N, C.D, eps_chunk);
-      err = hipGetLastError();
-      if (err != hipSuccess) return err;
-    }
     FusedArgs Fc = F;
     Fc.t0 = t;
     Fc.n_steps = n;
@@ -1393,46 +987,20 @@ hipError_t launch_streamed(const EnvConst& C, const EnvState& st, const EnsDev& 
   return hipSuccess;
 }
 
-// The resident schedule over a rollout: per chunk of at most kFusedChunk steps, the chunk's
-// market table, then the resident kernel for the chunk's steps (it draws its own noise).
-hipError_t launch_resident(const EnvConst& C, const EnvState& st, const EnsDev& E, FusedArgs F, float* mt_chunk,
-                           hipStream_t stream) {
-  if (F.tile_envs < 1 || F.tile_envs > kResRows) return hipErrorInvalidValue;
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(fused_resident_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(ResLds::total));
-  if (err != hipSuccess) return err;
-  const int t_end = F.t0 + F.n_steps;
-  const size_t N = C.N, D = C.D, S = C.S;
-  const int Fm = (1 + C.I) * C.D;
-  const int grid = (C.N + F.tile_envs - 1) / F.tile_envs;
-  for (int t = F.t0; t < t_end; t += kFusedChunk) {
-    const int n = t_end - t < kFusedChunk ? t_end - t : kFusedChunk;
-    const size_t i0 = static_cast<size_t>(t - F.t0);
-    hipLaunchKernelGGL(market_table_kernel, dim3(n, E.K), dim3(kStreamH), sizeof(float) * Fm, stream, C, E, t,
-                       mt_chunk);
-    err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    FusedArgs Fc = F;
-    Fc.t0 = t;
-    Fc.n_steps = n;
-    Fc.eps = nullptr;
-    Fc.mt = mt_chunk;
-    Fc.obs_traj = F.obs_traj ? F.obs_traj + i0 * N * S : nullptr;
-    Fc.act_traj = F.act_traj ? F.act_traj + i0 * N * D : nullptr;
-    Fc.rew_traj = F.rew_traj ? F.rew_traj + i0 * N : nullptr;
-    Fc.qty_traj = F.qty_traj ? F.qty_traj + i0 * N * D : nullptr;
-    hipLaunchKernelGGL(fused_resident_kernel, dim3(grid), dim3(kResThreads), ResLds::total, stream, C, st, E, Fc);
-    err = hipGetLastError();
-    if (err != hipSuccess) return err;
-  }
-  return hipSuccess;
-}
 
 }  // namespace
 
-bool fused_resident_shape(const EnvConst& C, const EnsDev& E) {
-  return fused_streamed_shape(C, E) && C.D <= 31 && E.ke_pad == 32 && (2 + C.I) * C.D <= kResIn &&
-         ResLds::total <= 160 * 1024;
+
+hipError_t launch_chunk_inputs(const EnvConst& C, const EnsDev& E, int t, int n, float sigma, uint64_t key,
+                               int64_t env_offset, float* eps_chunk, float* mt_chunk, hipStream_t stream) {
+  const int Fm = (1 + C.I) * C.D;
+  hipLaunchKernelGGL(market_table_kernel, dim3(n, E.K), dim3(kStreamH), sizeof(float) * Fm, stream, C, E, t, mt_chunk);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || sigma == 0.0f) return err;
+  const size_t total = static_cast<size_t>(n) * C.N * ((C.D + 3) / 4);
+  hipLaunchKernelGGL(noise_chunk_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream, key,
+                     env_offset, t, n, C.N, C.D, eps_chunk);
+  return hipGetLastError();
 }
 
 bool fused_streamed_shape(const EnvConst& C, const EnsDev& E) {
@@ -1522,7 +1090,7 @@ hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const Ens
           hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
         F.tile_envs = std::max(1, std::min(kResRows, (C.N + cus - 1) / cus));
     }
-    return launch_resident(C, st, E, F, mt_chunk, stream);
+    return launch_resident(C, st, E, F, eps_chunk, mt_chunk, stream);
   }
   if (tune.schedule != 2 && fused_streamed_shape(C, E))
     return launch_streamed(C, st, E, F, rowt, eps_chunk, mt_chunk, stream);
