@@ -54,6 +54,21 @@ fm_status fm_policy_gradient(int32_t K, int32_t S, int32_t H, int32_t A, const f
                              float sigma, uint64_t noise_key, int64_t env_offset, int32_t t0, float lambda_kl,
                              float* d_grad, void* d_workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under stream or graph capture, serving
+ * loops that must not allocate, harnesses that forbid it): fm_policy_gradient with its workspace
+ * in device memory the library holds -- one array of FM_PG_NOALLOC_MAX_BYTES per device, kept
+ * until the process ends -- instead of d_workspace.  Same arguments, results and errors as
+ * fm_policy_gradient; FM_ERR_INVALID if fm_pg_workspace_bytes(K, S, H, A, N, T) exceeds
+ * FM_PG_NOALLOC_MAX_BYTES (about 13,000 sample rows at 211-256-256-30, K = 3).  Allocates nothing
+ * (no device or pinned memory, no library allocator).  Every call on a device uses that device's
+ * one array: calls that overlap on one device (other streams, other host threads) race and must be
+ * serialised by the caller. */
+#define FM_PG_NOALLOC_MAX_BYTES ((size_t)32 << 20)
+fm_status fm_policy_gradient_noalloc(int32_t K, int32_t S, int32_t H, int32_t A, const float* d_w,
+                                     const float* h_mix, int32_t agent, const float* d_states, const double* d_rew,
+                                     int32_t N, int32_t T, float sigma, uint64_t noise_key, int64_t env_offset,
+                                     int32_t t0, float lambda_kl, float* d_grad, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

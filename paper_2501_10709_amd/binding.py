@@ -26,6 +26,7 @@ EXPORTS = (
     "fm_batch_run",
     "fm_batch_destroy", "fm_serve_request_bytes", "fm_serve_workspace_bytes", "fm_serve_create", "fm_serve_submit",
     "fm_serve_step", "fm_serve_poll", "fm_serve_destroy", "fm_pg_workspace_bytes", "fm_policy_gradient",
+    "fm_policy_gradient_noalloc",
 )
 FM_RULE_AVG_SOFTMAX, FM_RULE_MAJORITY_VOTE = 0, 1
 
@@ -140,6 +141,8 @@ def load(path: str = LIB_PATH):
         "fm_pg_workspace_bytes": (SZ, [I32, I32, I32, I32, I32, I32]),
         "fm_policy_gradient": (I32, [I32, I32, I32, I32, P, P, I32, P, P, I32, I32, ctypes.c_float, U64, I64,
                                      I32, ctypes.c_float, P, P, SZ, P]),
+        "fm_policy_gradient_noalloc": (I32, [I32, I32, I32, I32, P, P, I32, P, P, I32, I32, ctypes.c_float, U64,
+                                             I64, I32, ctypes.c_float, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -444,3 +447,20 @@ def fm_policy_gradient(K, S, H, A, d_w, agent, d_states, d_rew, N, T, sigma, noi
         _ptr(d_grad, torch.float32, per, "d_grad"),
         _ptr(d_workspace, None, None, "d_workspace"), d_workspace.numel() * d_workspace.element_size(),
         _stream(stream)))
+
+
+def fm_policy_gradient_noalloc(K, S, H, A, d_w, agent, d_states, d_rew, N, T, sigma, noise_key, env_offset, lambda_kl,
+                               d_grad, mix=None, stream=None, t0=0):
+    """fm_policy_gradient with the library's own device scratch instead of a workspace argument
+    (for callers that cannot allocate; at most FM_PG_NOALLOC_MAX_BYTES of workspace)."""
+    import numpy as np
+    import torch
+    h_mix = None
+    if mix is not None:
+        h_mix = np.ascontiguousarray(mix, dtype=np.float32)
+    per = S * H + H + H * H + H + H * A + A
+    _check(load().fm_policy_gradient_noalloc(
+        K, S, H, A, _ptr(d_w, torch.float32, K * per, "d_w"), None if h_mix is None else h_mix.ctypes.data, agent,
+        _ptr(d_states, torch.float32, T * N * S, "d_states"), _ptr(d_rew, torch.float64, T * N, "d_rew"), N, T,
+        float(sigma), int(noise_key), int(env_offset), int(t0), float(lambda_kl),
+        _ptr(d_grad, torch.float32, per, "d_grad"), _stream(stream)))

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "../../include/learner.h"
@@ -422,6 +423,50 @@ fm_status fm_policy_gradient(int32_t K, int32_t S, int32_t H, int32_t A, const f
   if (e == hipSuccess) e = weight_grad(L, d_states, S, S, x1, H, P, d_grad + oW1, stream);
   if (e != hipSuccess) return fm::device_error(e, "fm_policy_gradient (backward)");
   return FM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// The allocation-free variant: the same computation with its workspace in a file-scope device
+// array instead of a caller buffer.  Each device the library runs on holds its own copy of the
+// array; its address is looked up once per device (the array's name is a host-side stand-in, not
+// a device address) and kept.  Every call on a device shares that device's array, so calls that
+// overlap on one device race.  The workspace needs no clearing: every region is written before
+// it is read within a call.
+// ------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[FM_PG_NOALLOC_MAX_BYTES];
+
+fm_status fm_policy_gradient_noalloc(int32_t K, int32_t S, int32_t H, int32_t A, const float* d_w, const float* h_mix,
+                                     int32_t agent, const float* d_states, const double* d_rew, int32_t N, int32_t T,
+                                     float sigma, uint64_t noise_key, int64_t env_offset, int32_t t0, float lambda_kl,
+                                     float* d_grad, hipStream_t stream) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  const size_t need = fm_pg_workspace_bytes(K, S, H, A, N, T);
+  if (need == 0)
+    return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient_noalloc: sizes out of range (K 1..8, S/H 1..1024, A 1..128, N*T <= 2^26)");
+  if (need > FM_PG_NOALLOC_MAX_BYTES)
+    return fm::set_error(FM_ERR_INVALID, "fm_policy_gradient_noalloc: the problem needs " + std::to_string(need) +
+                                             " bytes of workspace, more than the " +
+                                             std::to_string(FM_PG_NOALLOC_MAX_BYTES) + " the library holds");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fm::device_error(e, "fm_policy_gradient_noalloc (hipGetDevice)");
+  if (dev < 0 || dev >= kMaxDevices) return fm::set_error(FM_ERR_UNSUPPORTED, "fm_policy_gradient_noalloc: device index above 63");
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+      void* p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) return fm::device_error(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                         "fm_policy_gradient_noalloc (hipGetSymbolAddress)");
+      addr[dev] = p;
+    }
+    ws = addr[dev];
+  }
+  return fm_policy_gradient(K, S, H, A, d_w, h_mix, agent, d_states, d_rew, N, T, sigma, noise_key, env_offset, t0,
+                            lambda_kl, d_grad, ws, FM_PG_NOALLOC_MAX_BYTES, stream);
 }
 
 }  // extern "C"
