@@ -125,15 +125,6 @@ __device__ __forceinline__ double row_sum(double acc, double v) {
   return row_sum_impl(acc, v, std::make_integer_sequence<int, 16>());
 }
 
-template <class Fn, int... I>
-__device__ __forceinline__ void static_for_impl(Fn&& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>()), ...);
-}
-template <int N, class Fn>
-__device__ __forceinline__ void static_for(Fn&& f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>());
-}
-
 // One stock's buy terms, owned by one lane of the row: the whole order's debit (p q)(1+c), the
 // one-share debit (p 1)(1+c), and the price and order packed as {float bits, int}.
 struct BuySet {
@@ -167,69 +158,173 @@ __device__ __forceinline__ int partial_fill_sel(double cash, double p, double c1
   return fp ? k + 1 : (f0 ? k : (k >= 1 ? k - 1 : 0));
 }
 
-// Buy of stock N of the row's environment (Section 3.1, readings 5-7), every lane of the row
-// computing the same recurrence on terms broadcast from the lane that owns the stock; lane j
-// keeps the fills of stocks j and j + 16 in k[0], k[1].  A buy fills whole when its debit fits
-// the cash and not at all when one share does not (selects); the partial fill is evaluated, for
-// the whole wavefront, only at a stock where some row needs it.
-template <int N>
-__device__ __forceinline__ void buy_stock(double& cash, int (&k)[2], int j, const BuySet (&B)[2], double one_p) {
+// acc - v(lane 0) - v(lane 1) - ... - v(lane 15) of the row, in lane order.
+template <int... L>
+__device__ __forceinline__ double row_sub_impl(double acc, double v, std::integer_sequence<int, L...>) {
 #pragma clang fp contract(off)
-  constexpr int s = N / 16, L = N % 16;
-  const double deb = row_bcast<L>(B[s].deb), c1 = row_bcast<L>(B[s].c1);
-  const long pq = row_bcast<L>(B[s].pq);
-  const bool fits = deb <= cash;
-  const bool need = !fits && c1 <= cash;
-  int kj = fits ? pq_order(pq) : 0;
-  double debit = fits ? deb : 0.0;
-  if (__builtin_amdgcn_ballot_w64(need) != 0) {
-    bool ok = true;
-    double dpart;
-    const int kp = partial_fill_sel(cash, static_cast<double>(pq_price(pq)), c1, pq_order(pq), one_p, dpart, ok);
-    if (need) {
-      kj = kp;
-      debit = dpart;
-    }
-    if (__builtin_amdgcn_ballot_w64(need && !ok) != 0) {
-      if (need && !ok) {
+  ((acc = acc - row_bcast<L>(v)), ...);
+  return acc;
+}
+
+// The buys of the wavefront's two environments (Section 3.1, readings 5-7).
+// If every row's cash covers the sum of its whole orders with a margin far above the rounding of
+// 32 subtractions, every whole order fits in sequence: the debits are subtracted in stock order
+// and every order fills.  Otherwise the buys run as a sequence of events, both rows in step: with
+// cash C, the next stock (in ascending order) that can change anything is the first one with a
+// buy order whose one-share debit fits C -- the stocks before it fill nothing and leave C as it
+// is.  A ballot per stock slot finds each row's next event; the lane owning that stock fills it
+// (the whole order if its debit fits C, else the partial fill) and keeps the fill, and its debit
+// reaches the rest of the row by a lane permute.
+__device__ __forceinline__ void buy_all(double& cash, int (&kown)[2], int lane, const BuySet (&B)[2], double one_p) {
+#pragma clang fp contract(off)
+  const int jl = lane & 15, rl = (lane >> 4) & 1, rbase = lane & 48;
+  const double total = row_sum(0.0, B[0].deb + B[1].deb);  // any order: only a bound
+  if (__builtin_amdgcn_ballot_w64(!(cash >= total * (1.0 + 0x1p-40))) == 0) {
+    cash = row_sub_impl(cash, B[0].deb, std::make_integer_sequence<int, 16>());
+    cash = row_sub_impl(cash, B[1].deb, std::make_integer_sequence<int, 16>());
+    kown[0] = pq_order(B[0].pq);
+    kown[1] = pq_order(B[1].pq);
+    return;
+  }
+  const bool buy0 = pq_order(B[0].pq) > 0, buy1 = pq_order(B[1].pq) > 0;
+  int dn = 0;  // the row's next stock to consider
+  for (int it = 0; it < 32; ++it) {
+    const unsigned long long b0 = __builtin_amdgcn_ballot_w64(buy0 && B[0].c1 <= cash && jl >= dn);
+    const unsigned long long b1 = __builtin_amdgcn_ballot_w64(buy1 && B[1].c1 <= cash && jl + 16 >= dn);
+    const unsigned m0 = static_cast<unsigned>(b0 & 0xffffu) | (static_cast<unsigned>(b1 & 0xffffu) << 16);
+    const unsigned m1 = static_cast<unsigned>((b0 >> 16) & 0xffffu) | (static_cast<unsigned>((b1 >> 16) & 0xffffu) << 16);
+    if ((m0 | m1) == 0) break;
+    const unsigned mine = rl == 0 ? m0 : m1;
+    const int e = mine != 0 ? __builtin_ctz(mine) : 64;  // the row's event stock (64: none)
+    const bool hi = e >= 16;
+    const bool owner = (e & 15) == jl && e < 32;
+    // The owner's fill of stock e: whole, or partial when only part of the order fits.
+    const double deb = hi ? B[1].deb : B[0].deb;
+    const long pq = hi ? B[1].pq : B[0].pq;
+    const bool fits = deb <= cash;
+    int k = fits ? pq_order(pq) : 0;
+    double debit = fits ? deb : 0.0;
+    if (owner && !fits) {
+      const double c1 = hi ? B[1].c1 : B[0].c1;
+      bool ok = true;
+      k = partial_fill_sel(cash, static_cast<double>(pq_price(pq)), c1, pq_order(pq), one_p, debit, ok);
+      if (!ok) {
         double rc1 = __builtin_amdgcn_rcp(c1);
         rc1 = fma(fma(-c1, rc1, 1.0), rc1, rc1);
-        kj = partial_fill(cash, static_cast<double>(pq_price(pq)), rc1, pq_order(pq), one_p, debit);
+        k = partial_fill(cash, static_cast<double>(pq_price(pq)), rc1, pq_order(pq), one_p, debit);
       }
     }
+    if (owner) kown[hi ? 1 : 0] = k;
+    const int src = rbase + (e & 15);
+    const long dbits = __builtin_bit_cast(long, debit);
+    const int lo = __builtin_amdgcn_ds_bpermute(4 * src, static_cast<int>(dbits));
+    const int hb = __builtin_amdgcn_ds_bpermute(4 * src, static_cast<int>(dbits >> 32));
+    const double d_e = __builtin_bit_cast(
+        double, static_cast<long>((static_cast<unsigned long>(static_cast<unsigned>(hb)) << 32) | static_cast<unsigned>(lo)));
+    if (e < 32) {
+      cash = cash - d_e;
+      dn = e + 1;
+    }
   }
-  cash = cash - debit;
-  k[s] = j == L ? kj : k[s];
 }
 
-// Stocks 4C .. 4C+3, unless no row of the wavefront can still buy: once the cash is below the
-// day's lowest price (a lower bound of every one-share debit), no later order fills even in
-// part, and the remaining stocks leave cash and fills unchanged.
-template <int C>
-__device__ __forceinline__ void buy_chunk(double& cash, int (&k)[2], int j, const BuySet (&B)[2], double one_p,
-                                          double p_min, bool& live) {
-  if (!live) return;
-  buy_stock<4 * C>(cash, k, j, B, one_p);
-  buy_stock<4 * C + 1>(cash, k, j, B, one_p);
-  buy_stock<4 * C + 2>(cash, k, j, B, one_p);
-  buy_stock<4 * C + 3>(cash, k, j, B, one_p);
-  live = __builtin_amdgcn_ballot_w64(cash >= p_min) != 0;
+// Trajectory stores go through buffer resources that cover the tile's rows of one step: a lane
+// with nothing to store passes an offset beyond the range, which the hardware drops, so the
+// stores need no branches; a trajectory that is not requested gets an empty range.
+constexpr int kNoStore = 0x7ffffff0;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const void* base, size_t elem_offset, size_t elem_bytes,
+                                                            int n_elems) {
+  if (!base) return __builtin_amdgcn_make_buffer_rsrc(nullptr, 0, 0, 0x00020000);
+  return __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char*>(static_cast<const char*>(base)) + elem_offset * elem_bytes, 0,
+      static_cast<int>(elem_bytes * n_elems), 0x00020000);
+}
+__device__ __forceinline__ void store_f32(__amdgpu_buffer_rsrc_t r, int byte_off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, byte_off, 0, 0);
+}
+// A load through such a resource returns 0 beyond its range.
+__device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
 }
 
-template <int... C>
-__device__ __forceinline__ void buy_all(double& cash, int (&k)[2], int j, const BuySet (&B)[2], double one_p,
-                                        double p_min, std::integer_sequence<int, C...>) {
-  bool live = __builtin_amdgcn_ballot_w64(cash >= p_min) != 0;
-  (buy_chunk<C>(cash, k, j, B, one_p, p_min, live), ...);
+// The three layers of one step for the wavefront's tiles.  Lane l's B operand is activation
+// row l mod 8 (the environment), entries 8(l/16) .. +7 of each 32-entry k-step; after a merge,
+// lane l holds tile (l / 8) mod 2 of a pair, environment l mod 8, units 4(l/16) .. +3.  The LDS
+// regions are passed as distinct (restrict) pointers, so the compiler may move the loads of
+// later tiles above the stores of earlier ones.
+__device__ __forceinline__ void layer1(const bf16x8* __restrict__ w1e, const float* __restrict__ mt,
+                                       const __bf16* __restrict__ x0, __bf16* __restrict__ x1, int wave, int lane) {
+  constexpr int K = kRK, H = kRH, MR = kResRows;
+  const int bev = lane & 7, bgrp = lane >> 4, pair_t = (lane >> 3) & 1;
+  const bf16x8 X = *reinterpret_cast<const bf16x8*>(x0 + bev * kRX0 + 8 * bgrp);
+#pragma unroll
+  for (int a = 0; a < K; ++a) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      floatx4 acc[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = 4 * wave + 2 * p + h;
+        acc[h] = mfma_bf16(w1e[(a * 16 + c) * 64 + lane], X,
+                           *reinterpret_cast<const floatx4*>(mt + a * H + 16 * c + 4 * bgrp));
+      }
+      const floatx4 v = merge_tiles(acc[0], acc[1]);
+      const int u0 = 16 * (4 * wave + 2 * p + pair_t) + 4 * bgrp;
+      *reinterpret_cast<uint2*>(x1 + a * MR * kRXS + bev * kRXS + u0) =
+          pack_bf16x4(tanh_sig(v[0]), tanh_sig(v[1]), tanh_sig(v[2]), tanh_sig(v[3]));
+    }
+  }
 }
 
-// Minimum over the 16 lanes of each row (DPP row rotations).
-__device__ __forceinline__ float row_min(float v) {
-  v = fminf(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false));  // row_ror:8
-  v = fminf(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xf, 0xf, false));  // row_ror:4
-  v = fminf(v, __builtin_amdgcn_update_dpp(v, v, 0x122, 0xf, 0xf, false));  // row_ror:2
-  v = fminf(v, __builtin_amdgcn_update_dpp(v, v, 0x121, 0xf, 0xf, false));  // row_ror:1
-  return v;
+__device__ __forceinline__ void layer2(const bf16x8 (&w2)[kRK][kRKK][4], const float* __restrict__ b2,
+                                       const __bf16* __restrict__ x1, __bf16* __restrict__ x2, int wave, int lane) {
+  constexpr int K = kRK, H = kRH, KK = kRKK, MR = kResRows;
+  const int bev = lane & 7, bgrp = lane >> 4, pair_t = (lane >> 3) & 1;
+#pragma unroll
+  for (int a = 0; a < K; ++a) {
+    const __bf16* src = x1 + a * MR * kRXS + bev * kRXS + 8 * bgrp;
+    bf16x8 X[KK];
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) X[kk] = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
+    floatx4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      acc[i] = mfma_bf16(w2[a][0][i], X[0], *reinterpret_cast<const floatx4*>(b2 + a * H + 16 * (4 * wave + i) + 4 * bgrp));
+#pragma unroll
+    for (int kk = 1; kk < KK; ++kk)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] = mfma_bf16(w2[a][kk][i], X[kk], acc[i]);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const floatx4 v = merge_tiles(acc[2 * p], acc[2 * p + 1]);
+      const int u0 = 16 * (4 * wave + 2 * p + pair_t) + 4 * bgrp;
+      *reinterpret_cast<uint2*>(x2 + a * MR * kRXS + bev * kRXS + u0) =
+          pack_bf16x4(tanh_sig(v[0]), tanh_sig(v[1]), tanh_sig(v[2]), tanh_sig(v[3]));
+    }
+  }
+}
+
+// Actor a = wave's two output tiles, w_a tanh(z + b3_a) into mu[a][env][dim].
+__device__ __forceinline__ void layer3(const bf16x8* __restrict__ w3, const float* __restrict__ b3,
+                                       const float* __restrict__ mix, const __bf16* __restrict__ x2,
+                                       float* __restrict__ mu, int wave, int lane) {
+  constexpr int KK = kRKK, MR = kResRows;
+  const int bev = lane & 7, bgrp = lane >> 4, pair_t = (lane >> 3) & 1;
+  const int a = wave;
+  const __bf16* src = x2 + a * MR * kRXS + bev * kRXS + 8 * bgrp;
+  floatx4 acc[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) acc[h] = *reinterpret_cast<const floatx4*>(b3 + a * 32 + 16 * h + 4 * bgrp);
+#pragma unroll
+  for (int kk = 0; kk < KK; ++kk) {
+    const bf16x8 X = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) acc[h] = mfma_bf16(w3[((a * 2 + h) * KK + kk) * 64 + lane], X, acc[h]);
+  }
+  const floatx4 v = merge_tiles(acc[0], acc[1]);
+  const float wk = mix[a];
+  *reinterpret_cast<float4*>(mu + a * MR * 32 + bev * 32 + 16 * pair_t + 4 * bgrp) =
+      float4{wk * tanh_sig(v[0]), wk * tanh_sig(v[1]), wk * tanh_sig(v[2]), wk * tanh_sig(v[3])};
 }
 
 __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(1, 1)))
@@ -327,6 +422,24 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
   }
   __syncthreads();
 
+  // The market entries (closes, indicators) of step jj's state rows, from its market rows in LDS:
+  // they do not depend on the trades, so they are stored at the start of the next step (and after
+  // the loop for the last step).  Wavefront w stores environments 2w, 2w+1, 32 lanes each.
+  auto store_market = [&](int jj, const float* in_jj, int lane_) {
+    const int e = 2 * wave + (lane_ >> 5), t32 = lane_ & 31;
+    const __amdgpu_buffer_rsrc_t r = rows_rsrc(F.obs_traj, (static_cast<size_t>(jj) * N + n0) * S, 4, M * S);
+    const int base = e < M ? 4 * (e * S + 1 + t32) : kNoStore;  // entry 1 + u of row e, u = t32 + 32 k
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = in_jj[min(D + t32 + 32 * k, kRIn - 1)];  // (1 + I) D <= 255
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int u = t32 + 32 * k;
+      // Closes (u < D) at entries 1 .. D, scaled; indicators (D <= u < (1 + I) D) at 1 + 2D ...
+      const int off = base + 4 * (32 * k + (D & -static_cast<int>(u >= D)));
+      store_f32(r, u < n_mkt ? off : kNoStore, u < D ? v[k] * C.price_scale : v[k]);
+    }
+  };
   for (int j = 0; j < F.n_steps; ++j) {
     const int b = j & 1;
     const bool nxt = j + 1 < F.n_steps;
@@ -350,87 +463,37 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
     // This step's noise and the next step's inputs, requested now, used after the MLP.
     const int m = 2 * wave + ((lane >> 4) & 1), jl = lane & 15;
     const bool env_ok = m < M;
-    float eps[2] = {0.0f, 0.0f};
-    if (env_ok && F.sigma != 0.0f) {
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-        if (jl + 16 * s < D) eps[s] = F.eps[(static_cast<size_t>(j) * N + n0 + m) * D + jl + 16 * s];
-    }
-    float p_in = 0.0f, p_mt[K] = {0.0f, 0.0f, 0.0f};
-    if (nxt) {
-      p_in = load_in(F.t0 + j + 1);
-#pragma unroll
-      for (int r = 0; r < K; ++r) p_mt[r] = F.mt[static_cast<size_t>(j + 1) * K * H + tid + kRT * r];
-    }
-    // ------------------------------------------------------------ L1
-    // Lane l's B operand: state row of environment l mod 8, entries 8(l/16) .. +7.  Lane l's
-    // results: tile T = (l / 8) mod 2 of the wavefront's pair, environment l mod 8, units
-    // u0 .. u0+3.
-    const int bev = lane & 7, bgrp = lane >> 4;
-    const int pair_t = (lane >> 3) & 1;
+    // Loads through buffer resources: out-of-range lanes read 0, so no branches.
+    float eps[2];
     {
-      const bf16x8 X = *reinterpret_cast<const bf16x8*>(s_x0 + bev * kRX0 + 8 * bgrp);
+      const __amdgpu_buffer_rsrc_t r =
+          rows_rsrc(F.sigma != 0.0f ? F.eps : nullptr, (static_cast<size_t>(j) * N + n0) * D, 4, M * D);
 #pragma unroll
-      for (int a = 0; a < K; ++a) {
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-          floatx4 acc[2];
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int c = 4 * wave + 2 * p + h;
-            acc[h] = mfma_bf16(s_w1e[(a * 16 + c) * 64 + lane], X,
-                               *reinterpret_cast<const floatx4*>(s_mt + a * H + 16 * c + 4 * bgrp));
-          }
-          const floatx4 v = merge_tiles(acc[0], acc[1]);
-          const int u0 = 16 * (4 * wave + 2 * p + pair_t) + 4 * bgrp;
-          *reinterpret_cast<uint2*>(s_x1 + a * MR * kRXS + bev * kRXS + u0) =
-              pack_bf16x4(tanh_sig(v[0]), tanh_sig(v[1]), tanh_sig(v[2]), tanh_sig(v[3]));
-        }
+      for (int s = 0; s < 2; ++s) {
+        const int d = jl + 16 * s;
+        eps[s] = load_f32(r, env_ok && d < D ? 4 * (m * D + d) : kNoStore);
       }
     }
+    float p_in, p_mt[K];
+    {
+      const int t = F.t0 + j + 1;  // the next step's trading day
+      const __amdgpu_buffer_rsrc_t rc = rows_rsrc(nxt ? C.close : nullptr, static_cast<size_t>(t) * D, 4, 2 * D);
+      const __amdgpu_buffer_rsrc_t ri = rows_rsrc(nxt ? C.ind : nullptr, static_cast<size_t>(t + 1) * I * D, 4, I * D);
+      const int i = threadIdx.x;
+      p_in = load_f32(rc, i < 2 * D ? 4 * i : kNoStore) + load_f32(ri, i >= 2 * D && i < n_in ? 4 * (i - 2 * D) : kNoStore);
+      const __amdgpu_buffer_rsrc_t rm = rows_rsrc(nxt ? F.mt : nullptr, static_cast<size_t>(j + 1) * K * H, 4, K * H);
+#pragma unroll
+      for (int r = 0; r < K; ++r) p_mt[r] = load_f32(rm, 4 * (i + kRT * r));
+    }
+    if (j >= 1) store_market(j - 1, s_in + (b ^ 1) * kRIn, lane);
+    // ------------------------------------------------------------ L1
+    layer1(s_w1e, s_mt, s_x0, s_x1, wave, lane);
     __syncthreads();  // 1: layer-1 outputs complete
     // ------------------------------------------------------------ L2
-#pragma unroll
-    for (int a = 0; a < K; ++a) {
-      const __bf16* src = s_x1 + a * MR * kRXS + bev * kRXS + 8 * bgrp;
-      bf16x8 X[KK];
-#pragma unroll
-      for (int kk = 0; kk < KK; ++kk) X[kk] = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
-      floatx4 acc[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        acc[i] = mfma_bf16(w2[a][0][i], X[0], *reinterpret_cast<const floatx4*>(s_b2 + a * H + 16 * (4 * wave + i) + 4 * bgrp));
-#pragma unroll
-      for (int kk = 1; kk < KK; ++kk)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = mfma_bf16(w2[a][kk][i], X[kk], acc[i]);
-#pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const floatx4 v = merge_tiles(acc[2 * p], acc[2 * p + 1]);
-        const int u0 = 16 * (4 * wave + 2 * p + pair_t) + 4 * bgrp;
-        *reinterpret_cast<uint2*>(s_x2 + a * MR * kRXS + bev * kRXS + u0) =
-            pack_bf16x4(tanh_sig(v[0]), tanh_sig(v[1]), tanh_sig(v[2]), tanh_sig(v[3]));
-      }
-    }
+    layer2(w2, s_b2, s_x1, s_x2, wave, lane);
     __syncthreads();  // 2: layer-2 outputs complete
     // ------------------------------------------------------------ L3: actor a on wavefront a
-    if (wave < K) {
-      const int a = wave;
-      const __bf16* src = s_x2 + a * MR * kRXS + bev * kRXS + 8 * bgrp;
-      floatx4 acc[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) acc[h] = *reinterpret_cast<const floatx4*>(s_b3 + a * 32 + 16 * h + 4 * bgrp);
-#pragma unroll
-      for (int kk = 0; kk < KK; ++kk) {
-        const bf16x8 X = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) acc[h] = mfma_bf16(s_w3[((a * 2 + h) * KK + kk) * 64 + lane], X, acc[h]);
-      }
-      const floatx4 v = merge_tiles(acc[0], acc[1]);
-      const float wk = s_mix[a];
-      *reinterpret_cast<float4*>(s_mu + a * MR * 32 + bev * 32 + 16 * pair_t + 4 * bgrp) =
-          float4{wk * tanh_sig(v[0]), wk * tanh_sig(v[1]), wk * tanh_sig(v[2]), wk * tanh_sig(v[3])};
-    }
+    if (wave < K) layer3(s_w3, s_b3, s_mix, s_x2, s_mu, wave, lane);
     __syncthreads();  // 3: the actors' weighted means complete
     {
       // ---------------------------------------------------------- the trading step
@@ -438,24 +501,8 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
       const float* in = s_in + b * kRIn;
       const size_t row = static_cast<size_t>(j) * N + n0 + m;
       const bool store_row = env_ok && lane < 32;  // rows 2 and 3 repeat rows 0 and 1
-      // The new state row's market entries (closes, indicators) do not depend on the trades:
-      // stored first, by both rows of the environment.
-      float* o = F.obs_traj ? F.obs_traj + row * S : nullptr;
-      if (env_ok && o) {
-        const int t32 = ((lane >> 5) << 4) | jl;  // 0 .. 31 over the environment's two rows
-        float v[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {  // (1 + I) D <= 255
-          const int u = t32 + 32 * r;
-          v[r] = u < n_mkt ? in[D + u] : 0.0f;
-        }
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const int u = t32 + 32 * r;
-          if (u < D) o[1 + u] = v[r] * C.price_scale;
-          else if (u < n_mkt) o[1 + D + u] = v[r];
-        }
-      }
+      const size_t row0 = static_cast<size_t>(j) * N + n0;  // the tile's first row of step j
+      const int em = m * D;                                 // environment m's first entry in [M][D]
       double cash = s_state[4 * m];
       int sold[2];
       BuySet B[2];
@@ -471,8 +518,8 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
           act = (mk[0] + mk[MR * 32]) + mk[2 * MR * 32];
           if (F.sigma != 0.0f) act = act + F.sigma * eps[s];
           act = fminf(fmaxf(act, -1.0f), 1.0f);
-          if (F.act_traj && lane < 32) F.act_traj[row * D + d] = act;
         }
+        store_f32(rows_rsrc(F.act_traj, row0 * D, 4, M * D), on && lane < 32 ? 4 * (em + d) : kNoStore, act);
         // Order and sale of stock d; the whole-order and one-share debits.
         const float p = on ? in[d] : 0.0f;
         const int q = on ? order_from_action(act, C.hmax_f) : 0;
@@ -490,8 +537,7 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
       cash = row_sum(cash, pro[0]);
       cash = row_sum(cash, pro[1]);
       int kown[2] = {0, 0};
-      const float p_min = row_min(fminf(jl < D ? in[jl] : __builtin_inff(), jl + 16 < D ? in[jl + 16] : __builtin_inff()));
-      buy_all(cash, kown, jl, B, C.one_p, static_cast<double>(p_min), std::make_integer_sequence<int, 8>());
+      buy_all(cash, kown, lane, B, C.one_p);
       // Holdings, executed quantities, the new day's position values, value and reward
       // (Section 3.1 reward, reading 8).
       double val[2];
@@ -503,11 +549,11 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
         const float pn = on ? in[D + d] : 0.0f;
         val[s] = static_cast<double>(pn) * static_cast<double>(hold[s]);
         const float he = static_cast<float>(hold[s]) * C.hold_scale;
-        if (on && lane < 32) {
-          s_x0[m * kRX0 + 1 + d] = static_cast<__bf16>(he);
-          if (F.qty_traj) F.qty_traj[row * D + d] = kown[s] - sold[s];
-          if (o) o[1 + D + d] = he;
-        }
+        if (on) s_x0[m * kRX0 + 1 + d] = static_cast<__bf16>(he);
+        const bool st_on = on && lane < 32;
+        store_f32(rows_rsrc(F.qty_traj, row0 * D, 4, M * D), st_on ? 4 * (em + d) : kNoStore,
+                  __int_as_float(kown[s] - sold[s]));
+        store_f32(rows_rsrc(F.obs_traj, row0 * S, 4, M * S), st_on ? 4 * (m * S + 1 + D + d) : kNoStore, he);
       }
       double v_new = row_sum(cash, val[0]);
       v_new = row_sum(v_new, val[1]);
@@ -519,7 +565,7 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
         s_state[4 * m + 2] = s_state[4 * m + 2] + r;
         s_x0[m * kRX0] = static_cast<__bf16>(ce);
         if (F.rew_traj) F.rew_traj[row] = r;
-        if (o) o[0] = ce;
+        if (F.obs_traj) F.obs_traj[row * S] = ce;
       }
     }
     if (nxt) {
@@ -529,6 +575,8 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
     }
     __syncthreads();  // 4: the next state rows and inputs are in LDS
   }
+  if (F.n_steps >= 1)
+    store_market(F.n_steps - 1, reinterpret_cast<const float*>(smem + RLds::in) + ((F.n_steps - 1) & 1) * kRIn, lane0);
   // The trading state back to HBM.
   if (tenv && lane0 < 32) {
     if (tj == 0) {
