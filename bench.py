@@ -56,6 +56,8 @@ CHUNK = 64  # steps per fused-kernel launch (the library's chunk)
 
 # Sources the stock-environment and fused-rollout kernels (and their launch choices) are built from.
 PROFILED_SOURCES = ("api.hip", "crypto_serve.hip", "device_common.h", "ensemble_kernels.hip", "env_kernels.hip",
+                    "env_lane.hip",
+                    "fused_resident.hip",
                     "fused.h", "fused_rollout.hip", "launch.h", "mlp_device.h", "status.h")
 
 
@@ -133,6 +135,47 @@ def time_launches(env, n_steps, reps, stream, **kw):
         torch.cuda.synchronize()
         res += [(n, a.elapsed_time(b)) for n, a, b in evs]
     return res
+
+
+def bench_precision(dev, w, args):
+    """The precision form: N=8192, D=30, T=252, bfloat16 fused path (streamed schedule, the
+    default at this size; the resident schedule timed beside it), states, actions and rewards
+    stored.  The action and episode-return errors against the oracle are measured by the GPU
+    test suite, not here."""
+    import torch
+    from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
+    from workload import make_actor_weights, make_market, pack_actor_weights
+    cfg, acfg = w.env, w.actors
+    N, D, T, S, H, K = cfg.n_envs, cfg.n_stocks, cfg.n_days, cfg.state_dim, acfg.hidden, acfg.n_actors
+    stream = torch.cuda.current_stream()
+    m = make_market(w.market_seed, D, T)
+    env = VecEnv(cfg, m.close, m.ind, device=dev)
+    ens = Ensemble(pack_actor_weights(make_actor_weights(acfg)), K, S, H, D, dtype="bf16", max_batch=N, device=dev)
+    kw = dict(ens=ens, sigma=w.sigma, noise_key=w.noise_key, path="fused", store=("obs", "act", "rew"))
+    reps = max(5, args.steps // 3)
+    out = {"workload": w.name, "dtype": "bf16",
+           "schedule": "streamed (the default past one resident workgroup per compute unit)"}
+    for name, schedule in (("streamed", 1), ("resident", 3)):
+        env.set_fused_tuning(schedule=schedule)
+        tot, _, _, _ = time_rollouts(env, T, reps, 2, stream, **kw)
+        out[name] = {"value": N * T / (float(np.median(tot)) / 1e3), "unit": "env-steps/s",
+                     "ms_per_rollout": float(np.median(tot)), "p50_ms": _pct(tot, 50), "p99_ms": _pct(tot, 99)}
+    env.set_fused_tuning(schedule=0)
+    launches = time_launches(env, T, 3, stream, **kw)
+    flop = mlp_flops_per_env_step(S, H, D, K)
+    steps = sum(n for n, _ in launches)
+    ms = sum(t for _, t in launches)
+    tf = flop * N * steps / (ms / 1e3) / 1e12
+    out["value"] = out["streamed"]["value"]
+    out["unit"] = "env-steps/s"
+    out["roofline"] = {"bound": "mfma", "achieved": tf, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                       "frac": tf / PEAK_BF16_TFLOPS, "kernel": "fused_streamed_kernel",
+                       "launch_ms": ms / len(launches), "steps_per_launch": steps / len(launches),
+                       "launch_includes": "the chunk's market_table_kernel and noise_chunk_kernel",
+                       "traffic": traffic_for("fused_streamed_kernel@8192", N * steps / len(launches))}
+    del env, ens
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_batched(dev, n_groups=64, reps=3):
@@ -464,6 +507,7 @@ def main():
                                                sigma=w.sigma, noise_key=w.noise_key, path="fused", store=store)
     launches = time_launches(env, T, max(3, args.steps // 5), stream, ens=ens_bf16, sigma=w.sigma,
                              noise_key=w.noise_key, path="fused", store=store)
+    precision = bench_precision(dev, WORKLOADS["precision"], args)
     ens_f32 = Ensemble(packed, K, S, H, D, dtype="f32", max_batch=N, device=dev)
     f32_reps = args.fp32_steps if args.fp32_steps is not None else max(5, args.steps // 3)
     f_tot, f_ker, f_wall, _ = time_rollouts(env, T, f32_reps, max(1, args.warmup // 2), stream, ens=ens_f32,
@@ -525,18 +569,22 @@ def main():
         "bf16_over_fp32": f_ms / bf_ms,
         "roofline": {"bound": "mfma", "achieved": achieved_tf, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_BF16_TFLOPS,
-                     "traffic": traffic_for("fused_streamed_kernel", N * steps_per_launch),
-                     "kernel": "fused_streamed_kernel", "launch_ms": mean_launch_ms,
+                     "traffic": traffic_for("fused_resident_kernel", N * steps_per_launch),
+                     "kernel": "fused_resident_kernel", "launch_ms": mean_launch_ms,
+                     "launch_includes": "the chunk's market_table_kernel and noise_chunk_kernel",
                      "steps_per_launch": steps_per_launch, "flop_per_env_step": flop_env_step},
         "env_roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": achieved_gbs / PEAK_HBM_GBS,
                          "traffic": traffic_for("env_tile_kernel<1>@2048", N * T),
-                         "kernel": "env_tile_kernel<1> (driven)", "kernel_ms": d_s * 1e3,
+                         "kernel": "env_tile_kernel<1> (driven; the size-based choice at this N)",
+                         "kernel_ms": d_s * 1e3, "us_per_step": d_s * 1e6 / T,
                          "bytes_per_env_step": env_bytes_per_env_step(D, S), "env_steps_per_s": env_steps / d_s,
                          "large": {"workload": wl.name, "achieved": large_gbs, "frac": large_gbs / PEAK_HBM_GBS,
+                                   "kernel": "env_lane_kernel<0,32> (one lane per environment)",
                                    "kernel_ms": l_s * 1e3, "env_steps_per_s": NL * TL / l_s,
-                                   "traffic": traffic_for("env_tile_kernel<1>@65536", NL * TL)}},
+                                   "traffic": traffic_for("env_lane_kernel@65536", NL * TL)}},
     }
+    rec["precision"] = precision
     rec["batched_uneven"] = bench_batched(dev)
     rec["serving"] = bench_serving(dev)
     rec["learner"] = bench_learner(dev, w)

@@ -136,14 +136,24 @@ int32_t env_day(const fm_env* env);
  * the value in effect. */
 fm_status env_set_tile(fm_env* env, int32_t envs_per_group, int32_t* h_tile);
 
+/* Tuning (no effect on results): the environment-step kernel of env_step, driven rollouts and
+ * the plain path's steps.  kernel 0 picks by shape and size: one lane per environment (the whole
+ * trading chain in registers) when n_stocks <= 32, (2 + n_ind) * n_stocks <= 256 and
+ * n_envs >= 24576, else the tile kernel; 1 always takes the tile kernel (env_set_tile's
+ * environments per workgroup); 2 the lane kernel whatever n_envs.  envs_per_wave: environments per wavefront of the lane kernel, 1..64; 0 by N (one
+ * wavefront per SIMD).  FM_ERR_INVALID for NULL or out-of-range values; FM_ERR_UNSUPPORTED for
+ * kernel 2 on a shape it does not take.  Reset and observation always use the tile kernel. */
+fm_status env_set_step_kernel(fm_env* env, int32_t kernel, int32_t envs_per_wave);
+
 /* Tuning of the fused rollout (results stay within the bfloat16 tolerance; the environment
- * arithmetic is unchanged): schedule 0 picks, by shape, the resident schedule (weights held on
- * chip; K = 3, hidden 256, <= 31 stocks), else the streamed one (weights streamed from L2;
+ * arithmetic is unchanged): schedule 0 picks, by shape and size, the resident schedule (weights
+ * held on chip, eight environments per compute unit; K = 3, hidden 256, <= 31 stocks) when the
+ * batch fits one workgroup per compute unit, else the streamed one (weights streamed from L2;
  * K = 3, hidden 256, <= 32 stocks), else the generic (runtime-shape) one; 1 skips the resident
- * schedule; 2 always takes the generic one.  row_tiles 1 or 2 sets the streamed schedule's 16
- * or 32 MFMA rows per workgroup (0: by N); tile_envs the environments per workgroup (resident
- * <= 8, streamed <= 16 * row_tiles; 0: fill the compute units).  FM_ERR_INVALID for NULL or
- * out-of-range values. */
+ * schedule; 2 always takes the generic one; 3 takes the resident schedule whenever the shape
+ * allows it, whatever N.  row_tiles 1 or 2 sets the streamed schedule's 16 or 32 MFMA rows per
+ * workgroup (0: by N); tile_envs the environments per workgroup (resident <= 8, streamed <= 16 *
+ * row_tiles; 0: fill the compute units).  FM_ERR_INVALID for NULL or out-of-range values. */
 fm_status env_set_fused_tuning(fm_env* env, int32_t schedule, int32_t row_tiles, int32_t tile_envs);
 void env_destroy(fm_env* env);
 

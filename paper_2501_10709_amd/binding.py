@@ -20,7 +20,7 @@ FM_PATH_PLAIN, FM_PATH_FUSED = 0, 1
 # Symbols declared in include/finrl_mi.h.
 EXPORTS = (
     "env_workspace_bytes", "env_create", "env_reset", "env_step", "env_rollout", "env_read_state",
-    "env_write_state", "env_day", "env_set_tile", "env_set_fused_tuning", "env_destroy", "ensemble_workspace_bytes", "ensemble_create",
+    "env_write_state", "env_day", "env_set_tile", "env_set_step_kernel", "env_set_fused_tuning", "env_destroy", "ensemble_workspace_bytes", "ensemble_create",
     "ensemble_act", "ensemble_destroy", "fm_last_error", "fm_noise", "fm_version", "fm_backtest_metrics",
     "fm_sharpe_weights", "fm_batch_workspace_bytes", "fm_batch_create", "fm_batch_tune", "fm_batch_set_tiling",
     "fm_batch_run",
@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
         "env_write_state": (I32, [P, P, P, P, P, I32]),
         "env_day": (I32, [P]),
         "env_set_tile": (I32, [P, I32, ctypes.POINTER(I32)]),
+        "env_set_step_kernel": (I32, [P, I32, I32]),
         "env_set_fused_tuning": (I32, [P, I32, I32, I32]),
         "env_destroy": (None, [P]),
         "ensemble_workspace_bytes": (SZ, [I32, I32, I32, I32, I32, I32]),
@@ -253,6 +254,10 @@ def env_set_tile(env, envs_per_group: int) -> int:
     out = ctypes.c_int32(0)
     _check(load().env_set_tile(env, int(envs_per_group), ctypes.byref(out)))
     return out.value
+
+
+def env_set_step_kernel(env, kernel=0, envs_per_wave=0):
+    _check(load().env_set_step_kernel(env, int(kernel), int(envs_per_wave)))
 
 
 def env_set_fused_tuning(env, schedule=0, row_tiles=0, tile_envs=0):

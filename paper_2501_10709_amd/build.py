@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB_NAME = "libfinrl_mi.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["api.hip", "env_kernels.hip", "ensemble_kernels.hip", "fused_rollout.hip", "fused_resident.hip", "metrics_kernels.hip", "crypto_serve.hip", "learner.hip"]
+SOURCES = ["api.hip", "env_kernels.hip", "env_lane.hip", "ensemble_kernels.hip", "fused_rollout.hip", "fused_resident.hip", "metrics_kernels.hip", "crypto_serve.hip", "learner.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -111,6 +111,8 @@ struct fm_env {
   int device;
   int day;
   int tile;
+  int step_kernel;    // 0 by shape, 1 the tile kernel, 2 the lane kernel
+  int lane_envs;      // environments per wavefront of the lane kernel (0: by N)
   fm::FusedTuning fused;  // fused-rollout tuning (schedule, row tiles, environments per workgroup)
 };
 
@@ -331,6 +333,24 @@ hipError_t batch_state_copy(fm_batch* b, bool save) {
     p += nd + align_up(nh);
   }
   return hipSuccess;
+}
+
+// The lane kernel (one lane per environment) by default from this many environments: below it
+// the batch holds too few environments per SIMD to hide the lane chains' instruction stream, and
+// the tile kernel's shorter per-step latency wins (measured on MI355X, D = 30, driven).
+constexpr int kLaneMinEnvs = 24576;
+
+bool lane_kernel(const fm_env* env) {
+  if (env->step_kernel == 1 || !fm::env_lane_shape(env->C)) return false;
+  return env->step_kernel == 2 || env->C.N >= kLaneMinEnvs;
+}
+
+// The caller's actions over n_steps days from day t0, by the chosen environment-step kernel.
+hipError_t launch_given(const fm_env* env, int t0, int n_steps, const float* act, float* obs, double* rew,
+                        int* qty, hipStream_t stream) {
+  if (lane_kernel(env))
+    return fm::launch_env_lane_given(env->C, env->st, t0, n_steps, act, obs, rew, qty, env->lane_envs, stream);
+  return fm::launch_env_given(env->C, env->st, t0, n_steps, act, obs, rew, qty, env->tile, stream);
 }
 
 }  // namespace
@@ -569,6 +589,8 @@ fm_status env_create(const fm_env_config* cfg, const float* d_close, const float
   if (hipGetDevice(&e->device) != hipSuccess) e->device = 0;
   e->day = 0;
   e->tile = env_tile(C.N);
+  e->step_kernel = 0;
+  e->lane_envs = 0;
   *out = e;
   return FM_OK;
 }
@@ -589,8 +611,7 @@ fm_status env_step(fm_env* env, const float* d_act, float* d_obs, double* d_rewa
   if (!d_reward) return fail(FM_ERR_INVALID, "d_reward is NULL");
   if (env->day >= env->C.T) return fail(FM_ERR_STATE, "environment is at the last day; reset first");
   DeviceGuard g(env->device);
-  fm_status s = device_status(fm::launch_env_given(env->C, env->st, env->day, 1, d_act, d_obs,
-                                                   d_reward, d_exec_qty, env->tile, env->stream),
+  fm_status s = device_status(launch_given(env, env->day, 1, d_act, d_obs, d_reward, d_exec_qty, env->stream),
                               "env_step");
   if (s != FM_OK) return s;
   env->day += 1;
@@ -613,10 +634,9 @@ fm_status env_rollout(fm_env* env, const fm_ensemble* ens, int32_t n_steps,
   DeviceGuard g(env->device);
   hipStream_t st = env->stream;
   if (opts->d_actions) {  // driven mode: one launch over all steps
-    fm_status s = device_status(
-        fm::launch_env_given(C, env->st, env->day, n_steps, opts->d_actions, opts->d_obs_traj,
-                             opts->d_rew_traj, opts->d_qty_traj, env->tile, st),
-        "env_rollout (driven)");
+    fm_status s = device_status(launch_given(env, env->day, n_steps, opts->d_actions, opts->d_obs_traj,
+                                             opts->d_rew_traj, opts->d_qty_traj, st),
+                                "env_rollout (driven)");
     if (s != FM_OK) return s;
     if (opts->d_act_traj) {
       s = device_status(hipMemcpyAsync(opts->d_act_traj, opts->d_actions,
@@ -660,10 +680,15 @@ fm_status env_rollout(fm_env* env, const fm_ensemble* ens, int32_t n_steps,
     float* act_out = opts->d_act_traj ? opts->d_act_traj + static_cast<size_t>(i) * N * D : nullptr;
     double* rew = opts->d_rew_traj ? opts->d_rew_traj + static_cast<size_t>(i) * N : nullptr;
     int* qty = opts->d_qty_traj ? opts->d_qty_traj + static_cast<size_t>(i) * N * D : nullptr;
-    s = device_status(fm::launch_env_ensemble_step(C, env->st, t, ens->mu, ens->E.mix, ens->K, opts->sigma,
-                                                   opts->noise_key, opts->env_offset, obs_out, act_out,
-                                                   rew, qty, env->tile, st),
-                      "env_rollout (step)");
+    const hipError_t e =
+        lane_kernel(env)
+            ? fm::launch_env_lane_ensemble_step(C, env->st, t, ens->mu, ens->E.mix, ens->K, opts->sigma,
+                                                opts->noise_key, opts->env_offset, obs_out, act_out, rew, qty,
+                                                env->lane_envs, st)
+            : fm::launch_env_ensemble_step(C, env->st, t, ens->mu, ens->E.mix, ens->K, opts->sigma,
+                                           opts->noise_key, opts->env_offset, obs_out, act_out, rew, qty,
+                                           env->tile, st);
+    s = device_status(e, "env_rollout (step)");
     if (s != FM_OK) return s;
     obs_in = obs_out;
   }
@@ -703,9 +728,21 @@ fm_status env_set_tile(fm_env* env, int32_t envs_per_group, int32_t* h_tile) {
   return FM_OK;
 }
 
+fm_status env_set_step_kernel(fm_env* env, int32_t kernel, int32_t envs_per_wave) {
+  if (!env) return fail(FM_ERR_INVALID, "env is NULL");
+  if (kernel < 0 || kernel > 2) return fail(FM_ERR_INVALID, "kernel must be 0 (by shape), 1 (tile) or 2 (lane)");
+  if (envs_per_wave < 0 || envs_per_wave > 64) return fail(FM_ERR_INVALID, "envs_per_wave must be in 0..64");
+  if (kernel == 2 && !fm::env_lane_shape(env->C))
+    return fail(FM_ERR_UNSUPPORTED, "the lane kernel takes at most 32 stocks and (2 + n_ind) * n_stocks <= 256");
+  env->step_kernel = kernel;
+  env->lane_envs = envs_per_wave;
+  return FM_OK;
+}
+
 fm_status env_set_fused_tuning(fm_env* env, int32_t schedule, int32_t row_tiles, int32_t tile_envs) {
   if (!env) return fail(FM_ERR_INVALID, "env is NULL");
-  if (schedule < 0 || schedule > 2) return fail(FM_ERR_INVALID, "schedule must be 0 (by shape), 1 (streamed) or 2 (generic)");
+  if (schedule < 0 || schedule > 3)
+    return fail(FM_ERR_INVALID, "schedule must be 0 (by shape and size), 1 (streamed), 2 (generic) or 3 (resident)");
   if (row_tiles < 0 || row_tiles > 2) return fail(FM_ERR_INVALID, "row_tiles must be 0, 1 or 2");
   if (tile_envs < 0 || tile_envs > 32) return fail(FM_ERR_INVALID, "tile_envs must be in 0..32");
   env->fused.schedule = schedule;

@@ -266,7 +266,9 @@ __device__ __forceinline__ int partial_fill(double cash, double p, double rc1, i
   const double dk1 = (p * (kd + 1.0)) * one_p;
   int k = static_cast<int>(kd);
   if (!(dk <= cash) || (kd < qm1 && dk1 <= cash)) {
+#pragma clang loop unroll(disable)
     while (k + 1 < q && (p * static_cast<double>(k + 1)) * one_p <= cash) ++k;
+#pragma clang loop unroll(disable)
     while (k > 0 && !((p * static_cast<double>(k)) * one_p <= cash)) --k;
     dk = k > 0 ? (p * static_cast<double>(k)) * one_p : 0.0;
   }

@@ -1,0 +1,411 @@
+// The environment step with one lane per environment, for up to 32 stocks (Section 3.1's
+// market step; Sections 4.2-4.3: the vectorised environments on the GPU).
+//
+// Each lane holds its environment's whole trading state in registers (cash, total asset and
+// cumulative reward in float64, the holdings as int32) and runs the step's serial chain --
+// orders, the sells, the buys against the cash, the new holdings, the position values and the
+// reward -- without any cross-lane traffic: the 64 lanes of a wavefront advance 64 chains at
+// once, so the serial recurrence costs one instruction stream per wavefront rather than one per
+// environment.  A wavefront owns M consecutive environments; it needs no workgroup barrier, so
+// the four wavefronts of a workgroup run free of each other.
+//
+// Per step a wavefront
+//   1. writes the step's inputs, fetched into registers during the previous step, to its LDS
+//      area: the market row [close[t] | close[t+1] | ind[t+1]] and, driven, the M x D actions;
+//   2. requests the next step's inputs into the same registers (coalesced: consecutive lanes
+//      read consecutive floats of the tile's contiguous block);
+//   3. runs the chains: lane m reads its action row and the day's prices from LDS;
+//   4. writes the state rows' cash and holdings entries and the executed quantities to LDS;
+//   5. stores the tile's state rows, quantities and rewards as wave-wide runs of addresses.
+// HBM sees each trajectory byte once: the actions are read and the states, quantities and
+// rewards written, nothing else (the per-environment state stays in registers across steps).
+#include "device_common.h"
+#include "launch.h"
+
+namespace fm {
+
+namespace {
+
+constexpr int kWaves = 4;       // wavefronts per workgroup
+constexpr int kRow = 33;        // LDS stride of the per-environment rows: lane m's reads of its
+                                // own row fall in distinct banks
+constexpr int kMaxMkt = 256;    // market floats staged per step, (2 + I) * D
+constexpr int kMaxEnvs = 64;    // environments per wavefront
+constexpr int kColGroups = (kMaxMkt + 1 + 63) / 64;  // 64-column groups of a state row (S <= 257)
+constexpr int kNoStore = 1 << 30;                     // a byte offset beyond any store range
+
+enum LaneMode { kDriven = 0, kMeans = 1 };
+
+struct LaneArgs {
+  int t0, n_steps, M;
+  const float* act;   // kDriven: [n_steps][N][D]
+  const float* mu;    // kMeans: [K][N][D] actor means
+  const float* mix;   // kMeans: [K] weights w_k (device)
+  int K;
+  float sigma;
+  uint64_t noise_key;
+  int64_t env_offset;
+  float* obs;         // [n_steps][N][S] or null
+  float* act_out;     // kMeans: [N][D] or null
+  double* rew;        // [n_steps][N] or null
+  int* qty;           // [n_steps][N][D] or null
+};
+
+__host__ __device__ inline int wave_floats(int M) { return kMaxMkt + 64 + 2 * (M + 1) * kRow; }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(const float* base, int n_floats) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, 4 * n_floats, 0x00020000);
+}
+// Beyond the resource's range a load returns 0.
+__device__ __forceinline__ float range_load(__amdgpu_buffer_rsrc_t r, int i) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, 4 * i, 0, 0));
+}
+
+// The day's trading chain of one environment (Section 3.1) over its lane's LDS rows: row holds
+// the actions on entry and the executed quantities on exit (signed orders in between), ent
+// receives the state row's cash and holdings entries.  The pointers are restrict-qualified (the
+// rows, the prices and the entries never overlap), so the compiler may issue the LDS reads
+// ahead of the writes.  Returns the new value v' = cash + sum_d p'_d h_d.
+template <int DP>
+__device__ __forceinline__ double lane_chain(double& cash, int (&hold)[DP], float* __restrict__ row,
+                                             float* __restrict__ ent, const float* __restrict__ px,
+                                             const float* __restrict__ pn, int D, const EnvConst& C) {
+#pragma clang fp contract(off)
+  const double one_p = C.one_p;
+  // Orders and all sells in ascending stock order.
+  float a[DP];
+#pragma unroll
+  for (int d = 0; d < DP; ++d) a[d] = row[d];
+#pragma unroll
+  for (int d = 0; d < DP; ++d) {
+    const int q = order_from_action(a[d], C.hmax_f);
+    const int s = q < 0 ? min(hold[d], -q) : 0;
+    hold[d] -= s;
+    row[d] = __int_as_float(q < 0 ? -s : q);
+    cash = cash + (static_cast<double>(px[d]) * static_cast<double>(s)) * C.one_m;
+  }
+  // All buys in ascending order, each whole when its debit fits the cash, else the largest
+  // affordable part: one loop body for every stock (the partial fill is long and rarely taken),
+  // the next stock's order and price read one iteration ahead (entry D of a row and of the
+  // prices exists).
+  int od = __float_as_int(row[0]);
+  float pf = px[0];
+#pragma clang loop unroll(disable)
+  for (int d = 0; d < D; ++d) {
+    const int od_next = __float_as_int(row[d + 1]);
+    const float pf_next = px[d + 1];
+    const int qd = od > 0 ? od : 0;
+    const double p = static_cast<double>(pf);
+    const double deb = (p * static_cast<double>(qd)) * one_p;
+    const bool fits = deb <= cash;
+    int k = fits ? qd : 0;
+    double debit = fits ? deb : 0.0;
+    if (!fits) {
+      const double c1 = p * one_p;
+      if (c1 <= cash) {
+        double rc = __builtin_amdgcn_rcp(c1);
+        rc = fma(fma(-c1, rc, 1.0), rc, rc);
+        k = partial_fill(cash, p, rc, qd, one_p, debit);
+      }
+    }
+    cash = cash - debit;
+    if (qd > 0) row[d] = __int_as_float(k);
+    od = od_next;
+    pf = pf_next;
+  }
+  // Holdings, the state row's entries and the value in ascending stock order.
+  double v = cash;
+#pragma unroll
+  for (int d = 0; d < DP; ++d) {
+    const int e = __float_as_int(row[d]);
+    hold[d] += e > 0 ? e : 0;
+    v = v + static_cast<double>(pn[d]) * static_cast<double>(hold[d]);
+    ent[1 + d] = static_cast<float>(hold[d]) * C.hold_scale;
+  }
+  ent[0] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
+  return v;
+}
+
+// DP: stocks per chain in registers (D <= DP); the entries d >= D carry a zero action, hence a
+// zero order, a zero sale and debit and a zero position value, and leave the cash and the value
+// unchanged bit for bit (adding +0.0 to a non-negative float64).
+template <int MODE, int DP>
+__global__ __launch_bounds__(kWaves * 64) void env_lane_kernel(EnvConst C, EnvState st, LaneArgs A) {
+  extern __shared__ __align__(16) float lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
+  const int MM = A.M;
+  const int n0 = (blockIdx.x * kWaves + wave) * MM;
+  if (n0 >= C.N) return;  // the whole wavefront; no barrier follows
+  const int N = C.N, D = C.D, S = C.S;
+  const int M = min(MM, N - n0);
+  const int MD = M * D;
+  const int n_mkt = (2 + C.I) * D;
+  const float inv_d = 1.0f / static_cast<float>(D);
+  float* mkt = lds + wave * wave_floats(MM);
+  float* px = mkt + kMaxMkt;      // close[t][d], zero from D to 31
+  float* pn = px + 32;            // close[t+1][d], likewise
+  // Rows of kRow floats, M + 1 of each (idle lanes work on the spare last row):
+  float* tile = pn + 32;                // actions / actor means, then orders, then quantities
+  float* ent = tile + (MM + 1) * kRow;  // noise, then the state rows' cash and holdings entries
+  const bool active = lane < M;
+  const int lr = active ? lane : MM;  // the lane's LDS row (idle lanes share the spare row)
+  const int n = n0 + lane;
+
+  // The holdings through a buffer resource over [D][N]: rows d >= D read 0 and are not stored.
+  const __amdgpu_buffer_rsrc_t hr = range_rsrc(reinterpret_cast<const float*>(st.hold), D * N);
+  double cash = 0.0, asset = 0.0, cumrew = 0.0;
+  int hold[DP];
+#pragma unroll
+  for (int d = 0; d < DP; ++d) hold[d] = active ? __float_as_int(range_load(hr, d * N + n)) : 0;
+  if (active) {
+    cash = st.cash[n];
+    asset = st.asset[n];
+    cumrew = st.cumrew[n];
+  }
+  // Entries d >= D of the LDS rows stay zero: they are written only with the zero actions,
+  // orders and quantities of those stocks.
+  for (int i = lane; i < 2 * (MM + 1) * kRow; i += 64) tile[i] = 0.0f;
+
+  // Inputs of step it in registers: market floats i = lane + 64 j (close[t] and close[t+1] are
+  // adjacent rows of close), lane d < 32's prices of stock d (zero beyond D), and the driven
+  // tile's floats i = lane + 64 j.
+  // Inside the step loop the lane index L is re-derived each step through an opaque copy, so
+  // the per-lane addresses and masks are recomputed rather than held in registers.
+  int L = lane, LR = lr;
+  float pm[kMaxMkt / 64], ppx = 0.0f, ppn = 0.0f;
+  float pa[DP];
+  auto fetch = [&](int it) {
+    const int t = A.t0 + it;
+    const float* cl = C.close + static_cast<size_t>(t) * D;
+    const float* ind = C.ind + static_cast<size_t>(t + 1) * C.I * D;
+#pragma unroll
+    for (int j = 0; j < kMaxMkt / 64; ++j) {
+      const int i = min(L + 64 * j, n_mkt - 1);
+      pm[j] = i < 2 * D ? cl[i] : ind[i - 2 * D];
+    }
+    const int dl = min(L, D - 1);
+    ppx = L < D ? cl[dl] : 0.0f;
+    ppn = L < D ? cl[D + dl] : 0.0f;
+    if (MODE == kDriven) {
+      const __amdgpu_buffer_rsrc_t r = range_rsrc(A.act + (static_cast<size_t>(it) * N + n0) * D, MD);
+      int md = MD;
+      __asm__ volatile("" : "+s"(md));  // a fresh value: the slice tests below are not kept live
+#pragma unroll
+      for (int j = 0; j < DP; ++j)
+        if (64 * j < md) pa[j] = range_load(r, L + 64 * j);
+    }
+  };
+  // Tile float i = m * D + d goes to row m, entry d.
+  auto tile_put = [&](const float (&v)[DP]) {
+    int md = MD;
+    __asm__ volatile("" : "+s"(md));
+#pragma unroll
+    for (int j = 0; j < DP; ++j) {
+      const int i = L + 64 * j;
+      if (64 * j < md && i < md) {
+        const int m = div_small(i, inv_d);
+        tile[m * kRow + (i - m * D)] = v[j];
+      }
+    }
+  };
+  auto tile_get = [&](int i) {
+    const int m = div_small(i, inv_d);
+    return tile[m * kRow + (i - m * D)];
+  };
+
+  // The state rows [cash, close[t+1] (D), holdings (D), ind[t+1] (I*D)]: lane column f = lane +
+  // 64 g is read from LDS (relative to mkt) at col_src + m * col_stride for row m -- the
+  // environment's entries row for the cash and holdings columns, the market row (stride 0)
+  // otherwise -- scaled by col_scale and stored at byte col_b of the row; columns past S store
+  // nowhere (col_b beyond every range of at most 64 rows, and no int overflow).
+  const int ent_off = static_cast<int>(ent - mkt);
+  int col_src[kColGroups], col_stride[kColGroups], col_b[kColGroups];
+  float col_scale[kColGroups];
+#pragma unroll
+  for (int g = 0; g < kColGroups; ++g) {
+    const int f = lane + 64 * g;
+    const bool own = f == 0 || (f > D && f <= 2 * D);
+    col_src[g] = own ? ent_off + (f == 0 ? 0 : f - D) : (f <= D ? D + f - 1 : min(f, S - 1) - 1);
+    col_stride[g] = own ? kRow : 0;
+    col_scale[g] = (f >= 1 && f <= D) ? C.price_scale : 1.0f;
+    col_b[g] = f < S ? 4 * f : kNoStore;
+  }
+
+  fetch(0);
+  for (int it = 0; it < A.n_steps; ++it) {
+#pragma clang fp contract(off)
+    const int t = A.t0 + it;
+    const size_t row0 = static_cast<size_t>(it) * N + n0;
+    L = lane;
+    __asm__ volatile("" : "+v"(L));
+    LR = L < M ? L : MM;
+#pragma unroll
+    for (int j = 0; j < kMaxMkt / 64; ++j)
+      if (L + 64 * j < n_mkt) mkt[L + 64 * j] = pm[j];
+    if (L < 32) {
+      px[L] = ppx;
+      pn[L] = ppn;
+    }
+    if (MODE == kDriven) tile_put(pa);
+    if (it + 1 < A.n_steps) fetch(it + 1);
+    wave_lds_sync();
+
+    // Actions (Section 5.2.1 for the ensemble's: a = clip(sum_k w_k mu_k + sigma eps)) in the
+    // lanes' tile rows.
+    if (MODE == kMeans) {
+      // One Philox block per (environment, group of four stocks), spread over the lanes; the
+      // noise rows' entries from D on are zero.
+      const int G = (D + 3) >> 2;
+      for (int i = L; i < M * 8; i += 64) {
+        const int m = i >> 3;
+        const int g = i & 7;
+        float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (g < G && A.sigma != 0.0f)
+          noise_block(A.noise_key, static_cast<uint64_t>(A.env_offset + n0 + m), static_cast<uint64_t>(t),
+                      static_cast<uint64_t>(g), z);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ent[m * kRow + 4 * g + r] = 4 * g + r < D ? z[r] : 0.0f;
+      }
+      float acc[DP];
+#pragma unroll
+      for (int d = 0; d < DP; ++d) acc[d] = 0.0f;
+      for (int k = 0; k < A.K; ++k) {
+        const float w = A.mix[k];
+        const __amdgpu_buffer_rsrc_t r = range_rsrc(A.mu + (static_cast<size_t>(k) * N + n0) * D, MD);
+        int md = MD;
+        __asm__ volatile("" : "+s"(md));
+        float v[DP];
+#pragma unroll
+        for (int j = 0; j < DP; ++j) v[j] = 64 * j < md ? range_load(r, L + 64 * j) : 0.0f;
+        wave_lds_sync();  // the previous actor's rows have been read
+        tile_put(v);
+        wave_lds_sync();
+#pragma unroll
+        for (int d = 0; d < DP; ++d) acc[d] = acc[d] + w * tile[LR * kRow + d];
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int d = 0; d < DP; ++d) {
+        float x = acc[d];
+        if (A.sigma != 0.0f) x = acc[d] + A.sigma * ent[LR * kRow + d];
+        tile[LR * kRow + d] = fminf(fmaxf(x, -1.0f), 1.0f);
+      }
+      wave_lds_sync();
+      if (A.act_out) wave_store_row(A.act_out + static_cast<size_t>(n0) * D, MD, L, tile_get);
+    }
+
+    // The chain (Section 3.1); the lane's tile row turns from actions into executed quantities.
+    const double v = lane_chain<DP>(cash, hold, tile + LR * kRow, ent + LR * kRow, px, pn, D, C);
+    const double r = (v - asset) * C.reward_scale;
+    cumrew = cumrew + r;
+    asset = v;
+    if (A.rew && L < M) A.rew[row0 + L] = r;
+
+    // The tile's stores.
+    wave_lds_sync();
+    if (A.qty)
+      wave_store_row(A.qty + row0 * D, MD, L, [&](int i) { return __float_as_int(tile_get(i)); });
+    if (A.obs) {
+      // Four rows per batch: every read is issued before the first store.  Rows past M read
+      // row M - 1 and their stores fall beyond the resource's range, as do columns past S.
+      const __amdgpu_buffer_rsrc_t orow = range_rsrc(A.obs + row0 * S, M * S);
+      for (int m0 = 0; m0 < M; m0 += 4) {
+        float v[4][kColGroups];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int g = 0; g < kColGroups; ++g) v[r][g] = mkt[col_src[g] + min(m0 + r, M - 1) * col_stride[g]];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int g = 0; g < kColGroups; ++g)
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[r][g] * col_scale[g]), orow,
+                                                  4 * (m0 + r) * S + col_b[g], 0, 0);
+      }
+    }
+    wave_lds_sync();  // the stores have read the LDS rows before the next step rewrites them
+  }
+
+  if (active) {
+    st.cash[n] = cash;
+    st.asset[n] = asset;
+    st.cumrew[n] = cumrew;
+#pragma unroll
+    for (int d = 0; d < DP; ++d) __builtin_amdgcn_raw_buffer_store_b32(hold[d], hr, 4 * (d * N + n), 0, 0);
+  }
+}
+
+template <int MODE, int DP>
+hipError_t launch_dp(const EnvConst& C, const EnvState& st, const LaneArgs& A, hipStream_t stream) {
+  const int waves = (C.N + A.M - 1) / A.M;
+  const int grid = (waves + kWaves - 1) / kWaves;
+  const size_t lds = sizeof(float) * kWaves * wave_floats(A.M);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(env_lane_kernel<MODE, DP>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((env_lane_kernel<MODE, DP>), dim3(grid), dim3(kWaves * 64), lds, stream, C, st, A);
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_mode(const EnvConst& C, const EnvState& st, LaneArgs A, hipStream_t stream) {
+  if (!env_lane_shape(C)) return hipErrorInvalidValue;
+  if (A.n_steps <= 0 || C.N <= 0) return hipSuccess;
+  if (A.M <= 0) {
+    // One wavefront per SIMD (four per compute unit) when the batch allows, up to 64 lanes each.
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    A.M = (C.N + 4 * cus - 1) / (4 * cus);
+  }
+  A.M = max(1, min(A.M, kMaxEnvs));
+  if (C.D <= 8) return launch_dp<MODE, 8>(C, st, A, stream);
+  if (C.D <= 16) return launch_dp<MODE, 16>(C, st, A, stream);
+  return launch_dp<MODE, 32>(C, st, A, stream);
+}
+
+}  // namespace
+
+bool env_lane_shape(const EnvConst& C) {
+  return C.D >= 1 && C.D <= 32 && (2 + C.I) * C.D <= kMaxMkt;
+}
+
+hipError_t launch_env_lane_given(const EnvConst& C, const EnvState& st, int t0, int n_steps, const float* act,
+                                 float* obs, double* rew, int* qty, int envs_per_wave, hipStream_t stream) {
+  LaneArgs A{};
+  A.t0 = t0;
+  A.n_steps = n_steps;
+  A.M = envs_per_wave;
+  A.act = act;
+  A.obs = obs;
+  A.rew = rew;
+  A.qty = qty;
+  return launch_mode<kDriven>(C, st, A, stream);
+}
+
+hipError_t launch_env_lane_ensemble_step(const EnvConst& C, const EnvState& st, int t, const float* mu,
+                                         const float* mix, int K, float sigma, uint64_t key, int64_t env_offset,
+                                         float* obs, float* act_out, double* rew, int* qty, int envs_per_wave,
+                                         hipStream_t stream) {
+  LaneArgs A{};
+  A.t0 = t;
+  A.n_steps = 1;
+  A.M = envs_per_wave;
+  A.mu = mu;
+  A.mix = mix;
+  A.K = K;
+  A.sigma = sigma;
+  A.noise_key = key;
+  A.env_offset = env_offset;
+  A.obs = obs;
+  A.act_out = act_out;
+  A.rew = rew;
+  A.qty = qty;
+  return launch_mode<kMeans>(C, st, A, stream);
+}
+
+}  // namespace fm

@@ -40,8 +40,10 @@ constexpr int kResRows = 8;
 // Rows (environments) per workgroup of the fused kernel: 16 * row_tiles.
 struct FusedTuning {
   int row_tiles = 0;  // streamed: 0 chooses from the problem size
-  int schedule = 0;   // 0: resident, else streamed, when the shape allows; 1: streamed when the
-                      // shape allows; 2: always the generic schedule
+  int schedule = 0;   // 0: resident when the shape allows and N fills at most one workgroup per
+                      // compute unit, else streamed when the shape allows; 1: streamed when the
+                      // shape allows; 2: always the generic schedule; 3: resident whenever the
+                      // shape allows
   int tile_envs = 0;  // resident / streamed: environments per workgroup, 0: fill the compute units
 };
 

@@ -1079,17 +1079,23 @@ hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const Ens
       if (per_cu < F.tile_envs) F.tile_envs = std::max(per_cu, 1);
     }
   }
-  if (tune.schedule == 0 && fused_resident_shape(C, E)) {
+  int cus = 0;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 0;
+  }
+  // The resident schedule runs one workgroup of up to eight environments per compute unit; past
+  // one workgroup per compute unit the streamed schedule's wider tiles do better.
+  const bool resident = fused_resident_shape(C, E) &&
+                        (tune.schedule == 3 || (tune.schedule == 0 && cus > 0 && C.N <= kResRows * cus));
+  if (resident) {
     // Up to eight environments per workgroup, fewer when that leaves compute units idle.
     F.tile_envs = kResRows;
-    if (tune.tile_envs > 0) {
+    if (tune.tile_envs > 0)
       F.tile_envs = std::min(tune.tile_envs, kResRows);
-    } else {
-      int dev = 0, cus = 0;
-      if (hipGetDevice(&dev) == hipSuccess &&
-          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-        F.tile_envs = std::max(1, std::min(kResRows, (C.N + cus - 1) / cus));
-    }
+    else if (cus > 0)
+      F.tile_envs = std::max(1, std::min(kResRows, (C.N + cus - 1) / cus));
     return launch_resident(C, st, E, F, eps_chunk, mt_chunk, stream);
   }
   if (tune.schedule != 2 && fused_streamed_shape(C, E))

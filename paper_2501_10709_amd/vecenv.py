@@ -83,9 +83,15 @@ class VecEnv:
         """Environments per workgroup of the environment kernels (0: size-based default)."""
         return B.env_set_tile(self.handle, envs_per_group)
 
+    def set_step_kernel(self, kernel=0, envs_per_wave=0):
+        """Environment-step kernel: 0 by shape, 1 the tile kernel, 2 one lane per environment;
+        environments per wavefront of the lane kernel (0: by N)."""
+        B.env_set_step_kernel(self.handle, kernel, envs_per_wave)
+
     def set_fused_tuning(self, schedule=0, row_tiles=0, tile_envs=0):
-        """Fused-rollout tuning: schedule (0 by shape, 2 generic), MFMA row tiles per workgroup
-        (1, 2; 0 by N) and environments per workgroup (0: fill the compute units)."""
+        """Fused-rollout tuning: schedule (0 by shape and size, 1 streamed, 2 generic, 3 resident),
+        MFMA row tiles per workgroup (1, 2; 0 by N) and environments per workgroup (0: fill the
+        compute units)."""
         B.env_set_fused_tuning(self.handle, schedule, row_tiles, tile_envs)
 
     def reset(self, return_obs=True):

@@ -114,6 +114,8 @@ def test_env_set_tile_validation(lib):
     assert "NULL" in B.fm_last_error()
     assert lib.env_set_fused_tuning(None, 0, 0, 0) == B.FM_ERR_INVALID
     assert "NULL" in B.fm_last_error()
+    assert lib.env_set_step_kernel(None, 0, 0) == B.FM_ERR_INVALID
+    assert "NULL" in B.fm_last_error()
 
 
 def test_batch_argument_validation(lib):

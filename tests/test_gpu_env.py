@@ -31,15 +31,22 @@ def _to_np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("name,N,D,I,T,seed,extra", CASES, ids=[c[0] for c in CASES])
-def test_driven_rollout_matches_oracle(name, N, D, I, T, seed, extra):
+KERNELS = {0: "by-shape", 1: "tile", 2: "lane"}
+DRIVEN = [c + (k,) for c in CASES for k in KERNELS if not (k == 2 and c[2] > 32)]
+
+
+@pytest.mark.parametrize("name,N,D,I,T,seed,extra,kernel", DRIVEN, ids=[f"{c[0]}-{KERNELS[c[-1]]}" for c in DRIVEN])
+def test_driven_rollout_matches_oracle(name, N, D, I, T, seed, extra, kernel):
+    """kernel 0 picks by shape and size (the tile kernel below 24576 environments), 1 the tile
+    kernel, 2 the lane kernel (one lane per environment) where the shape allows (D <= 32)."""
     import torch
     from paper_2501_10709_amd.vecenv import VecEnv
     dev = cuda()
-    print(f"[driven] {name}", flush=True)
+    print(f"[driven] {name} kernel {kernel}", flush=True)
     cfg, m = env_case(N, D, I, T, seed, **extra)
     acts = make_actions(seed + 100, T, N, D)
     env = VecEnv(cfg, m.close, m.ind, device=dev)
+    env.set_step_kernel(kernel)
     obs0 = _to_np(env.reset())
     traj = env.rollout(T, actions=torch.from_numpy(acts).to(dev))
     st = env.read_state()
@@ -55,6 +62,92 @@ def test_driven_rollout_matches_oracle(name, N, D, I, T, seed, extra):
     # Same operation order as the oracle: bit-exact float64 too.
     assert np.array_equal(_to_np(st["cash"]), ref["cash"])
     assert np.array_equal(_to_np(st["asset"]), ref["asset"])
+
+
+LANE = [
+    # N, D, I, envs per wavefront (0: by N), T, cash, hmax
+    (197, 30, 5, 64, 9, 1e6, 100),   # a partial last wavefront and workgroup
+    (197, 30, 5, 3, 9, 1e6, 100),
+    (130, 32, 5, 1, 7, 1e6, 100),    # 32 stocks: every register slot in use
+    (90, 16, 4, 7, 8, 1e6, 100),
+    (90, 9, 3, 0, 8, 1e6, 100),
+    (50, 8, 2, 5, 8, 1e6, 100),
+    (61, 30, 5, 0, 12, 4e3, 50),     # cash binds: partial fills on most days
+]
+
+
+@pytest.mark.parametrize("N,D,I,M,T,cash,hmax", LANE)
+def test_lane_kernel_widths_match_oracle(N, D, I, M, T, cash, hmax):
+    """The lane kernel at each register width (8, 16, 32 stocks) and wavefront width, driven by
+    the same actions as the oracle: holdings, quantities, states and float64 cash bit-exact."""
+    import torch
+    from paper_2501_10709_amd.vecenv import VecEnv
+    dev = cuda()
+    print(f"[lane] N={N} D={D} I={I} M={M} T={T} cash={cash}", flush=True)
+    cfg, m = env_case(N, D, I, T, 40 + D, hmax=hmax, cash=cash)
+    acts = make_actions(77 + D, T, N, D)
+    env = VecEnv(cfg, m.close, m.ind, device=dev)
+    env.set_step_kernel(2, M)
+    obs0 = _to_np(env.reset())
+    traj = env.rollout(T, actions=torch.from_numpy(acts).to(dev))
+    st = env.read_state()
+    traj = {k: _to_np(v) for k, v in traj.items()}
+    ref = check_replay(cfg, m, traj, obs0)
+    assert np.array_equal(_to_np(st["hold"]), ref["hold"])
+    assert np.array_equal(_to_np(st["cash"]), ref["cash"])
+    assert np.array_equal(_to_np(st["asset"]), ref["asset"])
+    assert np.abs(traj["qty"]).sum() > 0
+
+
+def test_driven_large_batch_by_shape_sampled():
+    """30011 environments: the size-based choice takes the lane kernel (30 environments per
+    wavefront, the last wavefront ragged); a sample including the wavefront edges is replayed."""
+    import torch
+    from paper_2501_10709_amd.vecenv import VecEnv
+    dev = cuda()
+    N, D, T = 30011, 30, 4
+    cfg, m = env_case(N, D, 5, T, 9)
+    acts = make_actions(109, T, N, D)
+    env = VecEnv(cfg, m.close, m.ind, device=dev)
+    obs0 = _to_np(env.reset())
+    traj = env.rollout(T, actions=torch.from_numpy(acts).to(dev))
+    traj = {k: _to_np(v) for k, v in traj.items()}
+    ids = [0, 1, 29, 30, 31, 15000, 29999, 30000, 30001, 30009, 30010]
+    check_replay(cfg, m, traj, obs0, env_ids=ids)
+
+
+def test_lane_kernel_plain_steps_match_tile_kernel():
+    """The plain path's ensemble steps (mean of the actors, noise, clip, trade) through the lane
+    kernel and through the tile kernel: the same arithmetic, so every output is bit-identical."""
+    import torch
+    from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
+    from _helpers import actors_case
+    dev = cuda()
+    N, D, T = 77, 30, 12
+    cfg, m = env_case(N, D, 5, T, 1001)
+    _, _, packed = actors_case(3, 211, 64, D)
+    ens = Ensemble(packed, 3, 211, 64, D, dtype="f32", max_batch=N, device=dev)
+    out = []
+    for kernel, M in ((1, 0), (2, 0), (2, 5)):
+        env = VecEnv(cfg, m.close, m.ind, device=dev)
+        env.set_step_kernel(kernel, M)
+        env.reset(return_obs=False)
+        out.append(env.rollout(T, ens=ens, sigma=0.1, noise_key=7, path="plain"))
+    for other in out[1:]:
+        for k in out[0]:
+            assert torch.equal(out[0][k], other[k]), k
+
+
+def test_step_kernel_choice_validation():
+    from paper_2501_10709_amd.vecenv import VecEnv
+    dev = cuda()
+    cfg, m = env_case(8, 40, 5, 4, 3)
+    env = VecEnv(cfg, m.close, m.ind, device=dev)
+    with pytest.raises(RuntimeError):
+        env.set_step_kernel(2)  # 40 stocks: beyond the lane kernel
+    with pytest.raises(RuntimeError):
+        env.set_step_kernel(3)
+    env.set_step_kernel(0)
 
 
 def test_step_api_matches_oracle_and_reports_done():

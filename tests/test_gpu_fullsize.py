@@ -61,18 +61,38 @@ def test_paper_scale_closed_loop_sampled(dtype, path, tol, schedule):
     print(f"  worst action error {worst:.3e}", flush=True)
 
 
-@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("schedule", [0, 3])
 def test_precision_scale_fused_sampled(schedule):
     """N=8192, bfloat16 fused path, all 252 steps: four 64-day launches, so the trading state
-    crosses three chunk boundaries in HBM.  The resident schedule runs 1024 workgroups of eight
-    environments; the streamed one 32-row workgroups."""
+    crosses three chunk boundaries in HBM.  The default choice at this size (schedule 0) is the
+    streamed schedule with 32-row workgroups; the resident schedule (forced, 3) runs 1024
+    workgroups of eight environments."""
     w = PRECISION
     print(f"[full] fused bf16 N=8192 T=252 schedule {schedule}", flush=True)
     cfg, m, actors, obs0, traj = _closed(w, 8192, 252, "bf16", "fused", schedule=schedule)
     ids = _sample(8192, seed=1)
     sub = {k: _np(v[:, ids]) for k, v in traj.items()}
     check_replay(cfg, m, sub, obs0[ids])
-    check_actions(actors, "bf16", sub, obs0[ids], w.sigma, w.noise_key, TOL_BF16, id_map=ids)
+    worst = check_actions(actors, "bf16", sub, obs0[ids], w.sigma, w.noise_key, TOL_BF16, id_map=ids)
+    # The second number of reading 17: the same GPU actions against the float32 master weights
+    # (the bfloat16 rounding of the weights included), reported, gated only loosely.
+    worst_master = check_actions(actors, "f32", sub, obs0[ids], w.sigma, w.noise_key, 0.1, id_map=ids)
+    print(f"  worst action error {worst:.3e} against the oracle on the device weights, {worst_master:.3e} "
+          f"against the float32 master weights ({len(ids)} environments x 252 steps)", flush=True)
+    if schedule == 0:
+        # Episode returns against the oracle's own closed loop on the first 64 environments: the
+        # bfloat16 actions change integer orders now and then, so the trajectories drift apart;
+        # the difference is reported, and asserted only to stay within the returns' own size.
+        n = 64
+        gpu_ret = _np(traj["rew"][:, :n]).sum(axis=0)
+        ref = rollout_closed_loop(cfg.replace(n_envs=n), m.close, m.ind, actors, 252, w.sigma, w.noise_key)
+        ora_ret = ref["reward"].sum(axis=0)
+        diff = np.abs(gpu_ret - ora_ret)
+        print(f"  episode return over 252 days, {n} environments: oracle mean {ora_ret.mean():.6g} "
+              f"(spread {ora_ret.std():.3g}), mean |gpu - oracle| {diff.mean():.3g}, max {diff.max():.3g}, "
+              f"mean difference {abs(gpu_ret.mean() - ora_ret.mean()):.3g}", flush=True)
+        assert np.isfinite(gpu_ret).all()
+        assert diff.mean() <= np.abs(ora_ret).mean() + ora_ret.std()
 
 
 @pytest.mark.parametrize("D,N,T", [(50, 300, 70), (30, 130, 66)])
@@ -102,7 +122,7 @@ def test_generic_schedule_hidden_256(D, N, T):
     print(f"  worst action error {worst:.3e}", flush=True)
 
 
-@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("schedule", [3, 1])
 def test_ragged_two_row_tiles_fused(schedule):
     """A batch that is not a multiple of the workgroup tile (8 environments resident, 32 streamed)."""
     w = PRECISION
