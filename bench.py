@@ -542,9 +542,9 @@ def main():
     mean_launch_ms = launch_ms / len(launches)
     steps_per_launch = launch_steps / len(launches)
     env_b = env_bytes_per_env_step(D, S) * env_steps
-    d_s = float(np.mean(d_ker)) / 1e3
+    d_s = float(np.median(d_ker)) / 1e3
     achieved_gbs = env_b / d_s / 1e9
-    l_s = float(np.mean(l_ker)) / 1e3
+    l_s = float(np.median(l_ker)) / 1e3
     large_gbs = env_bytes_per_env_step(D, S) * NL * TL / l_s / 1e9
     rec = {
         "metric": METRIC,

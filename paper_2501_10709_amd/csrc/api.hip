@@ -733,7 +733,7 @@ fm_status env_set_step_kernel(fm_env* env, int32_t kernel, int32_t envs_per_wave
   if (kernel < 0 || kernel > 2) return fail(FM_ERR_INVALID, "kernel must be 0 (by shape), 1 (tile) or 2 (lane)");
   if (envs_per_wave < 0 || envs_per_wave > 64) return fail(FM_ERR_INVALID, "envs_per_wave must be in 0..64");
   if (kernel == 2 && !fm::env_lane_shape(env->C))
-    return fail(FM_ERR_UNSUPPORTED, "the lane kernel takes at most 32 stocks and (2 + n_ind) * n_stocks <= 256");
+    return fail(FM_ERR_UNSUPPORTED, "the lane kernel takes at most 32 stocks and (2 + n_ind) * n_stocks < 256");
   env->step_kernel = kernel;
   env->lane_envs = envs_per_wave;
   return FM_OK;

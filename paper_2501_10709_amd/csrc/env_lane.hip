@@ -10,10 +10,11 @@
 // the four wavefronts of a workgroup run free of each other.
 //
 // Per step a wavefront
-//   1. writes the step's inputs, fetched into registers during the previous step, to its LDS
-//      area: the market row [close[t] | close[t+1] | ind[t+1]] and, driven, the M x D actions;
-//   2. requests the next step's inputs into the same registers (coalesced: consecutive lanes
-//      read consecutive floats of the tile's contiguous block);
+//   1. waits for the step's inputs, requested one step ahead straight from HBM into its LDS
+//      area (buffer loads with an LDS destination: the market rows and, driven, the tile of
+//      actions, 64 consecutive floats per instruction), and spreads the actions into
+//      per-environment rows;
+//   2. requests the next step's inputs;
 //   3. runs the chains: lane m reads its action row and the day's prices from LDS;
 //   4. writes the state rows' cash and holdings entries and the executed quantities to LDS;
 //   5. stores the tile's state rows, quantities and rewards as wave-wide runs of addresses.
@@ -31,7 +32,7 @@ constexpr int kRow = 33;        // LDS stride of the per-environment rows: lane 
                                 // own row fall in distinct banks
 constexpr int kMaxMkt = 256;    // market floats staged per step, (2 + I) * D
 constexpr int kMaxEnvs = 64;    // environments per wavefront
-constexpr int kColGroups = (kMaxMkt + 1 + 63) / 64;  // 64-column groups of a state row (S <= 257)
+constexpr int kColGroups = kMaxMkt / 64;             // 64-column groups of a state row (S <= 256)
 constexpr int kNoStore = 1 << 30;                     // a byte offset beyond any store range
 
 enum LaneMode { kDriven = 0, kMeans = 1 };
@@ -51,7 +52,16 @@ struct LaneArgs {
   int* qty;           // [n_steps][N][D] or null
 };
 
-__host__ __device__ inline int wave_floats(int M) { return kMaxMkt + 64 + 2 * (M + 1) * kRow; }
+constexpr int kMktClose = 64;   // LDS floats per buffer of close[t] | close[t+1] (2D <= 64)
+constexpr int kMktInd = 256;    // LDS floats per buffer of ind[t+1] (I*D < 256)
+constexpr int kWaitVm0 = 0x0F70;    // s_waitcnt vmcnt(0)
+constexpr int kWaitLgkm0 = 0xC07F;  // s_waitcnt lgkmcnt(0)
+
+// LDS floats of a wavefront's staging area and of its whole area, for M environments of D stocks.
+__host__ __device__ inline int stage_floats(int M, int D) { return (M * D + 63) / 64 * 64; }
+__host__ __device__ inline int wave_floats(int M, int D) {
+  return 2 * kMktClose + 2 * kMktInd + stage_floats(M, D) + 2 * (M + 1) * kRow;
+}
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(const float* base, int n_floats) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, 4 * n_floats, 0x00020000);
@@ -137,19 +147,17 @@ __global__ __launch_bounds__(kWaves * 64) void env_lane_kernel(EnvConst C, EnvSt
   const int MM = A.M;
   const int n0 = (blockIdx.x * kWaves + wave) * MM;
   if (n0 >= C.N) return;  // the whole wavefront; no barrier follows
-  const int N = C.N, D = C.D, S = C.S;
+  const int N = C.N, D = C.D, S = C.S, ID = C.I * D;
   const int M = min(MM, N - n0);
   const int MD = M * D;
-  const int n_mkt = (2 + C.I) * D;
   const float inv_d = 1.0f / static_cast<float>(D);
-  float* mkt = lds + wave * wave_floats(MM);
-  float* px = mkt + kMaxMkt;      // close[t][d], zero from D to 31
-  float* pn = px + 32;            // close[t+1][d], likewise
+  float* mcl = lds + wave * wave_floats(MM, D);  // [2][64]: close[t] | close[t+1], zero from 2D
+  float* mind = mcl + 2 * kMktClose;             // [2][256]: ind[t+1]
+  float* stage = mind + 2 * kMktInd;             // the driven tile as fetched, [M*D]
   // Rows of kRow floats, M + 1 of each (idle lanes work on the spare last row):
-  float* tile = pn + 32;                // actions / actor means, then orders, then quantities
-  float* ent = tile + (MM + 1) * kRow;  // noise, then the state rows' cash and holdings entries
+  float* tile = stage + stage_floats(MM, D);  // actions / actor means, then orders, then quantities
+  float* ent = tile + (MM + 1) * kRow;        // noise, then the state rows' cash and holdings entries
   const bool active = lane < M;
-  const int lr = active ? lane : MM;  // the lane's LDS row (idle lanes share the spare row)
   const int n = n0 + lane;
 
   // The holdings through a buffer resource over [D][N]: rows d >= D read 0 and are not stored.
@@ -167,33 +175,23 @@ __global__ __launch_bounds__(kWaves * 64) void env_lane_kernel(EnvConst C, EnvSt
   // orders and quantities of those stocks.
   for (int i = lane; i < 2 * (MM + 1) * kRow; i += 64) tile[i] = 0.0f;
 
-  // Inputs of step it in registers: market floats i = lane + 64 j (close[t] and close[t+1] are
-  // adjacent rows of close), lane d < 32's prices of stock d (zero beyond D), and the driven
-  // tile's floats i = lane + 64 j.
   // Inside the step loop the lane index L is re-derived each step through an opaque copy, so
   // the per-lane addresses and masks are recomputed rather than held in registers.
-  int L = lane, LR = lr;
-  float pm[kMaxMkt / 64], ppx = 0.0f, ppn = 0.0f;
-  float pa[DP];
+  int L = lane;
+  // Step it's inputs go from HBM straight into LDS buffer it & 1 (the market rows; lanes past
+  // the ranges write zeros) and, driven, into the staging area (64 floats per instruction,
+  // consecutive lanes on consecutive floats of the tile's contiguous block).
   auto fetch = [&](int it) {
-    const int t = A.t0 + it;
-    const float* cl = C.close + static_cast<size_t>(t) * D;
-    const float* ind = C.ind + static_cast<size_t>(t + 1) * C.I * D;
-#pragma unroll
-    for (int j = 0; j < kMaxMkt / 64; ++j) {
-      const int i = min(L + 64 * j, n_mkt - 1);
-      pm[j] = i < 2 * D ? cl[i] : ind[i - 2 * D];
-    }
-    const int dl = min(L, D - 1);
-    ppx = L < D ? cl[dl] : 0.0f;
-    ppn = L < D ? cl[D + dl] : 0.0f;
+    const int t = A.t0 + it, b = it & 1;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(range_rsrc(C.close + static_cast<size_t>(t) * D, 2 * D),
+                                             mcl + b * kMktClose, 4, 4 * L, 0, 0, 0);
+    const __amdgpu_buffer_rsrc_t ri = range_rsrc(C.ind + static_cast<size_t>(t + 1) * ID, ID);
+    for (int j = 0; 64 * j < ID; ++j)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ri, mind + b * kMktInd + 64 * j, 4, 4 * (L + 64 * j), 0, 0, 0);
     if (MODE == kDriven) {
-      const __amdgpu_buffer_rsrc_t r = range_rsrc(A.act + (static_cast<size_t>(it) * N + n0) * D, MD);
-      int md = MD;
-      __asm__ volatile("" : "+s"(md));  // a fresh value: the slice tests below are not kept live
-#pragma unroll
-      for (int j = 0; j < DP; ++j)
-        if (64 * j < md) pa[j] = range_load(r, L + 64 * j);
+      const __amdgpu_buffer_rsrc_t ra = range_rsrc(A.act + (static_cast<size_t>(it) * N + n0) * D, MD);
+      for (int j = 0; 64 * j < MD; ++j)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, stage + 64 * j, 4, 4 * (L + 64 * j), 0, 0, 0);
     }
   };
   // Tile float i = m * D + d goes to row m, entry d.
@@ -214,40 +212,24 @@ __global__ __launch_bounds__(kWaves * 64) void env_lane_kernel(EnvConst C, EnvSt
     return tile[m * kRow + (i - m * D)];
   };
 
-  // The state rows [cash, close[t+1] (D), holdings (D), ind[t+1] (I*D)]: lane column f = lane +
-  // 64 g is read from LDS (relative to mkt) at col_src + m * col_stride for row m -- the
-  // environment's entries row for the cash and holdings columns, the market row (stride 0)
-  // otherwise -- scaled by col_scale and stored at byte col_b of the row; columns past S store
-  // nowhere (col_b beyond every range of at most 64 rows, and no int overflow).
-  const int ent_off = static_cast<int>(ent - mkt);
-  int col_src[kColGroups], col_stride[kColGroups], col_b[kColGroups];
-  float col_scale[kColGroups];
-#pragma unroll
-  for (int g = 0; g < kColGroups; ++g) {
-    const int f = lane + 64 * g;
-    const bool own = f == 0 || (f > D && f <= 2 * D);
-    col_src[g] = own ? ent_off + (f == 0 ? 0 : f - D) : (f <= D ? D + f - 1 : min(f, S - 1) - 1);
-    col_stride[g] = own ? kRow : 0;
-    col_scale[g] = (f >= 1 && f <= D) ? C.price_scale : 1.0f;
-    col_b[g] = f < S ? 4 * f : kNoStore;
-  }
-
   fetch(0);
   for (int it = 0; it < A.n_steps; ++it) {
 #pragma clang fp contract(off)
-    const int t = A.t0 + it;
+    const int t = A.t0 + it, b = it & 1;
     const size_t row0 = static_cast<size_t>(it) * N + n0;
     L = lane;
     __asm__ volatile("" : "+v"(L));
-    LR = L < M ? L : MM;
-#pragma unroll
-    for (int j = 0; j < kMaxMkt / 64; ++j)
-      if (L + 64 * j < n_mkt) mkt[L + 64 * j] = pm[j];
-    if (L < 32) {
-      px[L] = ppx;
-      pn[L] = ppn;
-    }
-    if (MODE == kDriven) tile_put(pa);
+    const int LR = L < M ? L : MM;
+    const float* px = mcl + b * kMktClose;  // close[t][d]; entries from D on are finite
+    const float* pn = px + D;               // close[t+1][d]; entries from D on are finite
+    const float* ind = mind + b * kMktInd;
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);   // step it's inputs have landed in LDS
+    if (MODE == kDriven)
+      for (int i = L; i < MD; i += 64) {
+        const int m = div_small(i, inv_d);
+        tile[m * kRow + (i - m * D)] = stage[i];
+      }
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);  // the staging area is read before it is refilled
     if (it + 1 < A.n_steps) fetch(it + 1);
     wave_lds_sync();
 
@@ -307,21 +289,38 @@ __global__ __launch_bounds__(kWaves * 64) void env_lane_kernel(EnvConst C, EnvSt
     if (A.qty)
       wave_store_row(A.qty + row0 * D, MD, L, [&](int i) { return __float_as_int(tile_get(i)); });
     if (A.obs) {
-      // Four rows per batch: every read is issued before the first store.  Rows past M read
-      // row M - 1 and their stores fall beyond the resource's range, as do columns past S.
+      // The state rows [cash, close[t+1] (D), holdings (D), ind[t+1] (I*D)]: lane column
+      // f = L + 64 g of row m is read from LDS at src + m * stride -- the environment's entries
+      // row for the cash and holdings columns, a market row (stride 0) otherwise -- scaled, and
+      // stored at byte 4 f of the row; columns past S store nowhere (an offset beyond every
+      // range of at most 64 rows).  Four rows per batch: every read is issued before the first
+      // store; rows past M read row M - 1 and store beyond the range.
       const __amdgpu_buffer_rsrc_t orow = range_rsrc(A.obs + row0 * S, M * S);
+      int src[kColGroups], stride[kColGroups], cb[kColGroups];
+      float scale[kColGroups];
+      const int ent_o = static_cast<int>(ent - mcl), pn_o = static_cast<int>(pn - mcl);
+      const int ind_o = static_cast<int>(ind - mcl);
+#pragma unroll
+      for (int g = 0; g < kColGroups; ++g) {
+        const int f = L + 64 * g;
+        const bool own = f == 0 || (f > D && f <= 2 * D);
+        src[g] = own ? ent_o + (f == 0 ? 0 : f - D) : (f <= D ? pn_o + f - 1 : ind_o + min(f, S - 1) - 1 - 2 * D);
+        stride[g] = own ? kRow : 0;
+        scale[g] = (f >= 1 && f <= D) ? C.price_scale : 1.0f;
+        cb[g] = f < S ? 4 * f : kNoStore;
+      }
       for (int m0 = 0; m0 < M; m0 += 4) {
-        float v[4][kColGroups];
+        float x[4][kColGroups];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int g = 0; g < kColGroups; ++g) v[r][g] = mkt[col_src[g] + min(m0 + r, M - 1) * col_stride[g]];
+          for (int g = 0; g < kColGroups; ++g) x[r][g] = mcl[src[g] + min(m0 + r, M - 1) * stride[g]];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
           for (int g = 0; g < kColGroups; ++g)
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[r][g] * col_scale[g]), orow,
-                                                  4 * (m0 + r) * S + col_b[g], 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x[r][g] * scale[g]), orow, 4 * (m0 + r) * S + cb[g],
+                                                  0, 0);
       }
     }
     wave_lds_sync();  // the stores have read the LDS rows before the next step rewrites them
@@ -340,7 +339,7 @@ template <int MODE, int DP>
 hipError_t launch_dp(const EnvConst& C, const EnvState& st, const LaneArgs& A, hipStream_t stream) {
   const int waves = (C.N + A.M - 1) / A.M;
   const int grid = (waves + kWaves - 1) / kWaves;
-  const size_t lds = sizeof(float) * kWaves * wave_floats(A.M);
+  const size_t lds = sizeof(float) * kWaves * wave_floats(A.M, C.D);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(env_lane_kernel<MODE, DP>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
@@ -371,7 +370,7 @@ hipError_t launch_mode(const EnvConst& C, const EnvState& st, LaneArgs A, hipStr
 }  // namespace
 
 bool env_lane_shape(const EnvConst& C) {
-  return C.D >= 1 && C.D <= 32 && (2 + C.I) * C.D <= kMaxMkt;
+  return C.D >= 1 && C.D <= 32 && (2 + C.I) * C.D < kMaxMkt;
 }
 
 hipError_t launch_env_lane_given(const EnvConst& C, const EnvState& st, int t0, int n_steps, const float* act,

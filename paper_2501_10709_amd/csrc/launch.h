@@ -23,7 +23,7 @@ hipError_t launch_env_ensemble_step(const EnvConst& C, const EnvState& st, int t
                                     uint64_t key, int64_t env_offset, float* obs, float* act_out,
                                     double* rew, int* qty, int M, hipStream_t stream);
 // One lane per environment (env_lane.hip): the trading chain in registers, for D <= 32 and
-// (2 + I) * D <= 256.  envs_per_wave 0: by N (one wavefront per SIMD, up to 64 environments).
+// (2 + I) * D < 256.  envs_per_wave 0: by N (one wavefront per SIMD, up to 64 environments).
 bool env_lane_shape(const EnvConst& C);
 hipError_t launch_env_lane_given(const EnvConst& C, const EnvState& st, int t0, int n_steps, const float* act,
                                  float* obs, double* rew, int* qty, int envs_per_wave, hipStream_t stream);
