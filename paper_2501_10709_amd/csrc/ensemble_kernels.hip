@@ -1,5 +1,7 @@
-// Ensemble kernels: weight packing, the per-actor MLP over 16-row tiles, and the combine step
+// Ensemble kernels: weight packing, the per-actor MLP over 16- or 32-row tiles, and the combine step
 // (weighted average of the actor means, Gaussian noise, clip) used by ensemble_act.
+#include <algorithm>
+
 #include "device_common.h"
 #include "launch.h"
 #include "mlp_device.h"
@@ -79,23 +81,25 @@ __global__ void copy_pad_kernel(const float* __restrict__ src, int n, int n_pad,
   if (i < n_pad) dst[i] = i < n ? src[i] : 0.0f;
 }
 
-// The MLP of actor blockIdx.y on rows [16*blockIdx.x, +16) of obs [n][S]; writes tanh outputs to
-// mu [K][n][A].
-template <int DT, int TMAX>
-__global__ __launch_bounds__(256) void mlp_kernel(EnsDev E, const float* __restrict__ obs, int n,
+// The MLP of actor blockIdx.y on rows [16 RT blockIdx.x, +16 RT) of obs [n][S]; writes tanh
+// outputs to mu [K][n][A].
+template <int DT, int TMAX, int RT, int NW>
+__global__ __launch_bounds__(64 * NW) void mlp_kernel(EnsDev E, const float* __restrict__ obs, int n,
                                                   float* __restrict__ mu) {
   using act_t = typename MT<DT>::act_t;
+  constexpr int R = 16 * RT;
   extern __shared__ __align__(16) unsigned char smem[];
   const int k = blockIdx.y;
-  const int row0 = blockIdx.x * 16;
+  const int row0 = blockIdx.x * R;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int st0 = act_stride<DT>(E.S_pad), sth = act_stride<DT>(E.H);
+  // Two LDS regions: the state tile, then layer 2's outputs, in the first; layer 1's in the second.
   act_t* x0 = reinterpret_cast<act_t*>(smem);
-  act_t* x1 = x0 + 16 * st0;
-  act_t* x2 = x1 + 16 * sth;
+  act_t* x1 = x0 + R * max(st0, sth);
+  act_t* x2 = x0;
 
-  // Stage the state tile, zero-padded to S_pad columns and 16 rows.
-  for (int i = threadIdx.x; i < 16 * E.S_pad; i += 256) {
+  // Stage the state tile, zero-padded to S_pad columns and R rows.
+  for (int i = threadIdx.x; i < R * E.S_pad; i += 64 * NW) {
     const int r = i / E.S_pad, c = i - r * E.S_pad;
     float v = 0.0f;
     if (c < E.S && row0 + r < n) v = obs[static_cast<size_t>(row0 + r) * E.S + c];
@@ -110,30 +114,30 @@ __global__ __launch_bounds__(256) void mlp_kernel(EnsDev E, const float* __restr
   const int row_q = 4 * (lane >> 4), col_l = lane & 15;
 
   auto hidden_epi = [&](act_t* out, int ost, const float* bias) {
-    return [=](int, int c, floatx4 acc) {
+    return [=](int rt, int, int c, floatx4 acc) {
       const int col = 16 * c + col_l;
       const float b = bias[col];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) out[(row_q + r) * ost + col] = static_cast<act_t>(fast_tanh(acc[r] + b));
+      for (int r = 0; r < 4; ++r) out[(16 * rt + row_q + r) * ost + col] = static_cast<act_t>(fast_tanh(acc[r] + b));
     };
   };
   const int ht = E.H / 16;
-  mlp_layer<DT, TMAX>(x0, st0, E.S_pad, P + E.off_w1, ht, wave, lane, hidden_epi(x1, sth, b1));
+  mlp_layer<DT, TMAX, RT, NW>(x0, st0, E.S_pad, P + E.off_w1, ht, wave, lane, hidden_epi(x1, sth, b1));
   __syncthreads();
-  mlp_layer<DT, TMAX>(x1, sth, E.H, P + E.off_w2, ht, wave, lane, hidden_epi(x2, sth, b2));
+  mlp_layer<DT, TMAX, RT, NW>(x1, sth, E.H, P + E.off_w2, ht, wave, lane, hidden_epi(x2, sth, b2));
   __syncthreads();
   float* mu_k = mu + static_cast<size_t>(k) * n * E.A;
-  mlp_layer<DT, TMAX>(x2, sth, E.H, P + E.off_w3, E.A_pad / 16, wave, lane,
-                      [&](int, int c, floatx4 acc) {
-                        const int col = 16 * c + col_l;
-                        if (col >= E.A) return;
-                        const float b = b3[col];
+  mlp_layer<DT, TMAX, RT, NW>(x2, sth, E.H, P + E.off_w3, E.A_pad / 16, wave, lane,
+                          [&](int rt, int, int c, floatx4 acc) {
+                            const int col = 16 * c + col_l;
+                            if (col >= E.A) return;
+                            const float b = b3[col];
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                          const int row = row0 + row_q + r;
-                          if (row < n) mu_k[static_cast<size_t>(row) * E.A + col] = fast_tanh(acc[r] + b);
-                        }
-                      });
+                            for (int r = 0; r < 4; ++r) {
+                              const int row = row0 + 16 * rt + row_q + r;
+                              if (row < n) mu_k[static_cast<size_t>(row) * E.A + col] = fast_tanh(acc[r] + b);
+                            }
+                          });
 }
 
 // a_bar = sum_k w_k mu_k; a = clip(a_bar + sigma * eps, -1, 1).  One thread per (row, group of
@@ -167,27 +171,34 @@ __global__ void combine_kernel(int K, int n, int A, const float* __restrict__ mu
 template <int DT>
 hipError_t launch_mlp_dt(const EnsDev& E, const float* obs, int n, float* mu, hipStream_t stream) {
   const int st0 = act_stride<DT>(E.S_pad), sth = act_stride<DT>(E.H);
-  const size_t lds = static_cast<size_t>(16) * (st0 + 2 * sth) * MT<DT>::kElem;
-  const dim3 grid((n + 15) / 16, E.K);
-  const int tiles_per_wave = (E.H / 16 + 3) / 4;
-  auto go = [&](auto kern) -> hipError_t {
+  // Tiles of 32 rows (each weight fragment serves two row tiles) on sixteen wavefronts, each
+  // owning one or two output column tiles of every layer; a single 16-row tile on four
+  // wavefronts when the batch fits one.  Measured on MI355X (float32, hidden 256, N = 2048):
+  // 32 rows on 16 wavefronts beat 16 rows on 4 (the former schedule) by 15% per rollout, although
+  // they leave a quarter of the compute units idle.
+  const bool two = n > 16;
+  const int rt = two ? 2 : 1;
+  const size_t lds = static_cast<size_t>(16 * rt) * (std::max(st0, sth) + sth) * MT<DT>::kElem;
+  const dim3 grid((n + 16 * rt - 1) / (16 * rt), E.K);
+  auto go = [&](auto kern, int waves) -> hipError_t {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, stream, E, obs, n, mu);
+    hipLaunchKernelGGL(kern, grid, dim3(64 * waves), lds, stream, E, obs, n, mu);
     return hipGetLastError();
   };
-  if (tiles_per_wave <= 2) return go(mlp_kernel<DT, 2>);
-  if (tiles_per_wave <= 4) return go(mlp_kernel<DT, 4>);
-  return go(mlp_kernel<DT, 8>);
+  if (two) {
+    const int tiles_per_wave = (E.H / 16 + 15) / 16;
+    if (tiles_per_wave <= 2) return go(mlp_kernel<DT, 2, 2, 16>, 16);
+    return go(mlp_kernel<DT, 4, 2, 16>, 16);
+  }
+  const int tiles_per_wave = (E.H / 16 + 3) / 4;
+  if (tiles_per_wave <= 2) return go(mlp_kernel<DT, 2, 1, 4>, 4);
+  if (tiles_per_wave <= 4) return go(mlp_kernel<DT, 4, 1, 4>, 4);
+  return go(mlp_kernel<DT, 8, 1, 4>, 4);
 }
 
 }  // namespace
-
-size_t mlp_lds_bytes(int dtype, int S_pad, int H) {
-  return dtype == kF32 ? static_cast<size_t>(16) * (act_stride<kF32>(S_pad) + 2 * act_stride<kF32>(H)) * 4
-                       : static_cast<size_t>(16) * (act_stride<kBF16>(S_pad) + 2 * act_stride<kBF16>(H)) * 2;
-}
 
 hipError_t launch_pack_matrix(int dtype, const float* w, int kin, int nout, int kin_pad,
                               int nout_pad, void* out, hipStream_t stream) {

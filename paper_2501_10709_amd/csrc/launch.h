@@ -40,7 +40,6 @@ hipError_t launch_noise(uint64_t key, int64_t env_offset, int n, int t, int D, u
                         float* eps, hipStream_t stream);
 
 // Ensemble kernels (ensemble_kernels.hip).
-size_t mlp_lds_bytes(int dtype, int S_pad, int H);
 hipError_t launch_pack_matrix(int dtype, const float* w, int kin, int nout, int kin_pad,
                               int nout_pad, void* out, hipStream_t stream);
 hipError_t launch_copy_pad(const float* src, int n, int n_pad, float* dst, hipStream_t stream);

@@ -1,9 +1,9 @@
 // Ensemble MLP building blocks on MFMA (gfx950).
 //
 // Each actor is S -> H -> H -> A with tanh after every layer.  A workgroup evaluates one layer
-// for a 16-row tile of states: the tile's activations sit in LDS (row-major, padded rows), the
+// for a tile of 16 or 32 states: the tile's activations sit in LDS (row-major, padded rows), the
 // layer's weights are pre-packed so that every lane of a wavefront fetches the B-operand of an
-// MFMA with one contiguous load, and the four wavefronts of the workgroup split the layer's
+// MFMA with one contiguous load, and the wavefronts of the workgroup split the layer's
 // 16-column output tiles between them.
 //
 //   float32:  v_mfma_f32_16x16x4_f32, B packed [col tile][k/16][lane][4]
@@ -81,18 +81,21 @@ __device__ __forceinline__ floatx4 mfma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// One layer for the wavefront's column tiles c = wave, wave+4, ... (< ntiles).  sin: LDS tile
-// [16][in_stride] holding kin_pad valid (zero-padded) columns.  Calls epi(i, c, acc) for every
-// tile the wave owns.  The B-operand fragments of the next RING k-steps are in flight while the
-// current k-step's MFMAs run.
-template <int DT, int TMAX, class Epi>
+// One layer for RT row tiles of 16 and the wavefront's column tiles c = wave, wave + NW, ...
+// (< ntiles; NW wavefronts per workgroup).  sin: LDS tile [16 RT][in_stride] holding kin_pad valid (zero-padded) columns.
+// Calls epi(r, i, c, acc) for every (row tile r, column tile c) the wave owns.  Each B-operand
+// fragment serves all RT row tiles; the fragments of the next RING k-steps are in flight while
+// the current k-step's MFMAs run.
+template <int DT, int TMAX, int RT, int NW, class Epi>
 __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int in_stride,
                                           int kin_pad, const void* wp, int ntiles, int wave,
                                           int lane, Epi epi) {
   constexpr int RING = 4;
-  floatx4 acc[TMAX];
+  floatx4 acc[RT][TMAX];
 #pragma unroll
-  for (int i = 0; i < TMAX; ++i) acc[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int i = 0; i < TMAX; ++i) acc[r][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
   const int row = lane & 15, grp = lane >> 4;
   if constexpr (DT == kF32) {
     const float4* W = static_cast<const float4*>(wp);
@@ -101,7 +104,7 @@ __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int
     auto fetch = [&](float4 (&dst)[TMAX], int kq) {
 #pragma unroll
       for (int i = 0; i < TMAX; ++i) {
-        const int c = wave + 4 * i;
+        const int c = wave + NW * i;
         if (c < ntiles && kq < KQ) dst[i] = W[(static_cast<size_t>(c) * KQ + kq) * 64 + lane];
       }
     };
@@ -116,18 +119,21 @@ __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int
 #pragma unroll
           for (int i = 0; i < TMAX; ++i) b[i] = ring[j][i];
           fetch(ring[j], kq + RING);
-          float a[4];
+          float a[RT][4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) a[e] = sin[row * in_stride + 16 * kq + 4 * e + grp];
+          for (int r = 0; r < RT; ++r)
 #pragma unroll
-          for (int i = 0; i < TMAX; ++i) {
-            if (wave + 4 * i < ntiles) {
-              acc[i] = mfma_f32(a[0], b[i].x, acc[i]);
-              acc[i] = mfma_f32(a[1], b[i].y, acc[i]);
-              acc[i] = mfma_f32(a[2], b[i].z, acc[i]);
-              acc[i] = mfma_f32(a[3], b[i].w, acc[i]);
+            for (int e = 0; e < 4; ++e) a[r][e] = sin[(16 * r + row) * in_stride + 16 * kq + 4 * e + grp];
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int i = 0; i < TMAX; ++i) {
+              if (wave + NW * i < ntiles) {
+                const float bv = e == 0 ? b[i].x : e == 1 ? b[i].y : e == 2 ? b[i].z : b[i].w;
+#pragma unroll
+                for (int r = 0; r < RT; ++r) acc[r][i] = mfma_f32(a[r][e], bv, acc[r][i]);
+              }
             }
-          }
         }
       }
     }
@@ -138,7 +144,7 @@ __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int
     auto fetch = [&](bf16x8 (&dst)[TMAX], int kk) {
 #pragma unroll
       for (int i = 0; i < TMAX; ++i) {
-        const int c = wave + 4 * i;
+        const int c = wave + NW * i;
         if (c < ntiles && kk < KK) dst[i] = W[(static_cast<size_t>(c) * KK + kk) * 64 + lane];
       }
     };
@@ -153,19 +159,26 @@ __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int
 #pragma unroll
           for (int i = 0; i < TMAX; ++i) b[i] = ring[j][i];
           fetch(ring[j], kk + RING);
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(sin + row * in_stride + 32 * kk + 8 * grp);
+          bf16x8 a[RT];
+#pragma unroll
+          for (int r = 0; r < RT; ++r)
+            a[r] = *reinterpret_cast<const bf16x8*>(sin + (16 * r + row) * in_stride + 32 * kk + 8 * grp);
 #pragma unroll
           for (int i = 0; i < TMAX; ++i)
-            if (wave + 4 * i < ntiles) acc[i] = mfma_bf16(a, b[i], acc[i]);
+            if (wave + NW * i < ntiles)
+#pragma unroll
+              for (int r = 0; r < RT; ++r) acc[r][i] = mfma_bf16(a[r], b[i], acc[r][i]);
         }
       }
     }
   }
 #pragma unroll
-  for (int i = 0; i < TMAX; ++i) {
-    const int c = wave + 4 * i;
-    if (c < ntiles) epi(i, c, acc[i]);
-  }
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int i = 0; i < TMAX; ++i) {
+      const int c = wave + NW * i;
+      if (c < ntiles) epi(r, i, c, acc[r][i]);
+    }
 }
 
 }  // namespace fm
