@@ -138,9 +138,9 @@ fm_status env_set_tile(fm_env* env, int32_t envs_per_group, int32_t* h_tile);
 
 /* Tuning (no effect on results): the environment-step kernel of env_step, driven rollouts and
  * the plain path's steps.  kernel 0 picks by shape and size: one lane per environment (the whole
- * trading chain in registers) when n_stocks <= 32, (2 + n_ind) * n_stocks < 256 and
- * n_envs >= 24576, else the tile kernel; 1 always takes the tile kernel (env_set_tile's
- * environments per workgroup); 2 the lane kernel whatever n_envs.  envs_per_wave: environments per wavefront of the lane kernel, 1..64; 0 by N (one
+ * trading chain in registers) when n_stocks <= 32 and (2 + n_ind) * n_stocks < 256 -- for
+ * env_step and driven rollouts only from n_envs >= 24576 -- else the tile kernel; 1 always takes
+ * the tile kernel (env_set_tile's environments per workgroup); 2 the lane kernel whatever n_envs.  envs_per_wave: environments per wavefront of the lane kernel, 1..64; 0 by N (one
  * wavefront per SIMD).  FM_ERR_INVALID for NULL or out-of-range values; FM_ERR_UNSUPPORTED for
  * kernel 2 on a shape it does not take.  Reset and observation always use the tile kernel. */
 fm_status env_set_step_kernel(fm_env* env, int32_t kernel, int32_t envs_per_wave);

@@ -127,17 +127,47 @@ __global__ __launch_bounds__(64 * NW) void mlp_kernel(EnsDev E, const float* __r
   mlp_layer<DT, TMAX, RT, NW>(x1, sth, E.H, P + E.off_w2, ht, wave, lane, hidden_epi(x2, sth, b2));
   __syncthreads();
   float* mu_k = mu + static_cast<size_t>(k) * n * E.A;
-  mlp_layer<DT, TMAX, RT, NW>(x2, sth, E.H, P + E.off_w3, E.A_pad / 16, wave, lane,
-                          [&](int rt, int, int c, floatx4 acc) {
-                            const int col = 16 * c + col_l;
-                            if (col >= E.A) return;
-                            const float b = b3[col];
+  auto out_epi = [&](int rt, floatx4 acc, int c) {
+    const int col = 16 * c + col_l;
+    if (col >= E.A) return;
+    const float b = b3[col];
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                              const int row = row0 + 16 * rt + row_q + r;
-                              if (row < n) mu_k[static_cast<size_t>(row) * E.A + col] = fast_tanh(acc[r] + b);
-                            }
-                          });
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + 16 * rt + row_q + r;
+      if (row < n) mu_k[static_cast<size_t>(row) * E.A + col] = fast_tanh(acc[r] + b);
+    }
+  };
+  // Layer 3 has few output tiles (A_pad / 16): its k range is split over the otherwise idle
+  // wavefronts, whose partial tiles meet in LDS (over layer 1's outputs, no longer needed) and
+  // are summed in slice order.
+  const int nt3 = E.A_pad / 16;
+  const int nk3 = E.H / MT<DT>::kKGroup;
+  const int cap = R * sth * static_cast<int>(sizeof(act_t)) / (nt3 * RT * 1024);
+  const int slices = max(1, min(min(NW / nt3, nk3), cap));
+  if (slices == 1) {
+    mlp_layer<DT, TMAX, RT, NW>(x2, sth, E.H, P + E.off_w3, nt3, wave, lane,
+                                [&](int rt, int, int c, floatx4 acc) { out_epi(rt, acc, c); });
+    return;
+  }
+  floatx4* part = reinterpret_cast<floatx4*>(x1);  // [slices][nt3][RT][64]
+  const int c3 = wave % nt3, sl = wave / nt3;
+  if (sl < slices)
+    mlp_layer<DT, 1, RT, 1>(x2, sth, E.H, P + E.off_w3, nt3, c3, lane,
+                            [&](int rt, int, int, floatx4 acc) { part[((sl * nt3 + c3) * RT + rt) * 64 + lane] = acc; },
+                            sl * nk3 / slices, (sl + 1) * nk3 / slices);
+  __syncthreads();
+  if (wave < nt3) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      floatx4 acc = part[(wave * RT + rt) * 64 + lane];
+      for (int q = 1; q < slices; ++q) {
+        const floatx4 p = part[((q * nt3 + wave) * RT + rt) * 64 + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = acc[r] + p[r];
+      }
+      out_epi(rt, acc, wave);
+    }
+  }
 }
 
 // a_bar = sum_k w_k mu_k; a = clip(a_bar + sigma * eps, -1, 1).  One thread per (row, group of

@@ -50,6 +50,8 @@ struct LaneArgs {
   float* act_out;     // kMeans: [N][D] or null
   double* rew;        // [n_steps][N] or null
   int* qty;           // [n_steps][N][D] or null
+  int stage;          // LDS floats of a wavefront's staging area
+  int mu_slot;        // kMeans: staging floats per actor when the means go through LDS, else 0
 };
 
 constexpr int kMktClose = 64;   // LDS floats per buffer of close[t] | close[t+1] (2D <= 64)
@@ -57,10 +59,13 @@ constexpr int kMktInd = 256;    // LDS floats per buffer of ind[t+1] (I*D < 256)
 constexpr int kWaitVm0 = 0x0F70;    // s_waitcnt vmcnt(0)
 constexpr int kWaitLgkm0 = 0xC07F;  // s_waitcnt lgkmcnt(0)
 
-// LDS floats of a wavefront's staging area and of its whole area, for M environments of D stocks.
+constexpr int kMuStage = 4096;      // LDS floats per wavefront for the actor means' tiles
+
+// LDS floats of a tile of M environments of D stocks fetched 64 floats per instruction, and of a
+// wavefront's whole area with a staging area of `stage` floats.
 __host__ __device__ inline int stage_floats(int M, int D) { return (M * D + 63) / 64 * 64; }
-__host__ __device__ inline int wave_floats(int M, int D) {
-  return 2 * kMktClose + 2 * kMktInd + stage_floats(M, D) + 2 * (M + 1) * kRow;
+__host__ __device__ inline int wave_floats(int M, int stage) {
+  return 2 * kMktClose + 2 * kMktInd + stage + 2 * (M + 1) * kRow;
 }
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(const float* base, int n_floats) {
@@ -151,11 +156,11 @@ __global__ __launch_bounds__(kWaves * 64) void env_lane_kernel(EnvConst C, EnvSt
   const int M = min(MM, N - n0);
   const int MD = M * D;
   const float inv_d = 1.0f / static_cast<float>(D);
-  float* mcl = lds + wave * wave_floats(MM, D);  // [2][64]: close[t] | close[t+1], zero from 2D
-  float* mind = mcl + 2 * kMktClose;             // [2][256]: ind[t+1]
-  float* stage = mind + 2 * kMktInd;             // the driven tile as fetched, [M*D]
+  float* mcl = lds + wave * wave_floats(MM, A.stage);  // [2][64]: close[t] | close[t+1], zero from 2D
+  float* mind = mcl + 2 * kMktClose;                   // [2][256]: ind[t+1]
+  float* stage = mind + 2 * kMktInd;  // the driven tile, or the K actors' mean tiles, as fetched
   // Rows of kRow floats, M + 1 of each (idle lanes work on the spare last row):
-  float* tile = stage + stage_floats(MM, D);  // actions / actor means, then orders, then quantities
+  float* tile = stage + A.stage;  // actions / actor means, then orders, then quantities
   float* ent = tile + (MM + 1) * kRow;        // noise, then the state rows' cash and holdings entries
   const bool active = lane < M;
   const int n = n0 + lane;
@@ -192,6 +197,12 @@ __global__ __launch_bounds__(kWaves * 64) void env_lane_kernel(EnvConst C, EnvSt
       const __amdgpu_buffer_rsrc_t ra = range_rsrc(A.act + (static_cast<size_t>(it) * N + n0) * D, MD);
       for (int j = 0; 64 * j < MD; ++j)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, stage + 64 * j, 4, 4 * (L + 64 * j), 0, 0, 0);
+    } else if (A.mu_slot > 0) {
+      for (int k = 0; k < A.K; ++k) {
+        const __amdgpu_buffer_rsrc_t rk = range_rsrc(A.mu + (static_cast<size_t>(k) * N + n0) * D, MD);
+        for (int j = 0; 64 * j < MD; ++j)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rk, stage + k * A.mu_slot + 64 * j, 4, 4 * (L + 64 * j), 0, 0, 0);
+      }
     }
   };
   // Tile float i = m * D + d goes to row m, entry d.
@@ -211,6 +222,13 @@ __global__ __launch_bounds__(kWaves * 64) void env_lane_kernel(EnvConst C, EnvSt
     const int m = div_small(i, inv_d);
     return tile[m * kRow + (i - m * D)];
   };
+  // The fetched tile at src (float i = m * D + d) into the rows.
+  auto tile_from = [&](const float* src) {
+    for (int i = L; i < MD; i += 64) {
+      const int m = div_small(i, inv_d);
+      tile[m * kRow + (i - m * D)] = src[i];
+    }
+  };
 
   fetch(0);
   for (int it = 0; it < A.n_steps; ++it) {
@@ -223,21 +241,10 @@ __global__ __launch_bounds__(kWaves * 64) void env_lane_kernel(EnvConst C, EnvSt
     const float* px = mcl + b * kMktClose;  // close[t][d]; entries from D on are finite
     const float* pn = px + D;               // close[t+1][d]; entries from D on are finite
     const float* ind = mind + b * kMktInd;
-    __builtin_amdgcn_s_waitcnt(kWaitVm0);   // step it's inputs have landed in LDS
-    if (MODE == kDriven)
-      for (int i = L; i < MD; i += 64) {
-        const int m = div_small(i, inv_d);
-        tile[m * kRow + (i - m * D)] = stage[i];
-      }
-    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);  // the staging area is read before it is refilled
-    if (it + 1 < A.n_steps) fetch(it + 1);
-    wave_lds_sync();
-
-    // Actions (Section 5.2.1 for the ensemble's: a = clip(sum_k w_k mu_k + sigma eps)) in the
-    // lanes' tile rows.
     if (MODE == kMeans) {
-      // One Philox block per (environment, group of four stocks), spread over the lanes; the
-      // noise rows' entries from D on are zero.
+      // The noise (Section 5.2.1) while the inputs are in flight: one Philox block per
+      // (environment, group of four stocks), spread over the lanes; the noise rows' entries
+      // from D on are zero.
       const int G = (D + 3) >> 2;
       for (int i = L; i < M * 8; i += 64) {
         const int m = i >> 3;
@@ -249,19 +256,34 @@ __global__ __launch_bounds__(kWaves * 64) void env_lane_kernel(EnvConst C, EnvSt
 #pragma unroll
         for (int r = 0; r < 4; ++r) ent[m * kRow + 4 * g + r] = 4 * g + r < D ? z[r] : 0.0f;
       }
+    }
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);  // step it's inputs have landed in LDS
+    if (MODE == kDriven) tile_from(stage);
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);  // the staging area is read before it is refilled
+    if (it + 1 < A.n_steps) fetch(it + 1);
+    wave_lds_sync();
+
+    // Actions (Section 5.2.1 for the ensemble's: a = clip(sum_k w_k mu_k + sigma eps)) in the
+    // lanes' tile rows.
+    if (MODE == kMeans) {
       float acc[DP];
 #pragma unroll
       for (int d = 0; d < DP; ++d) acc[d] = 0.0f;
       for (int k = 0; k < A.K; ++k) {
         const float w = A.mix[k];
-        const __amdgpu_buffer_rsrc_t r = range_rsrc(A.mu + (static_cast<size_t>(k) * N + n0) * D, MD);
-        int md = MD;
-        __asm__ volatile("" : "+s"(md));
-        float v[DP];
+        if (A.mu_slot > 0) {
+          wave_lds_sync();  // the previous actor's rows have been read
+          tile_from(stage + k * A.mu_slot);
+        } else {
+          const __amdgpu_buffer_rsrc_t r = range_rsrc(A.mu + (static_cast<size_t>(k) * N + n0) * D, MD);
+          int md = MD;
+          __asm__ volatile("" : "+s"(md));
+          float v[DP];
 #pragma unroll
-        for (int j = 0; j < DP; ++j) v[j] = 64 * j < md ? range_load(r, L + 64 * j) : 0.0f;
-        wave_lds_sync();  // the previous actor's rows have been read
-        tile_put(v);
+          for (int j = 0; j < DP; ++j) v[j] = 64 * j < md ? range_load(r, L + 64 * j) : 0.0f;
+          wave_lds_sync();  // the previous actor's rows have been read
+          tile_put(v);
+        }
         wave_lds_sync();
 #pragma unroll
         for (int d = 0; d < DP; ++d) acc[d] = acc[d] + w * tile[LR * kRow + d];
@@ -339,7 +361,7 @@ template <int MODE, int DP>
 hipError_t launch_dp(const EnvConst& C, const EnvState& st, const LaneArgs& A, hipStream_t stream) {
   const int waves = (C.N + A.M - 1) / A.M;
   const int grid = (waves + kWaves - 1) / kWaves;
-  const size_t lds = sizeof(float) * kWaves * wave_floats(A.M, C.D);
+  const size_t lds = sizeof(float) * kWaves * wave_floats(A.M, A.stage);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(env_lane_kernel<MODE, DP>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
@@ -362,6 +384,11 @@ hipError_t launch_mode(const EnvConst& C, const EnvState& st, LaneArgs A, hipStr
     A.M = (C.N + 4 * cus - 1) / (4 * cus);
   }
   A.M = max(1, min(A.M, kMaxEnvs));
+  // The staging area: the driven tile, or all K actors' mean tiles when they fit (fetched with
+  // the market rows, under the noise); larger batches read the means into registers per actor.
+  const int slot = stage_floats(A.M, C.D);
+  A.mu_slot = (MODE == kMeans && A.K * slot <= kMuStage) ? slot : 0;
+  A.stage = MODE == kDriven ? slot : (A.mu_slot > 0 ? A.K * slot : 64);
   if (C.D <= 8) return launch_dp<MODE, 8>(C, st, A, stream);
   if (C.D <= 16) return launch_dp<MODE, 16>(C, st, A, stream);
   return launch_dp<MODE, 32>(C, st, A, stream);

@@ -82,14 +82,15 @@ __device__ __forceinline__ floatx4 mfma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
 }
 
 // One layer for RT row tiles of 16 and the wavefront's column tiles c = wave, wave + NW, ...
-// (< ntiles; NW wavefronts per workgroup).  sin: LDS tile [16 RT][in_stride] holding kin_pad valid (zero-padded) columns.
-// Calls epi(r, i, c, acc) for every (row tile r, column tile c) the wave owns.  Each B-operand
-// fragment serves all RT row tiles; the fragments of the next RING k-steps are in flight while
-// the current k-step's MFMAs run.
+// (< ntiles; NW wavefronts per workgroup).  sin: LDS tile [16 RT][in_stride] holding kin_pad
+// valid (zero-padded) columns.  Calls epi(r, i, c, acc) for every (row tile r, column tile c) the
+// wave owns.  Each B-operand fragment serves all RT row tiles; the fragments of the next RING
+// k-steps are in flight while the current k-step's MFMAs run.  [kbeg, kend) restricts the sum to
+// those k-steps (16 k for float32, 32 for bfloat16; kend < 0: to the end).
 template <int DT, int TMAX, int RT, int NW, class Epi>
 __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int in_stride,
                                           int kin_pad, const void* wp, int ntiles, int wave,
-                                          int lane, Epi epi) {
+                                          int lane, Epi epi, int kbeg = 0, int kend = -1) {
   constexpr int RING = 4;
   floatx4 acc[RT][TMAX];
 #pragma unroll
@@ -99,22 +100,22 @@ __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int
   const int row = lane & 15, grp = lane >> 4;
   if constexpr (DT == kF32) {
     const float4* W = static_cast<const float4*>(wp);
-    const int KQ = kin_pad / 16;
+    const int KQ = kin_pad / 16, K1 = kend < 0 ? KQ : min(kend, KQ);
     float4 ring[RING][TMAX];
     auto fetch = [&](float4 (&dst)[TMAX], int kq) {
 #pragma unroll
       for (int i = 0; i < TMAX; ++i) {
         const int c = wave + NW * i;
-        if (c < ntiles && kq < KQ) dst[i] = W[(static_cast<size_t>(c) * KQ + kq) * 64 + lane];
+        if (c < ntiles && kq < K1) dst[i] = W[(static_cast<size_t>(c) * KQ + kq) * 64 + lane];
       }
     };
 #pragma unroll
-    for (int j = 0; j < RING; ++j) fetch(ring[j], j);
-    for (int kq0 = 0; kq0 < KQ; kq0 += RING) {
+    for (int j = 0; j < RING; ++j) fetch(ring[j], kbeg + j);
+    for (int kq0 = kbeg; kq0 < K1; kq0 += RING) {
 #pragma unroll
       for (int j = 0; j < RING; ++j) {
         const int kq = kq0 + j;
-        if (kq < KQ) {
+        if (kq < K1) {
           float4 b[TMAX];
 #pragma unroll
           for (int i = 0; i < TMAX; ++i) b[i] = ring[j][i];
@@ -139,22 +140,22 @@ __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int
     }
   } else {
     const bf16x8* W = static_cast<const bf16x8*>(wp);
-    const int KK = kin_pad / 32;
+    const int KK = kin_pad / 32, K1 = kend < 0 ? KK : min(kend, KK);
     bf16x8 ring[RING][TMAX];
     auto fetch = [&](bf16x8 (&dst)[TMAX], int kk) {
 #pragma unroll
       for (int i = 0; i < TMAX; ++i) {
         const int c = wave + NW * i;
-        if (c < ntiles && kk < KK) dst[i] = W[(static_cast<size_t>(c) * KK + kk) * 64 + lane];
+        if (c < ntiles && kk < K1) dst[i] = W[(static_cast<size_t>(c) * KK + kk) * 64 + lane];
       }
     };
 #pragma unroll
-    for (int j = 0; j < RING; ++j) fetch(ring[j], j);
-    for (int kk0 = 0; kk0 < KK; kk0 += RING) {
+    for (int j = 0; j < RING; ++j) fetch(ring[j], kbeg + j);
+    for (int kk0 = kbeg; kk0 < K1; kk0 += RING) {
 #pragma unroll
       for (int j = 0; j < RING; ++j) {
         const int kk = kk0 + j;
-        if (kk < KK) {
+        if (kk < K1) {
           bf16x8 b[TMAX];
 #pragma unroll
           for (int i = 0; i < TMAX; ++i) b[i] = ring[j][i];

@@ -118,7 +118,9 @@ def test_driven_large_batch_by_shape_sampled():
 
 def test_lane_kernel_plain_steps_match_tile_kernel():
     """The plain path's ensemble steps (mean of the actors, noise, clip, trade) through the lane
-    kernel and through the tile kernel: the same arithmetic, so every output is bit-identical."""
+    kernel and through the tile kernel: the same arithmetic, so every output is bit-identical.
+    The lane kernel stages the actors' means through LDS for small wavefront tiles (1 and 5
+    environments) and reads them into registers for a full 64-environment tile."""
     import torch
     from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
     from _helpers import actors_case
@@ -128,7 +130,7 @@ def test_lane_kernel_plain_steps_match_tile_kernel():
     _, _, packed = actors_case(3, 211, 64, D)
     ens = Ensemble(packed, 3, 211, 64, D, dtype="f32", max_batch=N, device=dev)
     out = []
-    for kernel, M in ((1, 0), (2, 0), (2, 5)):
+    for kernel, M in ((1, 0), (2, 0), (2, 5), (2, 64)):
         env = VecEnv(cfg, m.close, m.ind, device=dev)
         env.set_step_kernel(kernel, M)
         env.reset(return_obs=False)
