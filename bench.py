@@ -212,8 +212,14 @@ def bench_batched(dev, n_groups=64, reps=3):
         ts.append(a.elapsed_time(b))
     ms = float(np.median(ts[1:]))
     batch.close()
+    flops = sum(g.env.n_envs * g.env.n_days * mlp_flops_per_env_step(g.actors.in_dim, g.actors.hidden,
+                                                                     g.env.n_stocks, 3) for g in gs)
+    tf = flops / (ms / 1e3) / 1e12
     return {"workload": f"{n_groups} uneven groups, {steps} env-steps", "value": steps / (ms / 1e3),
             "unit": "env-steps/s", "ms": ms, "tile_rows": rows, "blocks": blocks, "graph": True,
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / PEAK_BF16_TFLOPS, "kernel": "fused_batched_kernel", "traffic": None,
+                         "flop": flops, "flop_per_env_step": "2K(SH + H^2 + HA) of each group's shape"},
             "schedule": "generic (runtime shapes)"}
 
 

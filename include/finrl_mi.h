@@ -247,14 +247,15 @@ fm_status fm_batch_create(const fm_batch_group* h_groups, int32_t n_groups, void
                           size_t workspace_bytes, hipStream_t stream, fm_batch** out);
 
 /* Autotuner: times the first chunk under each candidate tile shape (16 or 32 environments per
- * work item) and persistent grid size, restores every group's state after each trial, and keeps
+ * work item; with 32, groups whose 32-row tile exceeds the LDS budget keep 16, in a launch of
+ * their own) and persistent grid size, restores every group's state after each trial, and keeps
  * the fastest.  *h_rows and *h_blocks (may be NULL) get the choice.  Invalidates a captured
  * graph.  Trajectory buffers are overwritten by the trials. */
 fm_status fm_batch_tune(fm_batch* batch, int32_t* h_rows, int32_t* h_blocks);
 
-/* Sets the tile shape by hand instead of the autotuner: rows (16 or 32 environments per work item)
- * and the persistent grid (blocks, 1..65536 workgroups).  FM_ERR_UNSUPPORTED if a group's tile of
- * that many rows exceeds the LDS budget.  Invalidates a captured graph. */
+/* Sets the tile shape by hand instead of the autotuner: rows (16 or 32 environments per work item;
+ * with 32, groups whose 32-row tile exceeds the LDS budget keep 16) and the persistent grid
+ * (blocks, 1..65536 workgroups per launch).  Invalidates a captured graph. */
 fm_status fm_batch_set_tiling(fm_batch* batch, int32_t rows, int32_t blocks);
 
 /* Runs every group's n_steps on the batch's stream and advances each environment's day.

@@ -132,7 +132,7 @@ struct EnsLayout {
 // The split first layer applies to bfloat16 ensembles over a trading state
 // [cash, closes(A), holdings(A), indicators(I*A)].
 bool splits_first_layer(int S, int A, int dtype) {
-  return dtype == FM_BF16 && A >= 1 && (S - 1) % A == 0 && (S - 1) / A >= 2 && 1 + A <= 64;
+  return dtype == FM_BF16 && A >= 1 && (S - 1) % A == 0 && (S - 1) / A >= 2 && 1 + A <= 128;
 }
 
 EnsLayout ens_layout(int K, int S, int H, int A, int dtype, int max_batch) {
@@ -201,7 +201,10 @@ struct fm_batch {
   int* d_items = nullptr;           // [n_chunks][items_cap] int2
   int* d_counter = nullptr;
   unsigned char* d_save = nullptr;  // state copies for the autotuner
-  std::vector<int> n_items;         // per chunk, for the current rows
+  std::vector<float*> d_mt;         // per group: its chunk's market table (split first layer), or null
+  std::vector<int> n_items;         // per chunk, for the current rows: all work items
+  std::vector<int> n_wide;          // per chunk: the first n_wide items run 32-row tiles
+  size_t lds_wide = 0;              // dynamic LDS of the 32-row and 16-row launches
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture = nullptr;  // private stream the chunk launches are captured on
@@ -212,9 +215,15 @@ namespace {
 constexpr int kBatchChunk = 64;
 
 struct BatchLayout {
-  size_t desc, items, counter, save, total, items_cap;
+  size_t desc, items, counter, save, mt, total, items_cap;
   int n_chunks;
 };
+
+// Floats of a group's market-table slot: the chunk's days x actors x hidden units.
+size_t batch_table_floats(const fm_batch_group& g) {
+  const fm::EnsDev& E = g.ens->E;
+  return E.split_a > 0 ? static_cast<size_t>(kBatchChunk) * E.K * E.H : 0;
+}
 
 std::string validate_batch(const fm_batch_group* g, int n, int device) {
   if (!g) return "groups is NULL";
@@ -255,30 +264,43 @@ BatchLayout batch_layout(const fm_batch_group* g, int n) {
   off = align_up(off + 256);
   L.save = off;
   off = align_up(off + save);
+  L.mt = off;
+  for (int i = 0; i < n; ++i) off = align_up(off + sizeof(float) * batch_table_floats(g[i]));
   L.total = off;
   return L;
 }
 
-// Work lists of every chunk for the given tile rows: (group, tile), most expensive first.
+// A group's tile rows for the batch's rows setting: 32 when its 32-row tile fits the LDS budget.
+int group_rows(const fm_batch_group& G, int rows) {
+  return rows == 32 && fm::batched_lds_bytes(32, G.env->C, G.ens->E) <= fm::batched_max_lds() ? 32 : 16;
+}
+
+// Work lists of every chunk for the given tile rows: (group, tile), the 32-row items first, each
+// part most expensive first.
 fm_status batch_items(fm_batch* b, int rows) {
   std::vector<int> host;
   b->n_items.assign(b->n_chunks, 0);
+  b->n_wide.assign(b->n_chunks, 0);
   for (int c = 0; c < b->n_chunks; ++c) {
-    struct It { double cost; int g, tile; };
+    struct It { double cost; int g, tile, wide; };
     std::vector<It> list;
     for (int g = 0; g < b->n_groups; ++g) {
       const fm_batch_group& G = b->groups[g];
       const int n = std::min(kBatchChunk, G.n_steps - c * kBatchChunk);
       if (n <= 0) continue;
       const fm::EnsDev& E = G.ens->E;
+      const int kin1 = E.split_a > 0 ? E.ke_pad : E.S_pad;
       const double per_step = static_cast<double>(E.K) *
-                              (static_cast<double>(E.S_pad) * E.H + static_cast<double>(E.H) * E.H +
+                              (static_cast<double>(kin1) * E.H + static_cast<double>(E.H) * E.H +
                                static_cast<double>(E.H) * E.A_pad) + 64.0 * G.env->C.D;
-      const int tiles = (G.env->C.N + rows - 1) / rows;
-      for (int t = 0; t < tiles; ++t) list.push_back({per_step * n, g, t});
+      const int gr = group_rows(G, rows);
+      const int tiles = (G.env->C.N + gr - 1) / gr;
+      for (int t = 0; t < tiles; ++t) list.push_back({per_step * n * gr, g, t, gr == 32 ? 1 : 0});
     }
-    std::stable_sort(list.begin(), list.end(), [](const It& x, const It& y) { return x.cost > y.cost; });
+    std::stable_sort(list.begin(), list.end(),
+                     [](const It& x, const It& y) { return x.wide != y.wide ? x.wide > y.wide : x.cost > y.cost; });
     b->n_items[c] = static_cast<int>(list.size());
+    for (const It& it : list) b->n_wide[c] += it.wide;
     host.resize(2 * b->items_cap);
     for (size_t i = 0; i < list.size(); ++i) {
       host[2 * i] = list[i].g;
@@ -291,10 +313,15 @@ fm_status batch_items(fm_batch* b, int rows) {
     if (e != hipSuccess) return device_status(e, "fm_batch (work lists)");
   }
   b->rows = rows;
-  size_t lds = 0;
-  for (const fm_batch_group& G : b->groups) lds = std::max(lds, fm::batched_lds_bytes(rows, G.env->C, G.ens->E));
+  size_t lds = 0, lds_wide = 0;
+  for (const fm_batch_group& G : b->groups) {
+    const int gr = group_rows(G, rows);
+    size_t& l = gr == 32 ? lds_wide : lds;
+    l = std::max(l, fm::batched_lds_bytes(gr, G.env->C, G.ens->E));
+  }
   b->lds = lds;
-  return device_status(fm::prepare_batched(lds), "fm_batch (LDS limit)");
+  b->lds_wide = lds_wide;
+  return device_status(fm::prepare_batched(std::max(lds, lds_wide)), "fm_batch (LDS limit)");
 }
 
 void batch_drop_graph(fm_batch* b) {
@@ -307,9 +334,23 @@ void batch_drop_graph(fm_batch* b) {
 hipError_t batch_enqueue(fm_batch* b, int n_chunks, hipStream_t stream) {
   for (int c = 0; c < n_chunks; ++c) {
     if (b->n_items[c] == 0) continue;
-    const hipError_t e = fm::launch_batched(b->rows, b->blocks, b->lds, b->d_desc + b->desc_bytes * b->n_groups * c,
-                                            b->d_items + 2 * b->items_cap * c, b->n_items[c], b->d_counter,
-                                            stream);
+    // The chunk's market tables of the groups that split their first layer.
+    for (int g = 0; g < b->n_groups; ++g) {
+      const fm_batch_group& G = b->groups[g];
+      const int n = std::min(kBatchChunk, G.n_steps - c * kBatchChunk);
+      if (n <= 0 || !b->d_mt[g]) continue;
+      const hipError_t e = fm::launch_market_table(G.env->C, G.ens->E, b->start_day[g] + c * kBatchChunk, n,
+                                                   b->d_mt[g], stream);
+      if (e != hipSuccess) return e;
+    }
+    // The 32-row items, then the 16-row ones: one persistent launch each, with its own counter.
+    const unsigned char* desc = b->d_desc + b->desc_bytes * b->n_groups * c;
+    const int* items = b->d_items + 2 * b->items_cap * c;
+    const int nw = b->n_wide[c], nn = b->n_items[c] - nw;
+    hipError_t e = hipSuccess;
+    if (nw > 0) e = fm::launch_batched(32, b->blocks, b->lds_wide, desc, items, nw, b->d_counter, stream);
+    if (e == hipSuccess && nn > 0)
+      e = fm::launch_batched(16, b->blocks, b->lds, desc, items + 2 * nw, nn, b->d_counter + 1, stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -396,6 +437,14 @@ fm_status fm_batch_create(const fm_batch_group* h_groups, int32_t n_groups, void
   b->d_items = reinterpret_cast<int*>(base + L.items);
   b->d_counter = reinterpret_cast<int*>(base + L.counter);
   b->d_save = base + L.save;
+  {
+    size_t off = L.mt;
+    for (int g = 0; g < n_groups; ++g) {
+      const size_t f = batch_table_floats(h_groups[g]);
+      b->d_mt.push_back(f > 0 ? reinterpret_cast<float*>(base + off) : nullptr);
+      off = align_up(off + sizeof(float) * f);
+    }
+  }
   int cus = 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
   b->blocks = cus;
@@ -412,7 +461,7 @@ fm_status fm_batch_create(const fm_batch_group* h_groups, int32_t n_groups, void
                              G.env_offset, G.d_obs_traj && n ? G.d_obs_traj + r0 * N * S : nullptr,
                              G.d_act_traj && n ? G.d_act_traj + r0 * N * D : nullptr,
                              G.d_rew_traj && n ? G.d_rew_traj + r0 * N : nullptr,
-                             G.d_qty_traj && n ? G.d_qty_traj + r0 * N * D : nullptr,
+                             G.d_qty_traj && n ? G.d_qty_traj + r0 * N * D : nullptr, b->d_mt[g],
                              host.data() + b->desc_bytes * (static_cast<size_t>(c) * n_groups + g));
     }
   for (int g = 0; g < n_groups; ++g) b->start_day.push_back(h_groups[g].env->day);
@@ -445,10 +494,6 @@ fm_status fm_batch_tune(fm_batch* b, int32_t* h_rows, int32_t* h_blocks) {
   float best_ms = -1.0f;
   fm_status status = FM_OK;
   for (int rows : {16, 32}) {
-    bool fits = true;
-    for (const fm_batch_group& G : b->groups)
-      fits = fits && fm::batched_lds_bytes(rows, G.env->C, G.ens->E) <= fm::batched_max_lds();
-    if (!fits) continue;
     status = batch_items(b, rows);
     if (status != FM_OK) break;
     for (int blocks : {cus / 2, cus, 2 * cus}) {
@@ -491,10 +536,6 @@ fm_status fm_batch_set_tiling(fm_batch* b, int32_t rows, int32_t blocks) {
   if (!b) return fail(FM_ERR_INVALID, "batch is NULL");
   if (rows != 16 && rows != 32) return fail(FM_ERR_INVALID, "fm_batch_set_tiling: rows must be 16 or 32");
   if (blocks < 1 || blocks > 65536) return fail(FM_ERR_INVALID, "fm_batch_set_tiling: blocks must be in 1..65536");
-  for (const fm_batch_group& G : b->groups)
-    if (fm::batched_lds_bytes(rows, G.env->C, G.ens->E) > fm::batched_max_lds())
-      return fail(FM_ERR_UNSUPPORTED, "fm_batch_set_tiling: a group's tile of " + std::to_string(rows) +
-                                          " environments exceeds the LDS budget");
   DeviceGuard guard(b->device);
   batch_drop_graph(b);
   b->blocks = blocks;

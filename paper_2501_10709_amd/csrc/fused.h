@@ -68,14 +68,21 @@ hipError_t launch_fused_rollout(const EnvConst& C, const EnvState& st, const Ens
                                 float* eps_chunk, float* mt_chunk, hipStream_t stream, std::string* why,
                                 FusedTuning tune = FusedTuning());
 
-// Batched persistent rollout of uneven groups (generic schedule, hidden size 256, K <= 8).
+// Batched persistent rollout of uneven groups (generic schedule, hidden size 256, K <= 8; the
+// first layer split into per-environment rows and a per-day market table when the ensemble
+// packs it so).
 // rows: environments per work item (16 or 32).  A group descriptor is an opaque block of
 // batched_group_desc_bytes() bytes, filled on the host and copied to the device.
 size_t batched_lds_bytes(int rows, const EnvConst& C, const EnsDev& E);
 size_t batched_group_desc_bytes();
+// mt: the group's market-table slot ([kFusedChunk][K][H] floats, refilled before each chunk by
+// launch_market_table) when the ensemble splits its first layer, else ignored.
 void batched_group_desc(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0, int n_steps, float sigma,
                         uint64_t key, int64_t env_offset, float* obs_traj, float* act_traj, double* rew_traj,
-                        int* qty_traj, void* out);
+                        int* qty_traj, const float* mt, void* out);
+// The market table mt[c][k][j] of days t .. t+n-1 (actor k's layer-1 share of day t+c's market
+// entries, bias included), for ensembles that split their first layer.
+hipError_t launch_market_table(const EnvConst& C, const EnsDev& E, int t, int n, float* mt, hipStream_t stream);
 // The batched kernels' dynamic LDS limit: raised to lds (<= batched_max_lds()) outside any
 // stream capture.
 size_t batched_max_lds();

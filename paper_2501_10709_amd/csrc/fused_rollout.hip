@@ -169,20 +169,35 @@ struct EnvPhase {
     return r;
   }
 
-  // State rows: bfloat16 into x0 for the next first layer, float32 into the trajectory.
-  __device__ void assemble(float* traj) {
+  // State rows: bfloat16 into x0 for the next first layer, float32 into the trajectory.  With
+  // the split first layer (split_pad > 0) x0 holds only the per-environment entries [cash,
+  // holdings] in split_pad columns; the market entries reach layer 1 through the day's table.
+  // The (row, column) pairs are spread over all threads: consecutive threads write consecutive
+  // entries of the tile's contiguous trajectory rows.
+  __device__ void assemble(float* traj, int split_pad = 0) {
     const int D = C.D, DS = D + 1, S = C.S;
-    for (int m = 0; m < M; ++m) {
-      for (int f = tid; f < S_pad; f += NT) {
-        float v = 0.0f;
-        if (f < S) {
-          if (f == 0) v = L.env[m * DS];
-          else if (f <= D) v = L.mkt[f - 1];
-          else if (f <= 2 * D) v = L.env[m * DS + f - D];
-          else v = L.mkt[f - 1 - D];
-          if (traj) traj[static_cast<size_t>(m) * S + f] = v;
-        }
-        L.x0[m * st0 + f] = static_cast<__bf16>(v);
+    const int W = split_pad > 0 ? S : S_pad;  // columns visited per row
+    const float inv_w = 1.0f / static_cast<float>(W);
+#pragma unroll 2
+    for (int i = tid; i < M * W; i += NT) {
+      const int m = div_small(i, inv_w);
+      const int f = i - m * W;
+      float v = 0.0f;
+      if (f < S) {
+        if (f == 0) v = L.env[m * DS];
+        else if (f <= D) v = L.mkt[f - 1];
+        else if (f <= 2 * D) v = L.env[m * DS + f - D];
+        else v = L.mkt[f - 1 - D];
+        if (traj) traj[static_cast<size_t>(m) * S + f] = v;
+      }
+      if (split_pad == 0) L.x0[m * st0 + f] = static_cast<__bf16>(v);
+    }
+    if (split_pad > 0) {
+      const float inv_p = 1.0f / static_cast<float>(split_pad);
+      for (int i = tid; i < M * split_pad; i += NT) {
+        const int m = div_small(i, inv_p);
+        const int f = i - m * split_pad;
+        L.x0[m * st0 + f] = static_cast<__bf16>(f <= D ? L.env[m * DS + f] : 0.0f);
       }
     }
   }
@@ -213,41 +228,15 @@ struct EnvPhase {
 };
 
 // ------------------------------------------------------------------------------------------
-// Generic MLP schedule (runtime shapes): wavefront w owns output tiles w, w+4, ...
+// Generic MLP schedule (runtime shapes): wavefront w owns output tiles w, w+4, ...; the weight
+// fragments of the next four k-steps are in flight in a register ring while the current ones are
+// multiplied (the ensemble MLP's layer loop).
 // ------------------------------------------------------------------------------------------
 template <int ROWT, int TMAX, class Epi>
 __device__ __forceinline__ void layer_bf16(const __bf16* sin, int ist, int kin_pad, const bf16x8* W,
                                            int ntiles, int wave, int lane, Epi epi) {
-  floatx4 acc[ROWT][TMAX];
-#pragma unroll
-  for (int rt = 0; rt < ROWT; ++rt)
-#pragma unroll
-    for (int i = 0; i < TMAX; ++i) acc[rt][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-  const int row = lane & 15, grp = lane >> 4;
-  const int KK = kin_pad / 32;
-  for (int kk = 0; kk < KK; ++kk) {
-    bf16x8 a[ROWT];
-#pragma unroll
-    for (int rt = 0; rt < ROWT; ++rt)
-      a[rt] = *reinterpret_cast<const bf16x8*>(sin + (rt * 16 + row) * ist + 32 * kk + 8 * grp);
-#pragma unroll
-    for (int i = 0; i < TMAX; ++i) {
-      const int c = wave + 4 * i;
-      if (c < ntiles) {
-        const bf16x8 b = W[(static_cast<size_t>(c) * KK + kk) * 64 + lane];
-#pragma unroll
-        for (int rt = 0; rt < ROWT; ++rt) acc[rt][i] = mfma_bf16(a[rt], b, acc[rt][i]);
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < TMAX; ++i) {
-    const int c = wave + 4 * i;
-    if (c < ntiles) {
-#pragma unroll
-      for (int rt = 0; rt < ROWT; ++rt) epi(rt, c, acc[rt][i]);
-    }
-  }
+  auto e = [&](int rt, int, int c, floatx4 acc) { epi(rt, c, acc); };
+  mlp_layer<kBF16, TMAX, ROWT, 4, decltype(e), 4>(sin, ist, kin_pad, W, ntiles, wave, lane, e);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -792,7 +781,10 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
   const int D = C.D, N = C.N, DS = D + 1;
   const int n0 = tile * MR;
   const int M = min(MR, N - n0);
-  const int st0 = E.S_pad + 8, sth = E.H + 8;
+  // Split first layer when the day's market tables come with the launch (F.mt, [n_steps][K][H],
+  // bias included): layer 1 runs on the ke_pad per-environment entries only.
+  const int split_pad = F.mt != nullptr ? E.ke_pad : 0;
+  const int st0 = (split_pad > 0 ? split_pad : E.S_pad) + 8, sth = E.H + 8;
 
   FusedLds L;
   L.carve(smem, MR, st0, sth, D);
@@ -809,10 +801,15 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
   P.stage_market(F.t0, false);
   P.env_entries(owner, cash);
   __syncthreads();
-  P.assemble(nullptr);
+  P.assemble(nullptr, split_pad);
 
   const int row_q = 4 * (lane >> 4), col_l = lane & 15;
   const int ht = E.H / 16, at = E.A_pad / 16;
+  // Layer 3's k-range slices: the wavefronts left over by its output tiles (partial tiles of
+  // sl3 * at * ROWT * 1024 bytes in the layer-1 output area).
+  const int kk3 = E.H / 32;
+  int sl3 = at < 4 ? min(4 / at, kk3) : 1;
+  while (sl3 > 1 && sl3 * at * ROWT * 1024 > MR * sth * 2) --sl3;
 
   for (int it = 0; it < F.n_steps; ++it) {
     const int t = F.t0 + it;
@@ -826,10 +823,16 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
       const float* b2 = reinterpret_cast<const float*>(PA + E.off_b2);
       const float* b3 = reinterpret_cast<const float*>(PA + E.off_b3);
       const float wk = E.mix[k];
-      layer_bf16<ROWT, TMAX>(L.x0, st0, E.S_pad, reinterpret_cast<const bf16x8*>(PA + E.off_w1), ht, wave, lane,
+      // Layer 1's bias, or with the split layer the day's market share (bias included).
+      const float* b1t = split_pad > 0 ? F.mt + (static_cast<size_t>(it) * E.K + k) * E.H : b1;
+      const bf16x8* W1 = split_pad > 0
+                             ? reinterpret_cast<const bf16x8*>(E.base + E.off_w1e +
+                                                               static_cast<size_t>(k) * E.H * split_pad * 2)
+                             : reinterpret_cast<const bf16x8*>(PA + E.off_w1);
+      layer_bf16<ROWT, TMAX>(L.x0, st0, split_pad > 0 ? split_pad : E.S_pad, W1, ht, wave, lane,
                              [&](int rt, int c, floatx4 acc) {
                                const int col = 16 * c + col_l;
-                               const float b = b1[col];
+                               const float b = b1t[col];
 #pragma unroll
                                for (int q = 0; q < 4; ++q)
                                  L.x1[(rt * 16 + row_q + q) * sth + col] = static_cast<__bf16>(fast_tanh(acc[q] + b));
@@ -844,18 +847,43 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
                                  L.x2[(rt * 16 + row_q + q) * sth + col] = static_cast<__bf16>(fast_tanh(acc[q] + b));
                              });
       __syncthreads();
-      layer_bf16<ROWT, TMAX>(L.x2, sth, E.H, reinterpret_cast<const bf16x8*>(PA + E.off_w3), at, wave, lane,
-                             [&](int rt, int c, floatx4 acc) {
-                               const int col = 16 * c + col_l;
-                               if (col >= E.A) return;
-                               const float b = b3[col];
+      auto out3 = [&](int rt, int c, floatx4 acc) {
+        const int col = 16 * c + col_l;
+        if (col >= E.A) return;
+        const float b = b3[col];
 #pragma unroll
-                               for (int q = 0; q < 4; ++q) {
-                                 float* dst = &L.abar[(rt * 16 + row_q + q) * DS + col];
-                                 const float v = wk * fast_tanh(acc[q] + b);
-                                 *dst = (k == 0) ? v : (*dst + v);
-                               }
-                             });
+        for (int q = 0; q < 4; ++q) {
+          float* dst = &L.abar[(rt * 16 + row_q + q) * DS + col];
+          const float v = wk * fast_tanh(acc[q] + b);
+          *dst = (k == 0) ? v : (*dst + v);
+        }
+      };
+      const bf16x8* W3 = reinterpret_cast<const bf16x8*>(PA + E.off_w3);
+      if (sl3 == 1) {
+        layer_bf16<ROWT, TMAX>(L.x2, sth, E.H, W3, at, wave, lane, out3);
+      } else {
+        // Fewer output tiles than wavefronts: the k range is split over them, the partial tiles
+        // meet in LDS over layer 1's outputs (read by now) and are summed in slice order.
+        floatx4* part = reinterpret_cast<floatx4*>(L.x1);  // [sl3][at][ROWT][64]
+        const int c3 = wave % at, q3 = wave / at;
+        auto e3 = [&](int rt, int, int, floatx4 acc) { part[((q3 * at + c3) * ROWT + rt) * 64 + lane] = acc; };
+        if (q3 < sl3)
+          mlp_layer<kBF16, 1, ROWT, 1, decltype(e3), 4>(L.x2, sth, E.H, W3, at, c3, lane, e3, q3 * kk3 / sl3,
+                                                        (q3 + 1) * kk3 / sl3);
+        __syncthreads();
+        if (wave < at) {
+#pragma unroll
+          for (int rt = 0; rt < ROWT; ++rt) {
+            floatx4 acc = part[(wave * ROWT + rt) * 64 + lane];
+            for (int q = 1; q < sl3; ++q) {
+              const floatx4 p = part[((q * at + wave) * ROWT + rt) * 64 + lane];
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc[r] = acc[r] + p[r];
+            }
+            out3(rt, wave, acc);
+          }
+        }
+      }
       __syncthreads();
     }
 
@@ -865,7 +893,7 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
     if (owner && F.rew_traj) F.rew_traj[static_cast<size_t>(it) * N + n] = rwd;
     __syncthreads();
     P.quantities(row_base);
-    P.assemble(F.obs_traj ? F.obs_traj + row_base * C.S : nullptr);
+    P.assemble(F.obs_traj ? F.obs_traj + row_base * C.S : nullptr, split_pad);
   }
 
   P.store_state(owner, st, cash, asset, cumrew);
@@ -1014,7 +1042,13 @@ bool fused_streamed_shape(const EnvConst& C, const EnsDev& E) {
 }
 
 size_t batched_lds_bytes(int rows, const EnvConst& C, const EnsDev& E) {
-  return FusedLds::bytes(rows, E.S_pad + 8, E.H + 8, C.D, C.I);
+  return FusedLds::bytes(rows, (E.split_a > 0 ? E.ke_pad : E.S_pad) + 8, E.H + 8, C.D, C.I);
+}
+
+hipError_t launch_market_table(const EnvConst& C, const EnsDev& E, int t, int n, float* mt, hipStream_t stream) {
+  const int Fm = (1 + C.I) * C.D;
+  hipLaunchKernelGGL(market_table_kernel, dim3(n, E.K), dim3(kStreamH), sizeof(float) * Fm, stream, C, E, t, mt);
+  return hipGetLastError();
 }
 
 size_t batched_max_lds() { return kBatchedMaxLds; }
@@ -1023,9 +1057,9 @@ size_t batched_group_desc_bytes() { return sizeof(GroupDesc); }
 
 void batched_group_desc(const EnvConst& C, const EnvState& st, const EnsDev& E, int t0, int n_steps, float sigma,
                         uint64_t key, int64_t env_offset, float* obs_traj, float* act_traj, double* rew_traj,
-                        int* qty_traj, void* out) {
+                        int* qty_traj, const float* mt, void* out) {
   GroupDesc G{C, st, E, FusedArgs{t0, n_steps, sigma, key, env_offset, obs_traj, act_traj, rew_traj, qty_traj,
-                                  nullptr, nullptr}};
+                                  nullptr, E.split_a > 0 ? mt : nullptr}};
   std::memcpy(out, &G, sizeof(GroupDesc));
 }
 

@@ -87,11 +87,10 @@ __device__ __forceinline__ floatx4 mfma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
 // wave owns.  Each B-operand fragment serves all RT row tiles; the fragments of the next RING
 // k-steps are in flight while the current k-step's MFMAs run.  [kbeg, kend) restricts the sum to
 // those k-steps (16 k for float32, 32 for bfloat16; kend < 0: to the end).
-template <int DT, int TMAX, int RT, int NW, class Epi>
+template <int DT, int TMAX, int RT, int NW, class Epi, int RING = 4>
 __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int in_stride,
                                           int kin_pad, const void* wp, int ntiles, int wave,
                                           int lane, Epi epi, int kbeg = 0, int kend = -1) {
-  constexpr int RING = 4;
   floatx4 acc[RT][TMAX];
 #pragma unroll
   for (int r = 0; r < RT; ++r)
