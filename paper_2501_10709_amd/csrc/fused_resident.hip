@@ -231,7 +231,7 @@ __device__ __forceinline__ void buy_all(double& cash, int (&kown)[2], int lane, 
 // Trajectory stores go through buffer resources that cover the tile's rows of one step: a lane
 // with nothing to store passes an offset beyond the range, which the hardware drops, so the
 // stores need no branches; a trajectory that is not requested gets an empty range.
-constexpr int kNoStore = 0x7ffffff0;
+constexpr int kNoStore = 1 << 30;  // beyond every range; adding a row offset stays below 2^31
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const void* base, size_t elem_offset, size_t elem_bytes,
                                                             int n_elems) {
   if (!base) return __builtin_amdgcn_make_buffer_rsrc(nullptr, 0, 0, 0x00020000);
