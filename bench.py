@@ -58,7 +58,7 @@ CHUNK = 64  # steps per fused-kernel launch (the library's chunk)
 PROFILED_SOURCES = ("api.hip", "crypto_serve.hip", "device_common.h", "ensemble_kernels.hip", "env_kernels.hip",
                     "env_lane.hip",
                     "fused_resident.hip",
-                    "fused.h", "fused_rollout.hip", "launch.h", "mlp_device.h", "status.h")
+                    "fused.h", "fused_rollout.hip", "launch.h", "mlp_device.h", "row_chain.h", "status.h")
 
 
 def source_hash():
@@ -581,8 +581,8 @@ def main():
                      "steps_per_launch": steps_per_launch, "flop_per_env_step": flop_env_step},
         "env_roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": achieved_gbs / PEAK_HBM_GBS,
-                         "traffic": traffic_for("env_tile_kernel<1>@2048", N * T),
-                         "kernel": "env_tile_kernel<1> (driven; the size-based choice at this N)",
+                         "traffic": traffic_for("env_row_kernel<0>@2048", N * T),
+                         "kernel": "env_row_kernel<0> (driven; the size-based choice at this N)",
                          "kernel_ms": d_s * 1e3, "us_per_step": d_s * 1e6 / T,
                          "bytes_per_env_step": env_bytes_per_env_step(D, S), "env_steps_per_s": env_steps / d_s,
                          "large": {"workload": wl.name, "achieved": large_gbs, "frac": large_gbs / PEAK_HBM_GBS,

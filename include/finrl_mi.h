@@ -137,12 +137,19 @@ int32_t env_day(const fm_env* env);
 fm_status env_set_tile(fm_env* env, int32_t envs_per_group, int32_t* h_tile);
 
 /* Tuning (no effect on results): the environment-step kernel of env_step, driven rollouts and
- * the plain path's steps.  kernel 0 picks by shape and size: one lane per environment (the whole
- * trading chain in registers) when n_stocks <= 32 and (2 + n_ind) * n_stocks < 256 -- for
- * env_step and driven rollouts only from n_envs >= 24576 -- else the tile kernel; 1 always takes
- * the tile kernel (env_set_tile's environments per workgroup); 2 the lane kernel whatever n_envs.  envs_per_wave: environments per wavefront of the lane kernel, 1..64; 0 by N (one
- * wavefront per SIMD).  FM_ERR_INVALID for NULL or out-of-range values; FM_ERR_UNSUPPORTED for
- * kernel 2 on a shape it does not take.  Reset and observation always use the tile kernel. */
+ * the plain path's steps.  The row kernel (a 16-lane row per environment, one or two per wavefront) and
+ * the lane kernel (one lane per environment, the whole trading chain in registers) take shapes
+ * with n_stocks <= 32 and (2 + n_ind) * n_stocks < 256; the tile kernel takes every shape.
+ * kernel 0 picks by shape and size: the row kernel up to n_envs = 12288 (for the plain path's
+ * steps with at most 8 actors); above that the lane kernel for the plain path's steps, and for
+ * env_step and driven rollouts the tile kernel up to 24575 environments and the lane kernel from
+ * 24576; shapes outside the row and lane kernels' limits always take the tile kernel.  1 always
+ * takes the tile kernel (env_set_tile's environments per workgroup); 2 the lane kernel and 3 the
+ * row kernel whatever n_envs (3: the plain path's steps with more than 8 actors take the lane
+ * kernel).  envs_per_wave: environments per wavefront of the lane kernel, 1..64 (0: by N, one
+ * wavefront per SIMD), and of the row kernel, 1 or 2 (0 or above 2: 2; above 2 is refused with
+ * kernel 3).  FM_ERR_INVALID for NULL or out-of-range values; FM_ERR_UNSUPPORTED for
+ * kernel 2 or 3 on a shape it does not take.  Reset and observation always use the tile kernel. */
 fm_status env_set_step_kernel(fm_env* env, int32_t kernel, int32_t envs_per_wave);
 
 /* Tuning of the fused rollout (results stay within the bfloat16 tolerance; the environment

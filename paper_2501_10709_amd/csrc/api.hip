@@ -111,7 +111,7 @@ struct fm_env {
   int device;
   int day;
   int tile;
-  int step_kernel;    // 0 by shape, 1 the tile kernel, 2 the lane kernel
+  int step_kernel;    // 0 by shape and size, 1 the tile kernel, 2 the lane kernel, 3 the row kernel
   int lane_envs;      // environments per wavefront of the lane kernel (0: by N)
   fm::FusedTuning fused;  // fused-rollout tuning (schedule, row tiles, environments per workgroup)
 };
@@ -376,25 +376,42 @@ hipError_t batch_state_copy(fm_batch* b, bool save) {
   return hipSuccess;
 }
 
-// The lane kernel (one lane per environment) by default from this many environments: below it
-// the batch holds too few environments per SIMD to hide the lane chains' instruction stream, and
-// the tile kernel's shorter per-step latency wins (measured on MI355X, D = 30, driven).
+// Default environment-step kernels by batch size (measured on MI355X, D = 30): up to
+// kRowMaxEnvs environments the row kernel (a 16-lane row per environment) has the shortest
+// per-step latency, since its cash chain is split over the row's lanes; from kLaneMinEnvs the lane
+// kernel (one lane per environment) holds enough environments per SIMD to hide its chains'
+// instruction stream and streams the state rows at the HBM rate; between them the tile kernel.
+constexpr int kRowMaxEnvs = 12288;
 constexpr int kLaneMinEnvs = 24576;
 
+bool row_kernel(const fm_env* env) {
+  if (!fm::env_lane_shape(env->C)) return false;
+  return env->step_kernel == 3 || (env->step_kernel == 0 && env->C.N <= kRowMaxEnvs);
+}
+
 bool lane_kernel(const fm_env* env) {
-  if (env->step_kernel == 1 || !fm::env_lane_shape(env->C)) return false;
+  if (env->step_kernel == 1 || env->step_kernel == 3 || !fm::env_lane_shape(env->C)) return false;
   return env->step_kernel == 2 || env->C.N >= kLaneMinEnvs;
 }
 
-// The plain path's one-step launches (ensemble means, noise and clip, then the trade) take the
-// lane kernel at every size its shape allows: it fetches the actors' means and the market rows
-// into LDS under the noise generation, and beat the tile kernel on MI355X from 2048 to 65536
-// environments (D = 30, K = 3).
-bool lane_kernel_means(const fm_env* env) { return env->step_kernel != 1 && fm::env_lane_shape(env->C); }
+// The plain path's one-step launches (ensemble means, noise and clip, then the trade): the row
+// kernel up to kRowMaxEnvs environments (at most 8 actors), else the lane kernel at every size its
+// shape allows; both fetch the actors' means and the market rows under the noise generation, and
+// beat the tile kernel on MI355X from 1024 to 65536 environments (D = 30, K = 3).
+bool row_kernel_means(const fm_env* env, int K) { return K <= 8 && row_kernel(env); }
+
+// Environments per wavefront of the row kernel: the caller's choice (env_set_step_kernel), else 2.
+int row_envs(const fm_env* env) { return env->lane_envs == 1 || env->lane_envs == 2 ? env->lane_envs : 2; }
+
+bool lane_kernel_means(const fm_env* env) {
+  return (env->step_kernel == 0 || env->step_kernel == 2) && fm::env_lane_shape(env->C);
+}
 
 // The caller's actions over n_steps days from day t0, by the chosen environment-step kernel.
 hipError_t launch_given(const fm_env* env, int t0, int n_steps, const float* act, float* obs, double* rew,
                         int* qty, hipStream_t stream) {
+  if (row_kernel(env))
+    return fm::launch_env_row_given(env->C, env->st, t0, n_steps, act, obs, rew, qty, row_envs(env), stream);
   if (lane_kernel(env))
     return fm::launch_env_lane_given(env->C, env->st, t0, n_steps, act, obs, rew, qty, env->lane_envs, stream);
   return fm::launch_env_given(env->C, env->st, t0, n_steps, act, obs, rew, qty, env->tile, stream);
@@ -728,7 +745,11 @@ fm_status env_rollout(fm_env* env, const fm_ensemble* ens, int32_t n_steps,
     double* rew = opts->d_rew_traj ? opts->d_rew_traj + static_cast<size_t>(i) * N : nullptr;
     int* qty = opts->d_qty_traj ? opts->d_qty_traj + static_cast<size_t>(i) * N * D : nullptr;
     const hipError_t e =
-        lane_kernel_means(env)
+        row_kernel_means(env, ens->K)
+            ? fm::launch_env_row_ensemble_step(C, env->st, t, ens->mu, ens->E.mix, ens->K, opts->sigma,
+                                               opts->noise_key, opts->env_offset, obs_out, act_out, rew, qty,
+                                               row_envs(env), st)
+        : lane_kernel_means(env)
             ? fm::launch_env_lane_ensemble_step(C, env->st, t, ens->mu, ens->E.mix, ens->K, opts->sigma,
                                                 opts->noise_key, opts->env_offset, obs_out, act_out, rew, qty,
                                                 env->lane_envs, st)
@@ -777,10 +798,12 @@ fm_status env_set_tile(fm_env* env, int32_t envs_per_group, int32_t* h_tile) {
 
 fm_status env_set_step_kernel(fm_env* env, int32_t kernel, int32_t envs_per_wave) {
   if (!env) return fail(FM_ERR_INVALID, "env is NULL");
-  if (kernel < 0 || kernel > 2) return fail(FM_ERR_INVALID, "kernel must be 0 (by shape), 1 (tile) or 2 (lane)");
+  if (kernel < 0 || kernel > 3)
+    return fail(FM_ERR_INVALID, "kernel must be 0 (by shape and size), 1 (tile), 2 (lane) or 3 (row)");
   if (envs_per_wave < 0 || envs_per_wave > 64) return fail(FM_ERR_INVALID, "envs_per_wave must be in 0..64");
-  if (kernel == 2 && !fm::env_lane_shape(env->C))
-    return fail(FM_ERR_UNSUPPORTED, "the lane kernel takes at most 32 stocks and (2 + n_ind) * n_stocks < 256");
+  if (kernel == 3 && envs_per_wave > 2) return fail(FM_ERR_INVALID, "the row kernel takes 1 or 2 environments per wavefront");
+  if ((kernel == 2 || kernel == 3) && !fm::env_lane_shape(env->C))
+    return fail(FM_ERR_UNSUPPORTED, "the lane and row kernels take at most 32 stocks and (2 + n_ind) * n_stocks < 256");
   env->step_kernel = kernel;
   env->lane_envs = envs_per_wave;
   return FM_OK;

@@ -22,6 +22,7 @@
 // rewards written, nothing else (the per-environment state stays in registers across steps).
 #include "device_common.h"
 #include "launch.h"
+#include "row_chain.h"
 
 namespace fm {
 
@@ -371,6 +372,220 @@ hipError_t launch_dp(const EnvConst& C, const EnvState& st, const LaneArgs& A, h
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------
+// Row variant (D <= 32): E = 1 or 2 environments per wavefront, one per 16-lane row (the other
+// rows repeat them and store nothing), lane j of a row owning stocks j and j + 16.  The step's chain is the
+// resident fused rollout's: the independent per-stock work spread over the row's lanes, the
+// serial cash recurrences on terms broadcast along the row (row_chain.h).  At small batches this
+// shortens a step: the 16 lanes of a row share an environment's instruction stream instead of
+// one lane issuing all of it.
+// ------------------------------------------------------------------------------------------
+constexpr int kRowEnvs = 2;  // the most environments per wavefront
+
+__host__ __device__ inline int row_wave_floats() { return 2 * kMktClose + 2 * kMktInd + 2 * (kRowEnvs + 1) * kRow; }
+
+template <int MODE, int E>
+__global__ __launch_bounds__(kWaves * 64) void env_row_kernel(EnvConst C, EnvState st, LaneArgs A) {
+#pragma clang fp contract(off)
+  extern __shared__ __align__(16) float lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n0 = (blockIdx.x * kWaves + wave) * E;
+  if (n0 >= C.N) return;  // the whole wavefront; no barrier follows
+  const int N = C.N, D = C.D, S = C.S, ID = C.I * D;
+  const int M = min(E, N - n0);
+  const int jl = lane & 15, m = (lane >> 4) & (E - 1);
+  const bool lead = lane < 16 * E;  // the rows that store their environment's results
+  const bool env_ok = m < M;
+  const int n = n0 + (env_ok ? m : 0);  // an idle row repeats environment n0 and stores nothing
+  float* mcl = lds + wave * row_wave_floats();  // [2][64]: close[t] | close[t+1], zero from 2D
+  float* mind = mcl + 2 * kMktClose;            // [2][256]: ind[t+1]
+  float* ent = mind + 2 * kMktInd;              // [2 + 1][kRow] the state rows' own entries
+  float* zrow = ent + (kRowEnvs + 1) * kRow;    // [2 + 1][kRow] noise (ensemble mode)
+
+  // The trading state: every lane of a row holds its environment's cash, value and cumulative
+  // reward; lane j the holdings of stocks j and j + 16 (zero beyond D).
+  double cash = st.cash[n], asset = st.asset[n], cumrew = st.cumrew[n];
+  const __amdgpu_buffer_rsrc_t hr = range_rsrc(reinterpret_cast<const float*>(st.hold), D * N);
+  int hold[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int d = jl + 16 * s;
+    hold[s] = __float_as_int(range_load(hr, d < D ? d * N + n : D * N));
+  }
+
+  auto fetch = [&](int it) {
+    const int t = A.t0 + it, b = it & 1;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(range_rsrc(C.close + static_cast<size_t>(t) * D, 2 * D),
+                                             mcl + b * kMktClose, 4, 4 * lane, 0, 0, 0);
+    const __amdgpu_buffer_rsrc_t ri = range_rsrc(C.ind + static_cast<size_t>(t + 1) * ID, ID);
+    for (int j = 0; 64 * j < ID; ++j)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ri, mind + b * kMktInd + 64 * j, 4, 4 * (lane + 64 * j), 0, 0, 0);
+  };
+  // Per-lane element of the wavefront's [M][D] block (the resources below cover the whole block,
+  // so their base stays wave-uniform); stocks beyond D index past the block and read zero.
+  auto blk = [&](int s) { return jl + 16 * s < D ? m * D + jl + 16 * s : M * D; };
+  // Driven: the row's actions of step it, one step ahead in registers (zero beyond D).
+  float pa[2] = {0.0f, 0.0f};
+  auto fetch_act = [&](int it) {
+    const __amdgpu_buffer_rsrc_t ra = range_rsrc(A.act + (static_cast<size_t>(it) * N + n0) * D, M * D);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) pa[s] = range_load(ra, blk(s));
+  };
+
+  fetch(0);
+  if (MODE == kDriven) fetch_act(0);
+  for (int it = 0; it < A.n_steps; ++it) {
+    const int t = A.t0 + it, b = it & 1;
+    const size_t row0 = static_cast<size_t>(it) * N + n0;
+    const float* px = mcl + b * kMktClose;
+    const float* ind = mind + b * kMktInd;
+    float a[2];
+    if (MODE == kDriven) {
+      a[0] = pa[0];
+      a[1] = pa[1];
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);  // step it's inputs have landed
+      if (it + 1 < A.n_steps) {
+        fetch(it + 1);
+        fetch_act(it + 1);
+      }
+    } else {
+      // Ensemble means, then the noise (Section 5.2.1): one Philox block per (environment, group
+      // of four stocks), lanes 0..7 of rows 0 and 1, through LDS to the lanes owning the stocks.
+      float acc[2] = {0.0f, 0.0f};
+      float mu[8][2];
+      const int K = min(A.K, 8);
+      for (int k = 0; k < K; ++k) {
+        const __amdgpu_buffer_rsrc_t rk = range_rsrc(A.mu + (static_cast<size_t>(k) * N + n0) * D, M * D);
+        mu[k][0] = range_load(rk, blk(0));
+        mu[k][1] = range_load(rk, blk(1));
+      }
+      if (A.sigma != 0.0f && lead && 4 * jl < D) {
+        float z[4];
+        noise_block(A.noise_key, static_cast<uint64_t>(A.env_offset + n), static_cast<uint64_t>(t),
+                    static_cast<uint64_t>(jl), z);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) zrow[m * kRow + 4 * jl + r] = z[r];
+      }
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      for (int k = 0; k < K; ++k) {
+        const float w = A.mix[k];
+        acc[0] = acc[0] + w * mu[k][0];
+        acc[1] = acc[1] + w * mu[k][1];
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int d = jl + 16 * s;
+        float x = acc[s];
+        if (A.sigma != 0.0f) x = acc[s] + A.sigma * zrow[m * kRow + min(d, kRow - 1)];
+        a[s] = d < D ? fminf(fmaxf(x, -1.0f), 1.0f) : 0.0f;
+        if (A.act_out && env_ok && lead && d < D)
+          A.act_out[static_cast<size_t>(n) * D + d] = a[s];
+      }
+    }
+
+    // The chain (Section 3.1): orders and sells, the sells' proceeds summed in stock order; the
+    // buys in stock order (events); holdings, the position values and the value in stock order.
+    int sold[2], q[2];
+    BuySet B[2];
+    double pro[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int d = jl + 16 * s;
+      const float p = d < D ? px[d] : 0.0f;
+      q[s] = d < D ? order_from_action(a[s], C.hmax_f) : 0;
+      sold[s] = q[s] < 0 ? min(hold[s], -q[s]) : 0;
+      hold[s] -= sold[s];
+      const double pd = static_cast<double>(p);
+      const int qd = q[s] > 0 ? q[s] : 0;
+      pro[s] = (pd * static_cast<double>(sold[s])) * C.one_m;
+      B[s].deb = (pd * static_cast<double>(qd)) * C.one_p;
+      B[s].c1 = pd * C.one_p;
+      B[s].pq = pack_pq(p, qd);
+    }
+    cash = row_sum(cash, pro[0]);
+    cash = row_sum(cash, pro[1]);
+    int kown[2] = {0, 0};
+    buy_all_seg(cash, kown, lane, B, C.one_p);
+    double val[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int d = jl + 16 * s;
+      hold[s] += kown[s];
+      const float pn = d < D ? px[D + d] : 0.0f;
+      val[s] = static_cast<double>(pn) * static_cast<double>(hold[s]);
+    }
+    double v = row_sum(cash, val[0]);
+    v = row_sum(v, val[1]);
+    const double r = (v - asset) * C.reward_scale;
+    cumrew = cumrew + r;
+    asset = v;
+
+    // Results: quantities and rewards straight from the owning lanes; the state rows' own
+    // entries through LDS, then the rows by column groups as in the lane kernel.
+    const bool own = env_ok && lead;
+    if (A.qty) {
+      const __amdgpu_buffer_rsrc_t rq = range_rsrc(reinterpret_cast<const float*>(A.qty) + row0 * D, M * D);
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        __builtin_amdgcn_raw_buffer_store_b32(q[s] < 0 ? -sold[s] : kown[s], rq, own ? 4 * blk(s) : kNoStore, 0, 0);
+    }
+    if (A.rew && own && jl == 0) A.rew[row0 + m] = r;
+    wave_lds_sync();  // the previous step's rows have been stored
+    if (jl == 0) ent[m * kRow] = static_cast<float>(cash * static_cast<double>(C.cash_scale));
+#pragma unroll
+    for (int s = 0; s < 2; ++s) ent[m * kRow + 1 + jl + 16 * s] = static_cast<float>(hold[s]) * C.hold_scale;
+    wave_lds_sync();
+    if (A.obs) {
+      const __amdgpu_buffer_rsrc_t orow = range_rsrc(A.obs + row0 * S, M * S);
+      const int ent_o = static_cast<int>(ent - mcl), pn_o = static_cast<int>(px - mcl) + D;
+      const int ind_o = static_cast<int>(ind - mcl);
+#pragma unroll
+      for (int g = 0; g < kColGroups; ++g) {
+        const int f = lane + 64 * g;
+        const bool own_col = f == 0 || (f > D && f <= 2 * D);
+        const int src = own_col ? ent_o + (f == 0 ? 0 : f - D) : (f <= D ? pn_o + f - 1 : ind_o + min(f, S - 1) - 1 - 2 * D);
+        const float scale = (f >= 1 && f <= D) ? C.price_scale : 1.0f;
+        const int cb = f < S ? 4 * f : kNoStore;
+        const float x0 = mcl[src], x1 = mcl[src + (own_col ? kRow : 0)];
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x0 * scale), orow, cb, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x1 * scale), orow, 4 * S + cb, 0, 0);
+      }
+    }
+  }
+
+  if (env_ok && lead) {
+    if (jl == 0) {
+      st.cash[n] = cash;
+      st.asset[n] = asset;
+      st.cumrew[n] = cumrew;
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int d = jl + 16 * s;
+      __builtin_amdgcn_raw_buffer_store_b32(hold[s], hr, d < D ? 4 * (d * N + n) : kNoStore, 0, 0);
+    }
+  }
+}
+
+template <int MODE, int E>
+hipError_t launch_row_e(const EnvConst& C, const EnvState& st, const LaneArgs& A, hipStream_t stream) {
+  const int waves = (C.N + E - 1) / E;
+  const int grid = (waves + kWaves - 1) / kWaves;
+  const size_t lds = sizeof(float) * kWaves * row_wave_floats();
+  hipLaunchKernelGGL((env_row_kernel<MODE, E>), dim3(grid), dim3(kWaves * 64), lds, stream, C, st, A);
+  return hipGetLastError();
+}
+
+// A.M: environments per wavefront, 1 or 2 (0: by N).
+template <int MODE>
+hipError_t launch_row(const EnvConst& C, const EnvState& st, const LaneArgs& A, hipStream_t stream) {
+  if (!env_lane_shape(C) || (MODE == kMeans && A.K > 8) || A.M < 0 || A.M > kRowEnvs) return hipErrorInvalidValue;
+  if (A.n_steps <= 0 || C.N <= 0) return hipSuccess;
+  return A.M == 1 ? launch_row_e<MODE, 1>(C, st, A, stream) : launch_row_e<MODE, 2>(C, st, A, stream);
+}
+
 template <int MODE>
 hipError_t launch_mode(const EnvConst& C, const EnvState& st, LaneArgs A, hipStream_t stream) {
   if (!env_lane_shape(C)) return hipErrorInvalidValue;
@@ -411,6 +626,40 @@ hipError_t launch_env_lane_given(const EnvConst& C, const EnvState& st, int t0, 
   A.rew = rew;
   A.qty = qty;
   return launch_mode<kDriven>(C, st, A, stream);
+}
+
+hipError_t launch_env_row_given(const EnvConst& C, const EnvState& st, int t0, int n_steps, const float* act,
+                                float* obs, double* rew, int* qty, int envs_per_wave, hipStream_t stream) {
+  LaneArgs A{};
+  A.M = envs_per_wave;
+  A.t0 = t0;
+  A.n_steps = n_steps;
+  A.act = act;
+  A.obs = obs;
+  A.rew = rew;
+  A.qty = qty;
+  return launch_row<kDriven>(C, st, A, stream);
+}
+
+hipError_t launch_env_row_ensemble_step(const EnvConst& C, const EnvState& st, int t, const float* mu,
+                                        const float* mix, int K, float sigma, uint64_t key, int64_t env_offset,
+                                        float* obs, float* act_out, double* rew, int* qty, int envs_per_wave,
+                                        hipStream_t stream) {
+  LaneArgs A{};
+  A.M = envs_per_wave;
+  A.t0 = t;
+  A.n_steps = 1;
+  A.mu = mu;
+  A.mix = mix;
+  A.K = K;
+  A.sigma = sigma;
+  A.noise_key = key;
+  A.env_offset = env_offset;
+  A.obs = obs;
+  A.act_out = act_out;
+  A.rew = rew;
+  A.qty = qty;
+  return launch_row<kMeans>(C, st, A, stream);
 }
 
 hipError_t launch_env_lane_ensemble_step(const EnvConst& C, const EnvState& st, int t, const float* mu,

@@ -31,6 +31,14 @@ hipError_t launch_env_lane_ensemble_step(const EnvConst& C, const EnvState& st, 
                                          const float* mix, int K, float sigma, uint64_t key, int64_t env_offset,
                                          float* obs, float* act_out, double* rew, int* qty, int envs_per_wave,
                                          hipStream_t stream);
+// Row variant (env_lane.hip): one or two environments per wavefront (envs_per_wave; 0: by N),
+// a 16-lane row each; same shapes.
+hipError_t launch_env_row_given(const EnvConst& C, const EnvState& st, int t0, int n_steps, const float* act,
+                                float* obs, double* rew, int* qty, int envs_per_wave, hipStream_t stream);
+hipError_t launch_env_row_ensemble_step(const EnvConst& C, const EnvState& st, int t, const float* mu,
+                                        const float* mix, int K, float sigma, uint64_t key, int64_t env_offset,
+                                        float* obs, float* act_out, double* rew, int* qty, int envs_per_wave,
+                                        hipStream_t stream);
 hipError_t launch_read_state(const EnvConst& C, const EnvState& st, double* cash, int* hold,
                              double* asset, double* cumrew, hipStream_t stream);
 hipError_t launch_write_state(const EnvConst& C, const EnvState& st, const double* cash,

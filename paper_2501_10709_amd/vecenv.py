@@ -84,8 +84,9 @@ class VecEnv:
         return B.env_set_tile(self.handle, envs_per_group)
 
     def set_step_kernel(self, kernel=0, envs_per_wave=0):
-        """Environment-step kernel: 0 by shape, 1 the tile kernel, 2 one lane per environment;
-        environments per wavefront of the lane kernel (0: by N)."""
+        """Environment-step kernel: 0 by shape and size, 1 the tile kernel, 2 one lane per
+        environment, 3 a 16-lane row per environment; environments per wavefront of the lane
+        kernel (0: by N)."""
         B.env_set_step_kernel(self.handle, kernel, envs_per_wave)
 
     def set_fused_tuning(self, schedule=0, row_tiles=0, tile_envs=0):

@@ -31,14 +31,15 @@ def _to_np(t):
     return t.detach().cpu().numpy()
 
 
-KERNELS = {0: "by-shape", 1: "tile", 2: "lane"}
-DRIVEN = [c + (k,) for c in CASES for k in KERNELS if not (k == 2 and c[2] > 32)]
+KERNELS = {0: "by-shape", 1: "tile", 2: "lane", 3: "row"}
+DRIVEN = [c + (k,) for c in CASES for k in KERNELS if not (k >= 2 and c[2] > 32)]
 
 
 @pytest.mark.parametrize("name,N,D,I,T,seed,extra,kernel", DRIVEN, ids=[f"{c[0]}-{KERNELS[c[-1]]}" for c in DRIVEN])
 def test_driven_rollout_matches_oracle(name, N, D, I, T, seed, extra, kernel):
     """kernel 0 picks by shape and size (the tile kernel below 24576 environments), 1 the tile
-    kernel, 2 the lane kernel (one lane per environment) where the shape allows (D <= 32)."""
+    kernel, 2 the lane kernel (one lane per environment), 3 the row kernel (a 16-lane row per
+    environment) where the shape allows (D <= 32)."""
     import torch
     from paper_2501_10709_amd.vecenv import VecEnv
     dev = cuda()
@@ -120,7 +121,9 @@ def test_lane_kernel_plain_steps_match_tile_kernel():
     """The plain path's ensemble steps (mean of the actors, noise, clip, trade) through the lane
     kernel and through the tile kernel: the same arithmetic, so every output is bit-identical.
     The lane kernel stages the actors' means through LDS for small wavefront tiles (1 and 5
-    environments) and reads them into registers for a full 64-environment tile."""
+    environments) and reads them into registers for a full 64-environment tile; the row kernel
+    takes them per lane (one or two environments per wavefront).  N = 77: the last wavefront of the
+    two-environment row kernel holds one environment."""
     import torch
     from paper_2501_10709_amd.vecenv import Ensemble, VecEnv
     from _helpers import actors_case
@@ -130,7 +133,7 @@ def test_lane_kernel_plain_steps_match_tile_kernel():
     _, _, packed = actors_case(3, 211, 64, D)
     ens = Ensemble(packed, 3, 211, 64, D, dtype="f32", max_batch=N, device=dev)
     out = []
-    for kernel, M in ((1, 0), (2, 0), (2, 5), (2, 64)):
+    for kernel, M in ((1, 0), (2, 0), (2, 5), (2, 64), (3, 0), (3, 1)):
         env = VecEnv(cfg, m.close, m.ind, device=dev)
         env.set_step_kernel(kernel, M)
         env.reset(return_obs=False)
@@ -138,6 +141,41 @@ def test_lane_kernel_plain_steps_match_tile_kernel():
     for other in out[1:]:
         for k in out[0]:
             assert torch.equal(out[0][k], other[k]), k
+
+
+ROW = [
+    # N, D, I, T, cash, hmax
+    (31, 30, 5, 9, 1e6, 100),    # the last wavefront holds one environment
+    (20, 32, 5, 7, 1e6, 100),    # 32 stocks: both stock slots of every lane in use
+    (18, 17, 4, 8, 1e6, 100),
+    (9, 3, 2, 8, 1e6, 100),
+    (33, 30, 5, 12, 4e3, 50),    # cash binds: partial fills on most days
+    (258, 32, 3, 16, 3e4, 100),  # cash binds after a few days: runs of whole fills then partials
+]
+
+
+@pytest.mark.parametrize("envs_per_wave", [1, 2])
+@pytest.mark.parametrize("N,D,I,T,cash,hmax", ROW)
+def test_row_kernel_matches_oracle(N, D, I, T, cash, hmax, envs_per_wave):
+    """The row kernel (one or two environments per wavefront) driven by the same actions as the
+    oracle: holdings, quantities, states and float64 cash bit-exact."""
+    import torch
+    from paper_2501_10709_amd.vecenv import VecEnv
+    dev = cuda()
+    print(f"[row] N={N} D={D} I={I} T={T} cash={cash} envs_per_wave={envs_per_wave}", flush=True)
+    cfg, m = env_case(N, D, I, T, 60 + D, hmax=hmax, cash=cash)
+    acts = make_actions(97 + D, T, N, D)
+    env = VecEnv(cfg, m.close, m.ind, device=dev)
+    env.set_step_kernel(3, envs_per_wave)
+    obs0 = _to_np(env.reset())
+    traj = env.rollout(T, actions=torch.from_numpy(acts).to(dev))
+    st = env.read_state()
+    traj = {k: _to_np(v) for k, v in traj.items()}
+    ref = check_replay(cfg, m, traj, obs0)
+    assert np.array_equal(_to_np(st["hold"]), ref["hold"])
+    assert np.array_equal(_to_np(st["cash"]), ref["cash"])
+    assert np.array_equal(_to_np(st["asset"]), ref["asset"])
+    assert np.abs(traj["qty"]).sum() > 0
 
 
 def test_step_kernel_choice_validation():
@@ -148,8 +186,15 @@ def test_step_kernel_choice_validation():
     with pytest.raises(RuntimeError):
         env.set_step_kernel(2)  # 40 stocks: beyond the lane kernel
     with pytest.raises(RuntimeError):
-        env.set_step_kernel(3)
+        env.set_step_kernel(3)  # also beyond the row kernel
+    with pytest.raises(RuntimeError):
+        env.set_step_kernel(4)
     env.set_step_kernel(0)
+    cfg, m = env_case(8, 30, 5, 4, 3)
+    env = VecEnv(cfg, m.close, m.ind, device=dev)
+    with pytest.raises(RuntimeError):
+        env.set_step_kernel(3, 3)  # the row kernel holds one or two environments per wavefront
+    env.set_step_kernel(3, 1)
 
 
 def test_step_api_matches_oracle_and_reports_done():
