@@ -317,6 +317,9 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
       store_f32(r, u < n_mkt ? off : kNoStore, u < D ? v[k] * C.price_scale : v[k]);
     }
   };
+  // Every set-up load has landed: a load still counted as pending on entry would make the
+  // compiler wait for all memory operations, stores included, at the top of every step.
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   for (int j = 0; j < F.n_steps; ++j) {
     const int b = j & 1;
     const bool nxt = j + 1 < F.n_steps;
@@ -389,13 +392,12 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
         const int d = jl + 16 * s;
         const bool on = env_ok && d < D;
         // Action: a_bar = sum_k w_k tanh(z_k + b3_k) in actor order, noise, clip (Section 5.2.1).
-        float act = 0.0f;
-        if (on) {
-          const float* mk = s_mu + m * 32 + d;
-          act = (mk[0] + mk[MR * 32]) + mk[2 * MR * 32];
-          if (F.sigma != 0.0f) act = act + F.sigma * eps[s];
-          act = fminf(fmaxf(act, -1.0f), 1.0f);
-        }
+        // Formed on every lane (m < 8 and d < 32 stay inside the means) and kept where on: the
+        // noise load is then consumed on every path, and no load is left pending at the next step.
+        const float* mk = s_mu + m * 32 + d;
+        const float mean = (mk[0] + mk[MR * 32]) + mk[2 * MR * 32];
+        const float noisy = F.sigma != 0.0f ? mean + F.sigma * eps[s] : mean;
+        const float act = on ? fminf(fmaxf(noisy, -1.0f), 1.0f) : 0.0f;
         store_f32(rows_rsrc(F.act_traj, row0 * D, 4, M * D), on && lane < 32 ? 4 * (em + d) : kNoStore, act);
         // Order and sale of stock d; the whole-order and one-share debits.
         const float p = on ? in[d] : 0.0f;
@@ -414,7 +416,7 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
       cash = row_sum(cash, pro[0]);
       cash = row_sum(cash, pro[1]);
       int kown[2] = {0, 0};
-      buy_all(cash, kown, lane, B, C.one_p);
+      buy_all_seg(cash, kown, lane, B, C.one_p);
       // Holdings, executed quantities, the new day's position values, value and reward
       // (Section 3.1 reward, reading 8).
       double val[2];
@@ -441,15 +443,16 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
         s_state[4 * m + 1] = v_new;
         s_state[4 * m + 2] = s_state[4 * m + 2] + r;
         s_x0[m * kRX0] = static_cast<__bf16>(ce);
-        if (F.rew_traj) F.rew_traj[row] = r;
-        if (F.obs_traj) F.obs_traj[row * S] = ce;
+        typedef __attribute__((ext_vector_type(2))) unsigned u32x2;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, r), rows_rsrc(F.rew_traj, row0, 8, M), 8 * m, 0, 0);
+        store_f32(rows_rsrc(F.obs_traj, row0 * S, 4, M * S), 4 * m * S, ce);
       }
     }
-    if (nxt) {
-      s_in[(b ^ 1) * kRIn + tid] = p_in;
+    // The next step's inputs into LDS (zeros after the last step: its loads had empty ranges), on
+    // every path, so that no load is still pending when the next step begins.
+    s_in[(b ^ 1) * kRIn + tid] = p_in;
 #pragma unroll
-      for (int r = 0; r < K; ++r) s_mt[tid + kRT * r] = p_mt[r];
-    }
+    for (int r = 0; r < K; ++r) s_mt[tid + kRT * r] = p_mt[r];
     __syncthreads();  // 4: the next state rows and inputs are in LDS
   }
   if (F.n_steps >= 1)
