@@ -87,6 +87,14 @@ struct FusedLds {
   }
 };
 
+// Global-memory view of a pointer.  The batched form reads its groups' pointers from memory, and
+// the compiler would access memory through such pointers with flat instructions, which also
+// count on the LDS counter, so that the step's LDS waits would also wait for them.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // The environment half of a step, shared by both schedules.  NT threads per workgroup.
 template <int NT>
 struct EnvPhase {
@@ -101,12 +109,12 @@ struct EnvPhase {
   __device__ void stage_market(int tn, bool with_trade_day) {
     const int D = C.D;
     for (int d = tid; d < D; d += NT) {
-      if (with_trade_day) L.px[d] = C.close[static_cast<size_t>(tn - 1) * D + d];
-      const float pn = C.close[static_cast<size_t>(tn) * D + d];
+      if (with_trade_day) L.px[d] = gbl(C.close)[static_cast<size_t>(tn - 1) * D + d];
+      const float pn = gbl(C.close)[static_cast<size_t>(tn) * D + d];
       L.pn[d] = pn;
       L.mkt[d] = pn * C.price_scale;
     }
-    for (int i = tid; i < C.I * D; i += NT) L.mkt[D + i] = C.ind[static_cast<size_t>(tn) * C.I * D + i];
+    for (int i = tid; i < C.I * D; i += NT) L.mkt[D + i] = gbl(C.ind)[static_cast<size_t>(tn) * C.I * D + i];
   }
 
   // a = clip(a_bar + sigma * eps, -1, 1) into LDS (and the action trajectory).
@@ -127,7 +135,7 @@ struct EnvPhase {
           if (F.sigma != 0.0f) a = a + F.sigma * z[r];
           a = fminf(fmaxf(a, -1.0f), 1.0f);
           L.act[m * D + d] = a;
-          if (F.act_traj) F.act_traj[(row_base + m) * D + d] = a;
+          if (F.act_traj) gbl(F.act_traj)[(row_base + m) * D + d] = a;
         }
       }
     }
@@ -188,7 +196,7 @@ struct EnvPhase {
         else if (f <= D) v = L.mkt[f - 1];
         else if (f <= 2 * D) v = L.env[m * DS + f - D];
         else v = L.mkt[f - 1 - D];
-        if (traj) traj[static_cast<size_t>(m) * S + f] = v;
+        if (traj) gbl(traj)[static_cast<size_t>(m) * S + f] = v;
       }
       if (split_pad == 0) L.x0[m * st0 + f] = static_cast<__bf16>(v);
     }
@@ -205,7 +213,7 @@ struct EnvPhase {
   __device__ void quantities(size_t row_base) {
     if (!F.qty_traj) return;
     const int D = C.D;
-    for (int i = tid; i < M * D; i += NT) F.qty_traj[row_base * D + i] = L.qty[i];
+    for (int i = tid; i < M * D; i += NT) gbl(F.qty_traj)[row_base * D + i] = L.qty[i];
   }
 
   // Load the tile's state into the owner lanes (holdings into LDS).
@@ -822,7 +830,7 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
       const float* b1 = reinterpret_cast<const float*>(PA + E.off_b1);
       const float* b2 = reinterpret_cast<const float*>(PA + E.off_b2);
       const float* b3 = reinterpret_cast<const float*>(PA + E.off_b3);
-      const float wk = E.mix[k];
+      const float wk = gbl(E.mix)[k];
       // Layer 1's bias, or with the split layer the day's market share (bias included).
       const float* b1t = split_pad > 0 ? F.mt + (static_cast<size_t>(it) * E.K + k) * E.H : b1;
       const bf16x8* W1 = split_pad > 0
@@ -832,7 +840,7 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
       layer_bf16<ROWT, TMAX>(L.x0, st0, split_pad > 0 ? split_pad : E.S_pad, W1, ht, wave, lane,
                              [&](int rt, int c, floatx4 acc) {
                                const int col = 16 * c + col_l;
-                               const float b = b1t[col];
+                               const float b = gbl(b1t)[col];
 #pragma unroll
                                for (int q = 0; q < 4; ++q)
                                  L.x1[(rt * 16 + row_q + q) * sth + col] = static_cast<__bf16>(fast_tanh(acc[q] + b));
@@ -841,7 +849,7 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
       layer_bf16<ROWT, TMAX>(L.x1, sth, E.H, reinterpret_cast<const bf16x8*>(PA + E.off_w2), ht, wave, lane,
                              [&](int rt, int c, floatx4 acc) {
                                const int col = 16 * c + col_l;
-                               const float b = b2[col];
+                               const float b = gbl(b2)[col];
 #pragma unroll
                                for (int q = 0; q < 4; ++q)
                                  L.x2[(rt * 16 + row_q + q) * sth + col] = static_cast<__bf16>(fast_tanh(acc[q] + b));
@@ -850,7 +858,7 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
       auto out3 = [&](int rt, int c, floatx4 acc) {
         const int col = 16 * c + col_l;
         if (col >= E.A) return;
-        const float b = b3[col];
+        const float b = gbl(b3)[col];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           float* dst = &L.abar[(rt * 16 + row_q + q) * DS + col];
@@ -890,7 +898,7 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
     P.actions(t, row_base);
     __syncthreads();
     const double rwd = P.chain(owner, cash, asset, cumrew);
-    if (owner && F.rew_traj) F.rew_traj[static_cast<size_t>(it) * N + n] = rwd;
+    if (owner && F.rew_traj) gbl(F.rew_traj)[static_cast<size_t>(it) * N + n] = rwd;
     __syncthreads();
     P.quantities(row_base);
     P.assemble(F.obs_traj ? F.obs_traj + row_base * C.S : nullptr, split_pad);

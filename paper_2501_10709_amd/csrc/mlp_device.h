@@ -87,6 +87,10 @@ __device__ __forceinline__ floatx4 mfma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
 // wave owns.  Each B-operand fragment serves all RT row tiles; the fragments of the next RING
 // k-steps are in flight while the current k-step's MFMAs run.  [kbeg, kend) restricts the sum to
 // those k-steps (16 k for float32, 32 for bfloat16; kend < 0: to the end).
+// The bfloat16 weights are read through a global-address-space pointer: a pointer that reached
+// the kernel through memory (the batched form's group table) would otherwise be read with flat
+// loads, which also count on the LDS counter, so that each wait for an activation fragment in
+// LDS would wait for the weight prefetch as well.
 template <int DT, int TMAX, int RT, int NW, class Epi, int RING = 4>
 __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int in_stride,
                                           int kin_pad, const void* wp, int ntiles, int wave,
@@ -138,7 +142,7 @@ __device__ __forceinline__ void mlp_layer(const typename MT<DT>::act_t* sin, int
       }
     }
   } else {
-    const bf16x8* W = static_cast<const bf16x8*>(wp);
+    const __attribute__((address_space(1))) bf16x8* W = (const __attribute__((address_space(1))) bf16x8*)wp;
     const int KK = kin_pad / 32, K1 = kend < 0 ? KK : min(kend, KK);
     bf16x8 ring[RING][TMAX];
     auto fetch = [&](bf16x8 (&dst)[TMAX], int kk) {
