@@ -238,13 +238,12 @@ struct EnvPhase {
 // ------------------------------------------------------------------------------------------
 // Generic MLP schedule (runtime shapes): wavefront w owns output tiles w, w+4, ...; the weight
 // fragments of the next four k-steps are in flight in a register ring while the current ones are
-// multiplied (the ensemble MLP's layer loop).
+// multiplied (the ensemble MLP's layer loop).  The epilogue gets (row tile, slot i, tile c).
 // ------------------------------------------------------------------------------------------
 template <int ROWT, int TMAX, class Epi>
 __device__ __forceinline__ void layer_bf16(const __bf16* sin, int ist, int kin_pad, const bf16x8* W,
                                            int ntiles, int wave, int lane, Epi epi) {
-  auto e = [&](int rt, int, int c, floatx4 acc) { epi(rt, c, acc); };
-  mlp_layer<kBF16, TMAX, ROWT, 4, decltype(e), 4>(sin, ist, kin_pad, W, ntiles, wave, lane, e);
+  mlp_layer<kBF16, TMAX, ROWT, 4, Epi, 4>(sin, ist, kin_pad, W, ntiles, wave, lane, epi);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -837,28 +836,51 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
                              ? reinterpret_cast<const bf16x8*>(E.base + E.off_w1e +
                                                                static_cast<size_t>(k) * E.H * split_pad * 2)
                              : reinterpret_cast<const bf16x8*>(PA + E.off_w1);
+      // Each layer's biases for the wavefront's output tiles are requested before its k loop, so
+      // that the epilogues do not wait for them (up to four tiles per wavefront; with eight the
+      // registers are short, and the epilogue reads its bias).
+      constexpr bool kPre = TMAX <= 4;
+      float bv[TMAX];
+      const float* bsrc = nullptr;
+      auto bias = [&](const float* b, int ntiles, int n) {  // n: the layer's outputs
+        bsrc = b;
+        if constexpr (kPre) {
+#pragma unroll
+          for (int i = 0; i < TMAX; ++i) {
+            const int c = wave + 4 * i;
+            bv[i] = c < ntiles && 16 * c + col_l < n ? gbl(b)[16 * c + col_l] : 0.0f;
+          }
+        }
+      };
+      auto bias_of = [&](int i, int col) -> float {
+        if constexpr (kPre) return bv[i];
+        else return gbl(bsrc)[col];
+      };
+      bias(b1t, ht, E.H);
       layer_bf16<ROWT, TMAX>(L.x0, st0, split_pad > 0 ? split_pad : E.S_pad, W1, ht, wave, lane,
-                             [&](int rt, int c, floatx4 acc) {
+                             [&](int rt, int i, int c, floatx4 acc) {
                                const int col = 16 * c + col_l;
-                               const float b = gbl(b1t)[col];
+                               const float b = bias_of(i, col);
 #pragma unroll
                                for (int q = 0; q < 4; ++q)
                                  L.x1[(rt * 16 + row_q + q) * sth + col] = static_cast<__bf16>(fast_tanh(acc[q] + b));
                              });
+      bias(b2, ht, E.H);
       __syncthreads();
       layer_bf16<ROWT, TMAX>(L.x1, sth, E.H, reinterpret_cast<const bf16x8*>(PA + E.off_w2), ht, wave, lane,
-                             [&](int rt, int c, floatx4 acc) {
+                             [&](int rt, int i, int c, floatx4 acc) {
                                const int col = 16 * c + col_l;
-                               const float b = gbl(b2)[col];
+                               const float b = bias_of(i, col);
 #pragma unroll
                                for (int q = 0; q < 4; ++q)
                                  L.x2[(rt * 16 + row_q + q) * sth + col] = static_cast<__bf16>(fast_tanh(acc[q] + b));
                              });
+      bias(b3, at, E.A);
       __syncthreads();
-      auto out3 = [&](int rt, int c, floatx4 acc) {
+      auto out3 = [&](int rt, int i, int c, floatx4 acc) {
         const int col = 16 * c + col_l;
         if (col >= E.A) return;
-        const float b = gbl(b3)[col];
+        const float b = bias_of(i, col);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           float* dst = &L.abar[(rt * 16 + row_q + q) * DS + col];
@@ -888,7 +910,7 @@ __device__ __forceinline__ void generic_tile(const EnvConst& C, const EnvState& 
 #pragma unroll
               for (int r = 0; r < 4; ++r) acc[r] = acc[r] + p[r];
             }
-            out3(rt, wave, acc);
+            out3(rt, 0, wave, acc);  // tile c = wave: slot 0 of the wavefront's biases
           }
         }
       }
