@@ -175,16 +175,26 @@ __device__ __forceinline__ void buy_all_seg(double& cash, int (&kown)[2], int la
     return;
   }
   const int q0 = pq_order(B[0].pq), q1 = pq_order(B[1].pq);
+  const int rsh = lane & 48;  // this lane's row's bits in a ballot
   int dn = 0;  // the row's next stock to consider
   for (int it = 0; it <= 32; ++it) {
     const bool c0 = q0 > 0 && B[0].c1 <= cash && jl >= dn;
     const bool c1 = q1 > 0 && B[1].c1 <= cash && jl + 16 >= dn;
-    if (__builtin_amdgcn_ballot_w64(c0 || c1) == 0) break;
-    double mid, end;
-    const double p0 = row_prefix(cash, c0 ? B[0].deb : 0.0, mid);
-    const double p1 = row_prefix(mid, c1 ? B[1].deb : 0.0, end);
+    const unsigned long long b0 = __builtin_amdgcn_ballot_w64(c0);
+    if ((b0 | __builtin_amdgcn_ballot_w64(c1)) == 0) break;
+    // A prefix is formed only where some row needs it: stocks 0-15 when a row has candidates
+    // there; stocks 16-31 when a row without a failure among stocks 0-15 has candidates there.
+    double mid = cash, end, p0 = cash, p1;
+    if (b0 != 0) p0 = row_prefix(cash, c0 ? B[0].deb : 0.0, mid);
     const unsigned long long f0 = __builtin_amdgcn_ballot_w64(c0 && !(B[0].deb <= p0));
-    const unsigned long long f1 = __builtin_amdgcn_ballot_w64(c1 && !(B[1].deb <= p1));
+    const bool own_f0 = ((f0 >> rsh) & 0xffffu) != 0;
+    unsigned long long f1 = 0;
+    end = mid;
+    p1 = mid;
+    if (__builtin_amdgcn_ballot_w64(c1 && !own_f0) != 0) {
+      p1 = row_prefix(mid, c1 ? B[1].deb : 0.0, end);
+      f1 = __builtin_amdgcn_ballot_w64(c1 && !(B[1].deb <= p1));
+    }
     const unsigned m0 = static_cast<unsigned>(f0 & 0xffffu) | (static_cast<unsigned>(f1 & 0xffffu) << 16);
     const unsigned m1 = static_cast<unsigned>((f0 >> 16) & 0xffffu) | (static_cast<unsigned>((f1 >> 16) & 0xffffu) << 16);
     const unsigned mine = rl == 0 ? m0 : m1;
