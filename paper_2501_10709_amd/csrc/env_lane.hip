@@ -319,31 +319,41 @@ __global__ __launch_bounds__(kWaves * 64) void env_lane_kernel(EnvConst C, EnvSt
       // range of at most 64 rows).  Four rows per batch: every read is issued before the first
       // store; rows past M read row M - 1 and store beyond the range.
       const __amdgpu_buffer_rsrc_t orow = range_rsrc(A.obs + row0 * S, M * S);
-      int src[kColGroups], stride[kColGroups], cb[kColGroups];
+      // Per lane and column group: the LDS byte address of the column's value for row 0, a mask
+      // that keeps the row's byte offset for the environment's own entries (zero for market
+      // columns, shared by all rows), the scale, and the column's byte offset in a row.  The
+      // row offsets are wave-uniform, so each value costs an and, two adds, a read, a multiply
+      // and a store.
+      int src[kColGroups], own[kColGroups], cb[kColGroups];
       float scale[kColGroups];
       const int ent_o = static_cast<int>(ent - mcl), pn_o = static_cast<int>(pn - mcl);
       const int ind_o = static_cast<int>(ind - mcl);
 #pragma unroll
       for (int g = 0; g < kColGroups; ++g) {
         const int f = L + 64 * g;
-        const bool own = f == 0 || (f > D && f <= 2 * D);
-        src[g] = own ? ent_o + (f == 0 ? 0 : f - D) : (f <= D ? pn_o + f - 1 : ind_o + min(f, S - 1) - 1 - 2 * D);
-        stride[g] = own ? kRow : 0;
+        const bool o = f == 0 || (f > D && f <= 2 * D);
+        src[g] = 4 * (o ? ent_o + (f == 0 ? 0 : f - D) : (f <= D ? pn_o + f - 1 : ind_o + min(f, S - 1) - 1 - 2 * D));
+        own[g] = o ? -1 : 0;
         scale[g] = (f >= 1 && f <= D) ? C.price_scale : 1.0f;
         cb[g] = f < S ? 4 * f : kNoStore;
       }
+      const char* lbase = reinterpret_cast<const char*>(mcl);
       for (int m0 = 0; m0 < M; m0 += 4) {
         float x[4][kColGroups];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int g = 0; g < kColGroups; ++g) x[r][g] = mcl[src[g] + min(m0 + r, M - 1) * stride[g]];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < 4; ++r) {
+          const int ro = 4 * kRow * min(m0 + r, M - 1);  // rows past M read row M - 1
 #pragma unroll
           for (int g = 0; g < kColGroups; ++g)
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x[r][g] * scale[g]), orow, 4 * (m0 + r) * S + cb[g],
-                                                  0, 0);
+            x[r][g] = *reinterpret_cast<const float*>(lbase + src[g] + (own[g] & ro));
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int so = 4 * (m0 + r) * S;  // rows past M store beyond the range
+#pragma unroll
+          for (int g = 0; g < kColGroups; ++g)
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x[r][g] * scale[g]), orow, so + cb[g], 0, 0);
+        }
       }
     }
     wave_lds_sync();  // the stores have read the LDS rows before the next step rewrites them
