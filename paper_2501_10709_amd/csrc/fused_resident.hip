@@ -26,8 +26,12 @@
 //         terms broadcast from the owning lane (DPP row broadcasts, no LDS round trip), keeping
 //         the fills of its own stocks; holdings, position values, the new value and reward, the
 //         next state row, and the trajectory stores straight from registers.
-// The step's noise (drawn per chunk by noise_chunk_kernel) and the next step's market rows and
-// table row are requested at the top of a step and used after the MLP.
+// The step's noise (drawn per chunk by noise_chunk_kernel) is requested at the top of a step and
+// used after the MLP.  The inputs travel by buffer loads that write LDS directly: the next step's
+// table row, a third by each of wavefronts 0-2 at the top of a step (waited for after the third
+// barrier; double-buffered), and the market rows two steps ahead by wavefront 3 after its trades
+// (waited for in the next step's L3; triple-buffered).  Wavefront 3, which has no actor in L3,
+// also stores the market entries of all eight state rows of the previous step there.
 #include <cstring>
 #include <utility>
 
@@ -45,6 +49,10 @@ constexpr int kRK = 3, kRH = 256, kRKK = 8;
 constexpr int kRX0 = 40;     // state-row stride (bfloat16): cash, <= 31 holdings, zeros
 constexpr int kRXS = 264;    // hidden-row stride (bfloat16)
 constexpr int kRIn = 256;    // market entries per day, (2 + I) * D <= 256
+// An input buffer in LDS: close[t] | close[t+1] in floats 0 .. 2D-1, ind[t+1] from float kRInd
+// (the fetch writes whole runs of 64 floats, so the two parts do not overlap).
+constexpr int kRInd = 64;
+constexpr int kRInBuf = kRInd + 256;
 
 constexpr size_t r16(size_t b) { return (b + 15) / 16 * 16; }
 
@@ -60,13 +68,14 @@ struct RLds {
   static constexpr size_t b2 = x0 + r16(sizeof(__bf16) * kResRows * kRX0);         // [K][256] f32
   static constexpr size_t b3 = b2 + sizeof(float) * kRK * kRH;                     // [K][32] f32
   static constexpr size_t mix = b3 + sizeof(float) * kRK * 32;                     // [4] f32
-  static constexpr size_t mt = mix + 16;                                           // [K][256] f32
-  static constexpr size_t in = mt + sizeof(float) * kRK * kRH;                     // [2][256] f32
-  static constexpr size_t state = in + sizeof(float) * 2 * kRIn;                   // [8] {cash, value, cumrew, 0} f64
+  static constexpr size_t mt = mix + 16;                                           // [2][K][256] f32
+  static constexpr size_t in = mt + sizeof(float) * 2 * kRK * kRH;                 // [3][320] f32
+  static constexpr size_t state = in + sizeof(float) * 3 * kRInBuf;                // [8] {cash, value, cumrew, 0} f64
   static constexpr size_t total = state + sizeof(double) * 4 * kResRows;
   static_assert(sizeof(float) * kRK * kResRows * 32 <= xb, "the actor means fit the layer-1 region");
 };
 static_assert(RLds::total <= 160 * 1024, "LDS budget");
+static_assert(kRK * kRH % (64 * 3) == 0, "wavefronts 0-2 fetch equal shares of a table row");
 
 // An opaque zero: values derived from it are recomputed where they are used instead of being
 // hoisted out of the step loop and held in registers.
@@ -213,7 +222,6 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
   const int D = C.D, N = C.N, I = C.I, S = C.S;
   const int n0 = blockIdx.x * F.tile_envs;
   const int M = min(F.tile_envs, N - n0);
-  const int n_in = (2 + I) * D;
   const int n_mkt = (1 + I) * D;  // market entries of a state row: closes, indicators
 
   // ---------------------------------------------------------------- set-up
@@ -230,12 +238,11 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
                                                         static_cast<size_t>((4 * wave + i) * KK + kk) * 1024 + lane0 * 16);
         if (a < 2) asm volatile("" : "+a"(w2[a][kk][i]));
       }
-  // Market rows close[t] | close[t+1] | ind[t+1] of step t's trade (entry tid of the row).
-  auto load_in = [&](int t) -> float {
-    const int i = tid;
+  // Entry i of step t's input buffer: close[t] | close[t+1] (i < 2D), ind[t+1] (from kRInd).
+  auto load_in = [&](int t, int i) -> float {
     if (i < D) return C.close[static_cast<size_t>(t) * D + i];
     if (i < 2 * D) return C.close[static_cast<size_t>(t + 1) * D + (i - D)];
-    if (i < n_in) return C.ind[static_cast<size_t>(t + 1) * I * D + (i - 2 * D)];
+    if (i >= kRInd && i - kRInd < I * D) return C.ind[static_cast<size_t>(t + 1) * I * D + (i - kRInd)];
     return 0.0f;
   };
   {
@@ -264,7 +271,11 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
     }
     if (tid < K) s_mix[tid] = E.mix[tid];
     for (int i = tid; i < MR * kRX0; i += kRT) s_x0[i] = static_cast<__bf16>(0.0f);
-    s_in[tid] = load_in(F.t0);
+    // Input buffers of the first two steps (later ones are fetched two steps ahead).
+    for (int i = tid; i < kRInBuf; i += kRT) {
+      s_in[i] = load_in(F.t0, i);
+      if (F.n_steps > 1) s_in[kRInBuf + i] = load_in(F.t0 + 1, i);
+    }
 #pragma unroll
     for (int r = 0; r < K; ++r) s_mt[tid + kRT * r] = F.mt[tid + kRT * r];
   }
@@ -300,28 +311,35 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
   __syncthreads();
 
   // The market entries (closes, indicators) of step jj's state rows, from its market rows in LDS:
-  // they do not depend on the trades, so they are stored at the start of the next step (and after
-  // the loop for the last step).  Wavefront w stores environments 2w, 2w+1, 32 lanes each.
-  auto store_market = [&](int jj, const float* in_jj, int lane_) {
-    const int e = 2 * wave + (lane_ >> 5), t32 = lane_ & 31;
+  // they do not depend on the trades, so they are stored during the next step (and after the loop
+  // for the last step).  Environments 2p and 2p + 1 for p in [p0, p1), 32 lanes each.
+  auto store_market = [&](int jj, const float* in_jj, int lane_, int p0, int p1) {
+    const int t32 = lane_ & 31;
     const __amdgpu_buffer_rsrc_t r = rows_rsrc(F.obs_traj, (static_cast<size_t>(jj) * N + n0) * S, 4, M * S);
-    const int base = e < M ? 4 * (e * S + 1 + t32) : kNoStore;  // entry 1 + u of row e, u = t32 + 32 k
     float v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = in_jj[min(D + t32 + 32 * k, kRIn - 1)];  // (1 + I) D <= 255
-#pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int u = t32 + 32 * k;
-      // Closes (u < D) at entries 1 .. D, scaled; indicators (D <= u < (1 + I) D) at 1 + 2D ...
-      const int off = base + 4 * (32 * k + (D & -static_cast<int>(u >= D)));
-      store_f32(r, u < n_mkt ? off : kNoStore, u < D ? v[k] * C.price_scale : v[k]);
+      const int u = t32 + 32 * k;  // market entry u of a state row: close[t+1] (u < D), then ind[t+1]
+      v[k] = in_jj[u < D ? D + u : min(kRInd + u - D, kRInBuf - 1)];
+    }
+    for (int p = p0; p < p1; ++p) {
+      const int e = 2 * p + (lane_ >> 5);
+      const int base = e < M ? 4 * (e * S + 1 + t32) : kNoStore;  // entry 1 + u of row e, u = t32 + 32 k
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int u = t32 + 32 * k;
+        // Closes (u < D) at entries 1 .. D, scaled; indicators (D <= u < (1 + I) D) at 1 + 2D ...
+        const int off = base + 4 * (32 * k + (D & -static_cast<int>(u >= D)));
+        store_f32(r, u < n_mkt ? off : kNoStore, u < D ? v[k] * C.price_scale : v[k]);
+      }
     }
   };
   // Every set-up load has landed: a load still counted as pending on entry would make the
   // compiler wait for all memory operations, stores included, at the top of every step.
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   for (int j = 0; j < F.n_steps; ++j) {
-    const int b = j & 1;
+    const int b = j & 1;       // this step's table row buffer
+    const int bi = j % 3;      // this step's market-row buffer
     const bool nxt = j + 1 < F.n_steps;
     // Addresses derived from the lane and the LDS base are recomputed every step rather than
     // held across the loop: the weights leave few registers for loop-invariant values.
@@ -354,31 +372,42 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
         eps[s] = load_f32(r, env_ok && d < D ? 4 * (m * D + d) : kNoStore);
       }
     }
-    float p_in, p_mt[K];
-    {
-      const int t = F.t0 + j + 1;  // the next step's trading day
-      const __amdgpu_buffer_rsrc_t rc = rows_rsrc(nxt ? C.close : nullptr, static_cast<size_t>(t) * D, 4, 2 * D);
-      const __amdgpu_buffer_rsrc_t ri = rows_rsrc(nxt ? C.ind : nullptr, static_cast<size_t>(t + 1) * I * D, 4, I * D);
-      const int i = threadIdx.x;
-      p_in = load_f32(rc, i < 2 * D ? 4 * i : kNoStore) + load_f32(ri, i >= 2 * D && i < n_in ? 4 * (i - 2 * D) : kNoStore);
-      const __amdgpu_buffer_rsrc_t rm = rows_rsrc(nxt ? F.mt : nullptr, static_cast<size_t>(j + 1) * K * H, 4, K * H);
+    // The next step's table row, straight into LDS, 64 floats per load, a third by each of
+    // wavefronts 0-2 (wavefront 3 fetches the market rows, two steps ahead, after its trades).
+    if (nxt && wave < K) {
+      constexpr int kPer = K * H / 64 / 3;  // 64-float runs of the table row per wavefront
+      const __amdgpu_buffer_rsrc_t rm = rows_rsrc(F.mt, static_cast<size_t>(j + 1) * K * H, 4, K * H);
 #pragma unroll
-      for (int r = 0; r < K; ++r) p_mt[r] = load_f32(rm, 4 * (i + kRT * r));
+      for (int q = 0; q < kPer; ++q) {
+        const int o = 64 * (kPer * wave + q);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rm, s_mt + (b ^ 1) * K * H + o, 4, 4 * (lane + o), 0, 0, 0);
+      }
     }
-    if (j >= 1) store_market(j - 1, s_in + (b ^ 1) * kRIn, lane);
     // ------------------------------------------------------------ L1
-    layer1(s_w1e, s_mt, s_x0, s_x1, wave, lane);
+    layer1(s_w1e, s_mt + b * K * H, s_x0, s_x1, wave, lane);
     __syncthreads();  // 1: layer-1 outputs complete
     // ------------------------------------------------------------ L2
     layer2(w2, s_b2, s_x1, s_x2, wave, lane);
     __syncthreads();  // 2: layer-2 outputs complete
     // ------------------------------------------------------------ L3: actor a on wavefront a
-    if (wave < K) layer3(s_w3, s_b3, s_mix, s_x2, s_mu, wave, lane);
+    if (wave < K) {
+      layer3(s_w3, s_b3, s_mix, s_x2, s_mu, wave, lane);
+    } else {
+      // The next step's market rows (requested at the end of the previous step) have landed in
+      // LDS, visible to all after the barriers below; then the previous step's market entries of
+      // all eight state rows.
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      if (j >= 1) store_market(j - 1, s_in + ((j + 2) % 3) * kRInBuf, lane, 0, 4);
+    }
     __syncthreads();  // 3: the actors' weighted means complete
+    // Wavefronts 0-2: their share of the next table row has landed in LDS (requested at the top of
+    // the step, so this wait costs nothing; it precedes the trade's stores, which it would
+    // otherwise also wait for at the end of the step).
+    if (wave < K) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     {
       // ---------------------------------------------------------- the trading step
 #pragma clang fp contract(off)
-      const float* in = s_in + b * kRIn;
+      const float* in = s_in + bi * kRInBuf;
       const size_t row = static_cast<size_t>(j) * N + n0 + m;
       const bool store_row = env_ok && lane < 32;  // rows 2 and 3 repeat rows 0 and 1
       const size_t row0 = static_cast<size_t>(j) * N + n0;  // the tile's first row of step j
@@ -448,15 +477,23 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
         store_f32(rows_rsrc(F.obs_traj, row0 * S, 4, M * S), 4 * m * S, ce);
       }
     }
-    // The next step's inputs into LDS (zeros after the last step: its loads had empty ranges), on
-    // every path, so that no load is still pending when the next step begins.
-    s_in[(b ^ 1) * kRIn + tid] = p_in;
-#pragma unroll
-    for (int r = 0; r < K; ++r) s_mt[tid + kRT * r] = p_mt[r];
+    if (wave == 3 && j + 2 < F.n_steps) {
+      // The market rows close[t] | close[t+1] | ind[t+1] of step j + 2 into its input buffer (last
+      // read by this step's market-entry stores), 64 floats per load, lanes past a range writing
+      // zeros; waited for in step j + 1's layer 3.
+      const int t = F.t0 + j + 2;
+      float* in_n = s_in + ((j + 2) % 3) * kRInBuf;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rows_rsrc(C.close, static_cast<size_t>(t) * D, 4, 2 * D), in_n, 4,
+                                               4 * lane, 0, 0, 0);
+      const __amdgpu_buffer_rsrc_t ri = rows_rsrc(C.ind, static_cast<size_t>(t + 1) * I * D, 4, I * D);
+      for (int q = 0; 64 * q < I * D; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ri, in_n + kRInd + 64 * q, 4, 4 * (lane + 64 * q), 0, 0, 0);
+    }
     __syncthreads();  // 4: the next state rows and inputs are in LDS
   }
   if (F.n_steps >= 1)
-    store_market(F.n_steps - 1, reinterpret_cast<const float*>(smem + RLds::in) + ((F.n_steps - 1) & 1) * kRIn, lane0);
+    store_market(F.n_steps - 1, reinterpret_cast<const float*>(smem + RLds::in) + ((F.n_steps - 1) % 3) * kRInBuf,
+                 lane0, wave, wave + 1);
   // The trading state back to HBM.
   if (tenv && lane0 < 32) {
     if (tj == 0) {
