@@ -166,27 +166,42 @@ __device__ __forceinline__ void layer2(const bf16x8 (&w2)[kRK][kRKK][4], const f
                                        const __bf16* __restrict__ x1, __bf16* __restrict__ x2, int wave, int lane) {
   constexpr int K = kRK, H = kRH, KK = kRKK, MR = kResRows;
   const int bev = lane & 7, bgrp = lane >> 4, pair_t = (lane >> 3) & 1;
-#pragma unroll
-  for (int a = 0; a < K; ++a) {
+  // Software-pipelined over (actor, tile pair): the MFMAs of one pair are issued next to the
+  // epilogue of the previous pair (its activations), so the vector work runs while the matrix
+  // cores are busy.  Each accumulator still sums its k-steps in the same order.
+  bf16x8 X[KK];
+  floatx4 acc[4];
+  auto load_x = [&](int a) {
     const __bf16* src = x1 + a * MR * kRXS + bev * kRXS + 8 * bgrp;
-    bf16x8 X[KK];
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) X[kk] = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
-    floatx4 acc[4];
+  };
+  auto mfma_pair = [&](int a, int p) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 2 * p; i < 2 * p + 2; ++i)
       acc[i] = mfma_bf16(w2[a][0][i], X[0], *reinterpret_cast<const floatx4*>(b2 + a * H + 16 * (4 * wave + i) + 4 * bgrp));
 #pragma unroll
     for (int kk = 1; kk < KK; ++kk)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] = mfma_bf16(w2[a][kk][i], X[kk], acc[i]);
+      for (int i = 2 * p; i < 2 * p + 2; ++i) acc[i] = mfma_bf16(w2[a][kk][i], X[kk], acc[i]);
+  };
+  auto epilogue = [&](int a, int p) {
+    const floatx4 v = merge_tiles(acc[2 * p], acc[2 * p + 1]);
+    const int u0 = 16 * (4 * wave + 2 * p + pair_t) + 4 * bgrp;
+    *reinterpret_cast<uint2*>(x2 + a * MR * kRXS + bev * kRXS + u0) =
+        pack_bf16x4(tanh_sig(v[0]), tanh_sig(v[1]), tanh_sig(v[2]), tanh_sig(v[3]));
+  };
+  load_x(0);
+  mfma_pair(0, 0);
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const floatx4 v = merge_tiles(acc[2 * p], acc[2 * p + 1]);
-      const int u0 = 16 * (4 * wave + 2 * p + pair_t) + 4 * bgrp;
-      *reinterpret_cast<uint2*>(x2 + a * MR * kRXS + bev * kRXS + u0) =
-          pack_bf16x4(tanh_sig(v[0]), tanh_sig(v[1]), tanh_sig(v[2]), tanh_sig(v[3]));
+  for (int a = 0; a < K; ++a) {
+    mfma_pair(a, 1);
+    epilogue(a, 0);
+    if (a + 1 < K) {
+      load_x(a + 1);
+      mfma_pair(a + 1, 0);
     }
+    epilogue(a, 1);
   }
 }
 
