@@ -143,16 +143,25 @@ __device__ __forceinline__ void layer1(const bf16x8* __restrict__ w1e, const flo
   constexpr int K = kRK, H = kRH, MR = kResRows;
   const int bev = lane & 7, bgrp = lane >> 4, pair_t = (lane >> 3) & 1;
   const bf16x8 X = *reinterpret_cast<const bf16x8*>(x0 + bev * kRX0 + 8 * bgrp);
+  // The accumulators start from the day's table entries, read one (actor, tile pair) ahead.
+  auto table = [&](int a, int p, floatx4 (&t)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      t[h] = *reinterpret_cast<const floatx4*>(mt + a * H + 16 * (4 * wave + 2 * p + h) + 4 * bgrp);
+  };
+  floatx4 tnext[2];
+  table(0, 0, tnext);
 #pragma unroll
   for (int a = 0; a < K; ++a) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
+      const floatx4 tcur[2] = {tnext[0], tnext[1]};
+      if (p == 0 || a + 1 < K) table(p == 1 ? a + 1 : a, p ^ 1, tnext);  // the next (actor, pair)
       floatx4 acc[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int c = 4 * wave + 2 * p + h;
-        acc[h] = mfma_bf16(w1e[(a * 16 + c) * 64 + lane], X,
-                           *reinterpret_cast<const floatx4*>(mt + a * H + 16 * c + 4 * bgrp));
+        acc[h] = mfma_bf16(w1e[(a * 16 + c) * 64 + lane], X, tcur[h]);
       }
       const floatx4 v = merge_tiles(acc[0], acc[1]);
       const int u0 = 16 * (4 * wave + 2 * p + pair_t) + 4 * bgrp;
