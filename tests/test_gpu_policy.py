@@ -119,6 +119,10 @@ CLOSED = [
     ("resident tiles of 5", 23, 256, "bf16", "fused", 20, (0, 5), 30),
     ("resident tiles of 3 D=31", 10, 256, "bf16", "fused", 20, (0, 3), 31),
     ("resident D=7", 19, 256, "bf16", "fused", 20, (0, 8), 7),
+    # Launches of one and two days (the inputs of the first two days come with the set-up, later
+    # ones are fetched two days ahead) after a full 64-day launch.
+    ("resident 1-day launch", 13, 256, "bf16", "fused", 65, (0, 8), 30),
+    ("resident 2-day launch", 11, 256, "bf16", "fused", 66, (0, 8), 30),
     ("streamed tiles of 16", 45, 256, "bf16", "fused", 70, (1, 16), 30),
 ]
 
