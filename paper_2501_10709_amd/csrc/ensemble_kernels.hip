@@ -113,24 +113,38 @@ __global__ __launch_bounds__(64 * NW) void mlp_kernel(EnsDev E, const float* __r
   const float* b3 = reinterpret_cast<const float*>(P + E.off_b3);
   const int row_q = 4 * (lane >> 4), col_l = lane & 15;
 
-  auto hidden_epi = [&](act_t* out, int ost, const float* bias) {
-    return [=](int rt, int, int c, floatx4 acc) {
+  // Each layer's biases for the wavefront's output tiles are requested before its k loop, so that
+  // the epilogue does not wait a memory round trip for them.
+  const int ht = E.H / 16;
+  float bv[TMAX];
+  auto bias = [&](const float* b, int ntiles, int nout) {
+#pragma unroll
+    for (int i = 0; i < TMAX; ++i) {
+      const int col = 16 * (wave + NW * i) + col_l;
+      bv[i] = wave + NW * i < ntiles && col < nout ? b[col] : 0.0f;
+    }
+  };
+  auto hidden_epi = [&](act_t* out, int ost) {
+    return [=, &bv](int rt, int i, int c, floatx4 acc) {
       const int col = 16 * c + col_l;
-      const float b = bias[col];
+      const float b = bv[i];
 #pragma unroll
       for (int r = 0; r < 4; ++r) out[(16 * rt + row_q + r) * ost + col] = static_cast<act_t>(fast_tanh(acc[r] + b));
     };
   };
-  const int ht = E.H / 16;
-  mlp_layer<DT, TMAX, RT, NW>(x0, st0, E.S_pad, P + E.off_w1, ht, wave, lane, hidden_epi(x1, sth, b1));
+  bias(b1, ht, E.H);
+  mlp_layer<DT, TMAX, RT, NW>(x0, st0, E.S_pad, P + E.off_w1, ht, wave, lane, hidden_epi(x1, sth));
+  bias(b2, ht, E.H);
   __syncthreads();
-  mlp_layer<DT, TMAX, RT, NW>(x1, sth, E.H, P + E.off_w2, ht, wave, lane, hidden_epi(x2, sth, b2));
+  mlp_layer<DT, TMAX, RT, NW>(x1, sth, E.H, P + E.off_w2, ht, wave, lane, hidden_epi(x2, sth));
   __syncthreads();
   float* mu_k = mu + static_cast<size_t>(k) * n * E.A;
+  // Layer 3's bias of this wavefront's output tile (slot 0: tile c = wave in both forms below).
+  const float b3v = wave < E.A_pad / 16 && 16 * wave + col_l < E.A ? b3[16 * wave + col_l] : 0.0f;
   auto out_epi = [&](int rt, floatx4 acc, int c) {
     const int col = 16 * c + col_l;
     if (col >= E.A) return;
-    const float b = b3[col];
+    const float b = c == wave ? b3v : b3[col];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = row0 + 16 * rt + row_q + r;
