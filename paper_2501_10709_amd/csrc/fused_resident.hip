@@ -40,6 +40,7 @@
 #include "mlp_device.h"
 #include "row_chain.h"
 
+
 namespace fm {
 
 namespace {
@@ -175,9 +176,9 @@ __device__ __forceinline__ void layer2(const bf16x8 (&w2)[kRK][kRKK][4], const f
                                        const __bf16* __restrict__ x1, __bf16* __restrict__ x2, int wave, int lane) {
   constexpr int K = kRK, H = kRH, KK = kRKK, MR = kResRows;
   const int bev = lane & 7, bgrp = lane >> 4, pair_t = (lane >> 3) & 1;
-  // Software-pipelined over (actor, tile pair): the MFMAs of one pair are issued next to the
-  // epilogue of the previous pair (its activations), so the vector work runs while the matrix
-  // cores are busy.  Each accumulator still sums its k-steps in the same order.
+  // Software-pipelined over (actor, tile pair): the MFMAs of one pair are issued between the
+  // slices of the previous pair's epilogue (its activations), so the vector work runs while the
+  // matrix cores are busy.  Each accumulator still sums its k-steps in the same order.
   bf16x8 X[KK];
   floatx4 acc[4];
   auto load_x = [&](int a) {
@@ -185,33 +186,49 @@ __device__ __forceinline__ void layer2(const bf16x8 (&w2)[kRK][kRKK][4], const f
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) X[kk] = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
   };
-  auto mfma_pair = [&](int a, int p) {
-#pragma unroll
-    for (int i = 2 * p; i < 2 * p + 2; ++i)
-      acc[i] = mfma_bf16(w2[a][0][i], X[0], *reinterpret_cast<const floatx4*>(b2 + a * H + 16 * (4 * wave + i) + 4 * bgrp));
-#pragma unroll
-    for (int kk = 1; kk < KK; ++kk)
-#pragma unroll
-      for (int i = 2 * p; i < 2 * p + 2; ++i) acc[i] = mfma_bf16(w2[a][kk][i], X[kk], acc[i]);
-  };
   auto epilogue = [&](int a, int p) {
     const floatx4 v = merge_tiles(acc[2 * p], acc[2 * p + 1]);
     const int u0 = 16 * (4 * wave + 2 * p + pair_t) + 4 * bgrp;
     *reinterpret_cast<uint2*>(x2 + a * MR * kRXS + bev * kRXS + u0) =
         pack_bf16x4(tanh_sig(v[0]), tanh_sig(v[1]), tanh_sig(v[2]), tanh_sig(v[3]));
   };
+  // Stage (a, p): the MFMAs of pair (a, p), k-step by k-step, each k-step followed by a slice of
+  // the previous pair (pa, pp)'s epilogue (merge, one activation, the pack, the store) and a
+  // scheduling fence: left to itself the scheduler issues the MFMAs of several pairs back to back
+  // and the epilogues after them, with nothing overlapped.
+  auto stage = [&](int a, int p, int pa, int pp, bool epi) {
+    floatx4 v;
+    float t[4];
+    uint2 packed;
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+#pragma unroll
+      for (int i = 2 * p; i < 2 * p + 2; ++i)
+        acc[i] = kk == 0 ? mfma_bf16(w2[a][0][i], X[0], *reinterpret_cast<const floatx4*>(b2 + a * H + 16 * (4 * wave + i) + 4 * bgrp))
+                         : mfma_bf16(w2[a][kk][i], X[kk], acc[i]);
+      if (epi) {
+        if (kk == 0) v = merge_tiles(acc[2 * pp], acc[2 * pp + 1]);
+        if (kk >= 1 && kk <= 4) t[kk - 1] = tanh_sig(v[kk - 1]);
+        if (kk == 5) packed = pack_bf16x4(t[0], t[1], t[2], t[3]);
+        if (kk == 6) {
+          const int u0 = 16 * (4 * wave + 2 * pp + pair_t) + 4 * bgrp;
+          *reinterpret_cast<uint2*>(x2 + pa * MR * kRXS + bev * kRXS + u0) = packed;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
   load_x(0);
-  mfma_pair(0, 0);
+  stage(0, 0, 0, 0, false);
 #pragma unroll
   for (int a = 0; a < K; ++a) {
-    mfma_pair(a, 1);
-    epilogue(a, 0);
+    stage(a, 1, a, 0, true);
     if (a + 1 < K) {
       load_x(a + 1);
-      mfma_pair(a + 1, 0);
+      stage(a + 1, 0, a, 1, true);
     }
-    epilogue(a, 1);
   }
+  epilogue(K - 1, 1);
 }
 
 // Actor a = wave's two output tiles, w_a tanh(z + b3_a) into mu[a][env][dim].
