@@ -25,13 +25,15 @@
 //         sells, then buys, in ascending stock order -- which every lane of the row computes on
 //         terms broadcast from the owning lane (DPP row broadcasts, no LDS round trip), keeping
 //         the fills of its own stocks; holdings, position values, the new value and reward, the
-//         next state row, and the trajectory stores straight from registers.
+//         next state row, and the trajectory stores of actions, quantities and rewards straight
+//         from registers.
 // The step's noise (drawn per chunk by noise_chunk_kernel) is requested at the top of a step and
 // used after the MLP.  The inputs travel by buffer loads that write LDS directly: the next step's
 // table row, a third by each of wavefronts 0-2 at the top of a step (waited for after the third
 // barrier; double-buffered), and the market rows two steps ahead by wavefront 3 after its trades
-// (waited for in the next step's L3; triple-buffered).  Wavefront 3, which has no actor in L3,
-// also stores the market entries of all eight state rows of the previous step there.
+// (waited for in the next step's L3; triple-buffered).  The state rows of a step are assembled
+// as a float32 image in LDS -- the market entries by wavefront 3, which has no actor in L3, the
+// cash and holdings by the trading lanes -- and stored whole by wavefront 3 in the next step's L3.
 #include <cstring>
 #include <utility>
 
@@ -54,6 +56,9 @@ constexpr int kRIn = 256;    // market entries per day, (2 + I) * D <= 256
 // (the fetch writes whole runs of 64 floats, so the two parts do not overlap).
 constexpr int kRInd = 64;
 constexpr int kRInBuf = kRInd + 256;
+// A float32 image of a step's state rows ([8][S], S = 1 + (2 + I) D <= 1 + kRIn), padded to whole
+// 16-byte units.
+constexpr int kRImg = kResRows * (kRIn + 4);
 
 constexpr size_t r16(size_t b) { return (b + 15) / 16 * 16; }
 
@@ -72,7 +77,8 @@ struct RLds {
   static constexpr size_t mt = mix + 16;                                           // [2][K][256] f32
   static constexpr size_t in = mt + sizeof(float) * 2 * kRK * kRH;                 // [3][320] f32
   static constexpr size_t state = in + sizeof(float) * 3 * kRInBuf;                // [8] {cash, value, cumrew, 0} f64
-  static constexpr size_t total = state + sizeof(double) * 4 * kResRows;
+  static constexpr size_t img = state + sizeof(double) * 4 * kResRows;              // [2][8][S] f32
+  static constexpr size_t total = img + sizeof(float) * 2 * kRImg;
   static_assert(sizeof(float) * kRK * kResRows * 32 <= xb, "the actor means fit the layer-1 region");
 };
 static_assert(RLds::total <= 160 * 1024, "LDS budget");
@@ -351,27 +357,46 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
   }
   __syncthreads();
 
-  // The market entries (closes, indicators) of step jj's state rows, from its market rows in LDS:
-  // they do not depend on the trades, so they are stored during the next step (and after the loop
-  // for the last step).  Environments 2p and 2p + 1 for p in [p0, p1), 32 lanes each.
-  auto store_market = [&](int jj, const float* in_jj, int lane_, int p0, int p1) {
-    const int t32 = lane_ & 31;
-    const __amdgpu_buffer_rsrc_t r = rows_rsrc(F.obs_traj, (static_cast<size_t>(jj) * N + n0) * S, 4, M * S);
-    float v[8];
+  // The state rows of a step are assembled in LDS as float32 images (double-buffered): the market
+  // entries (closes, indicators) of step jj's rows from its market rows, 64 entries by each
+  // wavefront at the end of the step's layer 3 (wavefronts 0-2 would otherwise wait there for
+  // wavefront 3's stores), and the cash and holdings entries by the trading lanes.  The tile's
+  // rows of a step are contiguous in the trajectory, so the image is stored whole, with
+  // 16-byte stores where the rows start on a 16-byte boundary, during the next step's layer 3
+  // (and after the loop for the last step).
+  const bool obs_on = F.obs_traj != nullptr;
+  // No per-row branches: rows past M are filled too and never stored.
+  static_assert(kRIn == 64 * 4, "one 64-entry chunk of the market entries per wavefront");
+  auto fill_image = [&](const float* in_jj, float* img_jj, int lane_, int k) {
+    const int u = lane_ + 64 * k;  // market entry u of a state row: close[t+1] (u < D), then ind[t+1]
+    if (u < n_mkt) {
+      const bool cl = u < D;
+      const float x = in_jj[cl ? D + u : kRInd + u - D];
+      const float v = x * (cl ? C.price_scale : 1.0f);  // closes scaled, indicators as they are
+      const int pos = 1 + u + (cl ? 0 : D);             // closes at entries 1 .. D, indicators from 1 + 2D
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int u = t32 + 32 * k;  // market entry u of a state row: close[t+1] (u < D), then ind[t+1]
-      v[k] = in_jj[u < D ? D + u : min(kRInd + u - D, kRInBuf - 1)];
+      for (int e = 0; e < MR; ++e) img_jj[e * S + pos] = v;
     }
-    for (int p = p0; p < p1; ++p) {
-      const int e = 2 * p + (lane_ >> 5);
-      const int base = e < M ? 4 * (e * S + 1 + t32) : kNoStore;  // entry 1 + u of row e, u = t32 + 32 k
+  };
+  auto store_image = [&](int jj, const float* img_jj, int lane_) {
+    const int total = M * S;
+    const size_t base = (static_cast<size_t>(jj) * N + n0) * S;
+    const __amdgpu_buffer_rsrc_t r = rows_rsrc(F.obs_traj, base, 4, total);
+    if ((reinterpret_cast<uintptr_t>(F.obs_traj + base) & 15) == 0 && (total & 3) == 0) {
+      typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
+      constexpr int kQ = (kRImg / 4 + 63) / 64;
+      u32x4 v[kQ];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int u = t32 + 32 * k;
-        // Closes (u < D) at entries 1 .. D, scaled; indicators (D <= u < (1 + I) D) at 1 + 2D ...
-        const int off = base + 4 * (32 * k + (D & -static_cast<int>(u >= D)));
-        store_f32(r, u < n_mkt ? off : kNoStore, u < D ? v[k] * C.price_scale : v[k]);
+      for (int q = 0; q < kQ; ++q) v[q] = reinterpret_cast<const u32x4*>(img_jj)[min(lane_ + 64 * q, kRImg / 4 - 1)];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const int i4 = lane_ + 64 * q;
+        __builtin_amdgcn_raw_buffer_store_b128(v[q], r, 4 * i4 < total ? 16 * i4 : kNoStore, 0, 0);
+      }
+    } else {
+      for (int q = 0; 64 * q < total; ++q) {
+        const int i = lane_ + 64 * q;
+        store_f32(r, i < total ? 4 * i : kNoStore, img_jj[min(i, kRImg - 1)]);
       }
     }
   };
@@ -399,6 +424,7 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
     float* s_mt = reinterpret_cast<float*>(sm + RLds::mt);
     float* s_in = reinterpret_cast<float*>(sm + RLds::in);
     double* s_state = reinterpret_cast<double*>(sm + RLds::state);
+    float* s_img = reinterpret_cast<float*>(sm + RLds::img);
     // This step's noise and the next step's inputs, requested now, used after the MLP.
     const int m = 2 * wave + ((lane >> 4) & 1), jl = lane & 15;
     const bool env_ok = m < M;
@@ -435,11 +461,13 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
       layer3(s_w3, s_b3, s_mix, s_x2, s_mu, wave, lane);
     } else {
       // The next step's market rows (requested at the end of the previous step) have landed in
-      // LDS, visible to all after the barriers below; then the previous step's market entries of
-      // all eight state rows.
+      // LDS, visible to all after the barriers below; then the previous step's state rows go out
+      // from their image.
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-      if (j >= 1) store_market(j - 1, s_in + ((j + 2) % 3) * kRInBuf, lane, 0, 4);
+      if (obs_on && j >= 1) store_image(j - 1, s_img + ((j - 1) & 1) * kRImg, lane);
     }
+    // This step's image receives its market entries, chunk `wave` of them.
+    if (obs_on) fill_image(s_in + bi * kRInBuf, s_img + (j & 1) * kRImg, lane, wave);
     __syncthreads();  // 3: the actors' weighted means complete
     // Wavefronts 0-2: their share of the next table row has landed in LDS (requested at the top of
     // the step, so this wait costs nothing; it precedes the trade's stores, which it would
@@ -502,7 +530,7 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
         const bool st_on = on && lane < 32;
         store_f32(rows_rsrc(F.qty_traj, row0 * D, 4, M * D), st_on ? 4 * (em + d) : kNoStore,
                   __int_as_float(kown[s] - sold[s]));
-        store_f32(rows_rsrc(F.obs_traj, row0 * S, 4, M * S), st_on ? 4 * (m * S + 1 + D + d) : kNoStore, he);
+        if (st_on) s_img[(j & 1) * kRImg + m * S + 1 + D + d] = he;
       }
       double v_new = row_sum(cash, val[0]);
       v_new = row_sum(v_new, val[1]);
@@ -515,13 +543,13 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
         s_x0[m * kRX0] = static_cast<__bf16>(ce);
         typedef __attribute__((ext_vector_type(2))) unsigned u32x2;
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, r), rows_rsrc(F.rew_traj, row0, 8, M), 8 * m, 0, 0);
-        store_f32(rows_rsrc(F.obs_traj, row0 * S, 4, M * S), 4 * m * S, ce);
+        s_img[(j & 1) * kRImg + m * S] = ce;
       }
     }
     if (wave == 3 && j + 2 < F.n_steps) {
       // The market rows close[t] | close[t+1] | ind[t+1] of step j + 2 into its input buffer (last
-      // read by this step's market-entry stores), 64 floats per load, lanes past a range writing
-      // zeros; waited for in step j + 1's layer 3.
+      // read in step j - 1), 64 floats per load, lanes past a range writing zeros; waited for in
+      // step j + 1's layer 3.
       const int t = F.t0 + j + 2;
       float* in_n = s_in + ((j + 2) % 3) * kRInBuf;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rows_rsrc(C.close, static_cast<size_t>(t) * D, 4, 2 * D), in_n, 4,
@@ -532,9 +560,8 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
     }
     __syncthreads();  // 4: the next state rows and inputs are in LDS
   }
-  if (F.n_steps >= 1)
-    store_market(F.n_steps - 1, reinterpret_cast<const float*>(smem + RLds::in) + ((F.n_steps - 1) % 3) * kRInBuf,
-                 lane0, wave, wave + 1);
+  if (obs_on && F.n_steps >= 1 && wave == 3)
+    store_image(F.n_steps - 1, reinterpret_cast<const float*>(smem + RLds::img) + ((F.n_steps - 1) & 1) * kRImg, lane0);
   // The trading state back to HBM.
   if (tenv && lane0 < 32) {
     if (tj == 0) {
