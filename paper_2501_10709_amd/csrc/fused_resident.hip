@@ -43,6 +43,7 @@
 #include "row_chain.h"
 
 
+
 namespace fm {
 
 namespace {
@@ -245,14 +246,26 @@ __device__ __forceinline__ void layer3(const bf16x8* __restrict__ w3, const floa
   const int bev = lane & 7, bgrp = lane >> 4, pair_t = (lane >> 3) & 1;
   const int a = wave;
   const __bf16* src = x2 + a * MR * kRXS + bev * kRXS + 8 * bgrp;
+  // The operands of k-step kk + kRL3 are requested before the products of k-step kk, so the LDS
+  // latency is paid once rather than per k-step.
+  constexpr int kRL3 = 4;
   floatx4 acc[2];
+  bf16x8 X[KK], W[2][KK];
+  auto load = [&](int kk) {
+    X[kk] = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) W[h][kk] = w3[((a * 2 + h) * KK + kk) * 64 + lane];
+  };
 #pragma unroll
   for (int h = 0; h < 2; ++h) acc[h] = *reinterpret_cast<const floatx4*>(b3 + a * 32 + 16 * h + 4 * bgrp);
 #pragma unroll
-  for (int kk = 0; kk < KK; ++kk) {
-    const bf16x8 X = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
+  for (int kk = 0; kk < kRL3; ++kk) load(kk);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) acc[h] = mfma_bf16(w3[((a * 2 + h) * KK + kk) * 64 + lane], X, acc[h]);
+  for (int kk = 0; kk < KK; ++kk) {
+    if (kk + kRL3 < KK) load(kk + kRL3);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) acc[h] = mfma_bf16(W[h][kk], X[kk], acc[h]);
+    __builtin_amdgcn_sched_barrier(0);
   }
   const floatx4 v = merge_tiles(acc[0], acc[1]);
   const float wk = mix[a];
