@@ -30,10 +30,11 @@
 // The step's noise (drawn per chunk by noise_chunk_kernel) is requested at the top of a step and
 // used after the MLP.  The inputs travel by buffer loads that write LDS directly: the next step's
 // table row, a third by each of wavefronts 0-2 at the top of a step (waited for after the third
-// barrier; double-buffered), and the market rows two steps ahead by wavefront 3 after its trades
-// (waited for in the next step's L3; triple-buffered).  The state rows of a step are assembled
-// as a float32 image in LDS -- the market entries by wavefront 3, which has no actor in L3, the
-// cash and holdings by the trading lanes -- and stored whole by wavefront 3 in the next step's L3.
+// barrier; double-buffered), and the market rows two steps ahead by wavefront 3, which has no
+// actor in L3, in that phase (waited for in the next step's L3; triple-buffered).  The state rows
+// of a step are assembled as a float32 image in LDS -- the market entries by every wavefront in
+// L3, the cash and holdings by the trading lanes -- and stored whole by wavefront 3 in the next
+// step's L3.
 #include <cstring>
 #include <utility>
 
@@ -453,7 +454,7 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
       }
     }
     // The next step's table row, straight into LDS, 64 floats per load, a third by each of
-    // wavefronts 0-2 (wavefront 3 fetches the market rows, two steps ahead, after its trades).
+    // wavefronts 0-2 (wavefront 3 fetches the market rows, two steps ahead, in layer 3).
     if (nxt && wave < K) {
       constexpr int kPer = K * H / 64 / 3;  // 64-float runs of the table row per wavefront
       const __amdgpu_buffer_rsrc_t rm = rows_rsrc(F.mt, static_cast<size_t>(j + 1) * K * H, 4, K * H);
@@ -473,11 +474,23 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
     if (wave < K) {
       layer3(s_w3, s_b3, s_mix, s_x2, s_mu, wave, lane);
     } else {
-      // The next step's market rows (requested at the end of the previous step) have landed in
+      // The next step's market rows (requested in the previous step's layer 3) have landed in
       // LDS, visible to all after the barriers below; then the previous step's state rows go out
-      // from their image.
+      // from their image, and the market rows two steps ahead are requested.
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
       if (obs_on && j >= 1) store_image(j - 1, s_img + ((j - 1) & 1) * kRImg, lane);
+      if (j + 2 < F.n_steps) {
+        // The market rows close[t] | close[t+1] | ind[t+1] of step j + 2 into its input buffer
+        // (last read in step j - 1), 64 floats per load, lanes past a range writing zeros;
+        // waited for in step j + 1's layer 3.
+        const int t = F.t0 + j + 2;
+        float* in_n = s_in + ((j + 2) % 3) * kRInBuf;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rows_rsrc(C.close, static_cast<size_t>(t) * D, 4, 2 * D), in_n, 4,
+                                                 4 * lane, 0, 0, 0);
+        const __amdgpu_buffer_rsrc_t ri = rows_rsrc(C.ind, static_cast<size_t>(t + 1) * I * D, 4, I * D);
+        for (int q = 0; 64 * q < I * D; ++q)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(ri, in_n + kRInd + 64 * q, 4, 4 * (lane + 64 * q), 0, 0, 0);
+      }
     }
     // This step's image receives its market entries, chunk `wave` of them.
     if (obs_on) fill_image(s_in + bi * kRInBuf, s_img + (j & 1) * kRImg, lane, wave);
@@ -558,18 +571,6 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, r), rows_rsrc(F.rew_traj, row0, 8, M), 8 * m, 0, 0);
         s_img[(j & 1) * kRImg + m * S] = ce;
       }
-    }
-    if (wave == 3 && j + 2 < F.n_steps) {
-      // The market rows close[t] | close[t+1] | ind[t+1] of step j + 2 into its input buffer (last
-      // read in step j - 1), 64 floats per load, lanes past a range writing zeros; waited for in
-      // step j + 1's layer 3.
-      const int t = F.t0 + j + 2;
-      float* in_n = s_in + ((j + 2) % 3) * kRInBuf;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rows_rsrc(C.close, static_cast<size_t>(t) * D, 4, 2 * D), in_n, 4,
-                                               4 * lane, 0, 0, 0);
-      const __amdgpu_buffer_rsrc_t ri = rows_rsrc(C.ind, static_cast<size_t>(t + 1) * I * D, 4, I * D);
-      for (int q = 0; 64 * q < I * D; ++q)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(ri, in_n + kRInd + 64 * q, 4, 4 * (lane + 64 * q), 0, 0, 0);
     }
     __syncthreads();  // 4: the next state rows and inputs are in LDS
   }
