@@ -152,31 +152,43 @@ __device__ __forceinline__ void layer1(const bf16x8* __restrict__ w1e, const flo
   constexpr int K = kRK, H = kRH, MR = kResRows;
   const int bev = lane & 7, bgrp = lane >> 4, pair_t = (lane >> 3) & 1;
   const bf16x8 X = *reinterpret_cast<const bf16x8*>(x0 + bev * kRX0 + 8 * bgrp);
-  // The accumulators start from the day's table entries, read one (actor, tile pair) ahead.
-  auto table = [&](int a, int p, floatx4 (&t)[2]) {
+  // Six (actor, tile pair) stages: stage i requests the operands of pair i + 2 (the weight
+  // fragments and the day's table entries, which the accumulators start from), issues the MFMAs
+  // of pair i + 1 and then the epilogue of pair i, fenced so that the activations run while the
+  // matrix cores work and no LDS latency sits between a load and its use.
+  constexpr int NP = 2 * K;
+  floatx4 T[NP][2], acc[NP][2];
+  bf16x8 Wf[NP][2];
+  auto ld = [&](int i) {
+    const int a = i >> 1, p = i & 1;
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-      t[h] = *reinterpret_cast<const floatx4*>(mt + a * H + 16 * (4 * wave + 2 * p + h) + 4 * bgrp);
-  };
-  floatx4 tnext[2];
-  table(0, 0, tnext);
-#pragma unroll
-  for (int a = 0; a < K; ++a) {
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const floatx4 tcur[2] = {tnext[0], tnext[1]};
-      if (p == 0 || a + 1 < K) table(p == 1 ? a + 1 : a, p ^ 1, tnext);  // the next (actor, pair)
-      floatx4 acc[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = 4 * wave + 2 * p + h;
-        acc[h] = mfma_bf16(w1e[(a * 16 + c) * 64 + lane], X, tcur[h]);
-      }
-      const floatx4 v = merge_tiles(acc[0], acc[1]);
-      const int u0 = 16 * (4 * wave + 2 * p + pair_t) + 4 * bgrp;
-      *reinterpret_cast<uint2*>(x1 + a * MR * kRXS + bev * kRXS + u0) =
-          pack_bf16x4(tanh_sig(v[0]), tanh_sig(v[1]), tanh_sig(v[2]), tanh_sig(v[3]));
+    for (int h = 0; h < 2; ++h) {
+      const int c = 4 * wave + 2 * p + h;
+      T[i][h] = *reinterpret_cast<const floatx4*>(mt + a * H + 16 * c + 4 * bgrp);
+      Wf[i][h] = w1e[(a * 16 + c) * 64 + lane];
     }
+  };
+  auto mm = [&](int i) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) acc[i][h] = mfma_bf16(Wf[i][h], X, T[i][h]);
+  };
+  auto epi = [&](int i) {
+    const int a = i >> 1, p = i & 1;
+    const floatx4 v = merge_tiles(acc[i][0], acc[i][1]);
+    const int u0 = 16 * (4 * wave + 2 * p + pair_t) + 4 * bgrp;
+    *reinterpret_cast<uint2*>(x1 + a * MR * kRXS + bev * kRXS + u0) =
+        pack_bf16x4(tanh_sig(v[0]), tanh_sig(v[1]), tanh_sig(v[2]), tanh_sig(v[3]));
+  };
+  ld(0);
+  ld(1);
+  mm(0);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    if (i + 2 < NP) ld(i + 2);
+    if (i + 1 < NP) mm(i + 1);
+    epi(i);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
