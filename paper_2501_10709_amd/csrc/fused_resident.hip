@@ -199,12 +199,13 @@ __device__ __forceinline__ void layer2(const bf16x8 (&w2)[kRK][kRKK][4], const f
   // Software-pipelined over (actor, tile pair): the MFMAs of one pair are issued between the
   // slices of the previous pair's epilogue (its activations), so the vector work runs while the
   // matrix cores are busy.  Each accumulator still sums its k-steps in the same order.
-  bf16x8 X[KK];
+  // Actor a's activations: X[a & 1], requested one stage before the first use.
+  bf16x8 X[2][KK];
   floatx4 acc[4];
   auto load_x = [&](int a) {
     const __bf16* src = x1 + a * MR * kRXS + bev * kRXS + 8 * bgrp;
 #pragma unroll
-    for (int kk = 0; kk < KK; ++kk) X[kk] = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
+    for (int kk = 0; kk < KK; ++kk) X[a & 1][kk] = *reinterpret_cast<const bf16x8*>(src + 32 * kk);
   };
   auto epilogue = [&](int a, int p) {
     const floatx4 v = merge_tiles(acc[2 * p], acc[2 * p + 1]);
@@ -216,7 +217,7 @@ __device__ __forceinline__ void layer2(const bf16x8 (&w2)[kRK][kRKK][4], const f
   // the previous pair (pa, pp)'s epilogue (merge, one activation, the pack, the store) and a
   // scheduling fence: left to itself the scheduler issues the MFMAs of several pairs back to back
   // and the epilogues after them, with nothing overlapped.
-  auto stage = [&](int a, int p, int pa, int pp, bool epi) {
+  auto stage = [&](int a, int p, int pa, int pp, bool epi, int pre) {
     floatx4 v;
     float t[4];
     uint2 packed;
@@ -224,8 +225,11 @@ __device__ __forceinline__ void layer2(const bf16x8 (&w2)[kRK][kRKK][4], const f
     for (int kk = 0; kk < KK; ++kk) {
 #pragma unroll
       for (int i = 2 * p; i < 2 * p + 2; ++i)
-        acc[i] = kk == 0 ? mfma_bf16(w2[a][0][i], X[0], *reinterpret_cast<const floatx4*>(b2 + a * H + 16 * (4 * wave + i) + 4 * bgrp))
-                         : mfma_bf16(w2[a][kk][i], X[kk], acc[i]);
+        acc[i] = kk == 0 ? mfma_bf16(w2[a][0][i], X[a & 1][0], *reinterpret_cast<const floatx4*>(b2 + a * H + 16 * (4 * wave + i) + 4 * bgrp))
+                         : mfma_bf16(w2[a][kk][i], X[a & 1][kk], acc[i]);
+      // The next actor's activations, requested after this stage's bias loads so that waiting
+      // for those does not wait for these.
+      if (kk == 0 && pre >= 0) load_x(pre);
       if (epi) {
         if (kk == 0) v = merge_tiles(acc[2 * pp], acc[2 * pp + 1]);
         if (kk >= 1 && kk <= 4) t[kk - 1] = tanh_sig(v[kk - 1]);
@@ -239,14 +243,11 @@ __device__ __forceinline__ void layer2(const bf16x8 (&w2)[kRK][kRKK][4], const f
     }
   };
   load_x(0);
-  stage(0, 0, 0, 0, false);
+  stage(0, 0, 0, 0, false, -1);
 #pragma unroll
   for (int a = 0; a < K; ++a) {
-    stage(a, 1, a, 0, true);
-    if (a + 1 < K) {
-      load_x(a + 1);
-      stage(a + 1, 0, a, 1, true);
-    }
+    stage(a, 1, a, 0, true, a + 1 < K ? a + 1 : -1);
+    if (a + 1 < K) stage(a + 1, 0, a, 1, true, -1);
   }
   epilogue(K - 1, 1);
 }
