@@ -310,22 +310,46 @@ struct Streamed {
 //     environment of day t, so it is computed once per day instead of once per environment;
 //   eps[c][n][d]: the noise of step t for environment n (Philox4x64-10 + Box-Muller).
 // ------------------------------------------------------------------------------------------
-__global__ void market_table_kernel(EnvConst C, EnsDev E, int t0, float* __restrict__ mt) {
-  extern __shared__ float xs[];  // the day's market entries, bfloat16-rounded
-  const int c = blockIdx.x, k = blockIdx.y, t = t0 + c;
-  const int D = C.D, I = C.I, Fm = (1 + I) * D, H = E.H;
-  for (int f = threadIdx.x; f < Fm; f += blockDim.x) {
-    const float v = f < D ? C.close[static_cast<size_t>(t) * D + f] * C.price_scale
-                          : C.ind[static_cast<size_t>(t) * I * D + (f - D)];
-    xs[f] = static_cast<float>(static_cast<__bf16>(v));
+// One workgroup per (kMtDays days, actor), thread j per hidden unit: each weight load serves
+// kMtDays days, and the weights are requested 64 at a time before they are used, so the load
+// latency is paid a few times per unit rather than once per few entries.  Each sum still runs
+// over f in ascending order, one rounding per product and per addition; the entries are padded
+// with zeros to whole batches (a zero product added to a sum that starts at +0 changes nothing).
+constexpr int kMtDays = 2, kMtBatch = 64;
+__host__ __device__ constexpr int mt_row(int Fm) { return (Fm + kMtBatch - 1) / kMtBatch * kMtBatch; }
+// A few hundred workgroups at most: registers for the batch matter more than occupancy.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void market_table_kernel(EnvConst C, EnsDev E, int t0, int n_days, float* __restrict__ mt) {
+  extern __shared__ float xs[];  // [kMtDays][Fp]: the days' market entries, bfloat16-rounded, zero-padded
+  const int c0 = blockIdx.x * kMtDays, k = blockIdx.y;
+  const int D = C.D, I = C.I, Fm = (1 + I) * D, H = E.H, Fp = mt_row(Fm);
+  for (int i = threadIdx.x; i < kMtDays * Fp; i += blockDim.x) {
+    const int dd = i / Fp, f = i - dd * Fp, t = t0 + c0 + dd;
+    float v = 0.0f;
+    if (c0 + dd < n_days && f < Fm)
+      v = f < D ? C.close[static_cast<size_t>(t) * D + f] * C.price_scale
+                : C.ind[static_cast<size_t>(t) * I * D + (f - D)];
+    xs[i] = static_cast<float>(static_cast<__bf16>(v));
   }
   __syncthreads();
   const __bf16* w = reinterpret_cast<const __bf16*>(E.base + E.off_w1m) + static_cast<size_t>(k) * Fm * H;
   const float* b1 = reinterpret_cast<const float*>(E.base + k * E.actor_stride + E.off_b1);
   for (int j = threadIdx.x; j < H; j += blockDim.x) {
-    float acc = 0.0f;
-    for (int f = 0; f < Fm; ++f) acc = acc + xs[f] * static_cast<float>(w[static_cast<size_t>(f) * H + j]);
-    mt[(static_cast<size_t>(c) * E.K + k) * H + j] = acc + b1[j];
+    float acc[kMtDays];
+#pragma unroll
+    for (int dd = 0; dd < kMtDays; ++dd) acc[dd] = 0.0f;
+    for (int f0 = 0; f0 < Fm; f0 += kMtBatch) {
+      float wv[kMtBatch];
+#pragma unroll
+      for (int q = 0; q < kMtBatch; ++q) wv[q] = static_cast<float>(w[static_cast<size_t>(min(f0 + q, Fm - 1)) * H + j]);
+#pragma unroll
+      for (int q = 0; q < kMtBatch; ++q)
+#pragma unroll
+        for (int dd = 0; dd < kMtDays; ++dd) acc[dd] = acc[dd] + xs[dd * Fp + f0 + q] * wv[q];
+    }
+#pragma unroll
+    for (int dd = 0; dd < kMtDays; ++dd)
+      if (c0 + dd < n_days) mt[(static_cast<size_t>(c0 + dd) * E.K + k) * H + j] = acc[dd] + b1[j];
   }
 }
 
@@ -1052,7 +1076,8 @@ hipError_t launch_streamed(const EnvConst& C, const EnvState& st, const EnsDev& 
 hipError_t launch_chunk_inputs(const EnvConst& C, const EnsDev& E, int t, int n, float sigma, uint64_t key,
                                int64_t env_offset, float* eps_chunk, float* mt_chunk, hipStream_t stream) {
   const int Fm = (1 + C.I) * C.D;
-  hipLaunchKernelGGL(market_table_kernel, dim3(n, E.K), dim3(kStreamH), sizeof(float) * Fm, stream, C, E, t, mt_chunk);
+  hipLaunchKernelGGL(market_table_kernel, dim3((n + kMtDays - 1) / kMtDays, E.K), dim3(kStreamH),
+                     sizeof(float) * kMtDays * mt_row(Fm), stream, C, E, t, n, mt_chunk);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess || sigma == 0.0f) return err;
   const size_t total = static_cast<size_t>(n) * C.N * ((C.D + 3) / 4);
@@ -1077,7 +1102,8 @@ size_t batched_lds_bytes(int rows, const EnvConst& C, const EnsDev& E) {
 
 hipError_t launch_market_table(const EnvConst& C, const EnsDev& E, int t, int n, float* mt, hipStream_t stream) {
   const int Fm = (1 + C.I) * C.D;
-  hipLaunchKernelGGL(market_table_kernel, dim3(n, E.K), dim3(kStreamH), sizeof(float) * Fm, stream, C, E, t, mt);
+  hipLaunchKernelGGL(market_table_kernel, dim3((n + kMtDays - 1) / kMtDays, E.K), dim3(kStreamH),
+                     sizeof(float) * kMtDays * mt_row(Fm), stream, C, E, t, n, mt);
   return hipGetLastError();
 }
 
