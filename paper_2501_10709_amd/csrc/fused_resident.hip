@@ -488,10 +488,9 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
       layer3(s_w3, s_b3, s_mix, s_x2, s_mu, wave, lane);
     } else {
       // The next step's market rows (requested in the previous step's layer 3) have landed in
-      // LDS, visible to all after the barriers below; then the previous step's state rows go out
-      // from their image, and the market rows two steps ahead are requested.
+      // LDS, visible to all after the barriers below; then the market rows two steps ahead are
+      // requested, and the previous step's state rows go out from their image.
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-      if (obs_on && j >= 1) store_image(j - 1, s_img + ((j - 1) & 1) * kRImg, lane);
       if (j + 2 < F.n_steps) {
         // The market rows close[t] | close[t+1] | ind[t+1] of step j + 2 into its input buffer
         // (last read in step j - 1), 64 floats per load, lanes past a range writing zeros;
@@ -504,6 +503,7 @@ void fused_resident_kernel(EnvConst C, EnvState st, EnsDev E, FusedArgs F) {
         for (int q = 0; 64 * q < I * D; ++q)
           __builtin_amdgcn_raw_ptr_buffer_load_lds(ri, in_n + kRInd + 64 * q, 4, 4 * (lane + 64 * q), 0, 0, 0);
       }
+      if (obs_on && j >= 1) store_image(j - 1, s_img + ((j - 1) & 1) * kRImg, lane);
     }
     // This step's image receives its market entries, chunk `wave` of them.
     if (obs_on) fill_image(s_in + bi * kRInBuf, s_img + (j & 1) * kRImg, lane, wave);
